@@ -1,0 +1,190 @@
+/*
+ * tetsplat.h -- C ABI of the MI355X (gfx950) tile-based differentiable
+ * tetrahedron rasterizer of "Tetrahedron Splatting for 3D Generation"
+ * (TeT-Splatting, arXiv 2406.01579).
+ *
+ * What the library computes (paper passages):
+ *   - Scene: a tetrahedral grid (V_T, T) with one SDF value per vertex,
+ *     linearly interpolated inside every tet (Sec. 3.1), and one RGB per
+ *     vertex; a tet's colour is the mean of its four vertex colours (materials
+ *     taken at the tet centre, App. B).
+ *   - Pre-filter: tets whose opacity upper bound alpha_max (Eq. 1 at the max
+ *     and min vertex SDF) is below prefilter_tf are dropped (Sec. 3.2).
+ *   - Normal: n = g/|g| with g the constant SDF gradient of the tet
+ *     (Sec. 3.2, App. A.3).
+ *   - Per view: cull, project the four vertices, bin each tet to every screen
+ *     tile its pixel rectangle touches, sort by (tile, mean vertex depth)
+ *     (Sec. 3.3).
+ *   - Per pixel: entry/exit SDF values from 2D barycentrics on the projected
+ *     faces with perspective correction (App. A.1, A.2), opacity by Eq. 1,
+ *     front-to-back alpha blending of colour, depth, normal and opacity
+ *     (Eq. 2) with the 3DGS blending thresholds (Sec. 3.3).
+ *   - Backward: reverse-order traversal of every tile, chained to the SDF
+ *     values, the vertex colours and the vertex positions.
+ *
+ * Conventions.
+ *   - Every pointer inside the structs below is a DEVICE pointer, float32 or
+ *     int32, contiguous, row-major.  The struct arrays themselves are HOST
+ *     memory and are read during the call only.
+ *   - Cameras are OpenCV pinholes: world->camera x_c = R x_w + t with +x right,
+ *     +y down, +z forward; pixel (i, j) has centre (i + 0.5, j + 0.5).
+ *   - Output image layout: out[8][H][W] = R, G, B, O(opacity), D(depth),
+ *     Nx, Ny, Nz.  The background colour is added to RGB as T_final * bg.
+ *   - The caller owns every buffer, including the workspace.  The library
+ *     never allocates or frees device memory.
+ *   - Calls are asynchronous on the given HIP stream (hipStream_t, passed as
+ *     void*; NULL is the null stream) unless stated otherwise.
+ *   - Return value 0 on success, else one of the negative codes; the message
+ *     of the last failure on the calling thread is in render_last_error().
+ *     No call aborts or throws across this boundary.
+ */
+#ifndef TETSPLAT_H
+#define TETSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RENDER_OK = 0,
+  RENDER_EINVAL = -1,    /* bad argument: null pointer, size, unsupported tile shape or flag */
+  RENDER_ENOSPC = -2,    /* workspace smaller than render_workspace_size() says */
+  RENDER_EHIP = -3,      /* HIP runtime error; its name is in render_last_error() */
+  RENDER_EOVERFLOW = -4  /* a capacity bound was exceeded; outputs are invalid, re-plan */
+};
+
+/* render_params.flags */
+enum {
+  RENDER_RECOMPUTE_STATE = 1, /* backward recomputes each pixel's last contributor and
+                                 transmittance by a forward sweep instead of reading them */
+  RENDER_VALIDATE = 2         /* accepted for compatibility: tet indices are always checked
+                                 against [0, V) on the device; a tet with an index outside it is
+                                 dropped and counted in render_status.invalid_index */
+};
+
+typedef struct {
+  const float* verts;   /* [V,3] vertex positions */
+  const int32_t* tets;  /* [K,4] vertex indices of each tet */
+  const float* sdf;     /* [V]   signed distance per vertex */
+  const float* colors;  /* [V,3] RGB per vertex */
+  int32_t V, K;
+  float s;              /* steepness of Eq. 1 (s of Phi_s) */
+} render_scene;
+
+typedef struct {
+  int32_t scene;        /* index into the scene array */
+  int32_t width, height;
+  float R[9];           /* row-major world->camera rotation */
+  float t[3];
+  float fx, fy, cx, cy;
+  float znear;          /* tets with any vertex depth below znear are culled */
+  float bg[3];          /* background RGB */
+  float* out;           /* [8,H,W] output image, written by render_forward */
+} render_view;
+
+typedef struct {
+  int32_t tile_w, tile_h; /* screen tile; supported: 8x8, 16x8, 8x16, 16x16, 32x8 */
+  int32_t flags;          /* RENDER_* flags above */
+  float alpha_min;        /* skip a tet whose alpha is below this (3DGS: 1/255) */
+  float alpha_clamp;      /* clamp alpha to at most this (3DGS: 0.99) */
+  float t_min;            /* stop before a tet that takes T below this (3DGS: 1e-4) */
+  float prefilter_tf;     /* pre-filter threshold T_f on alpha_max (paper: 1/255) */
+} render_params;
+
+typedef struct {
+  float* dverts;        /* [V,3] dL/dverts, overwritten */
+  float* dsdf;          /* [V]   dL/dsdf, overwritten */
+  float* dcolors;       /* [V,3] dL/dcolors, overwritten */
+} render_grads;
+
+typedef struct {
+  int64_t entries;      /* tile-duplicated (tet, tile) entries of the last forward */
+  int64_t kept;         /* tets kept by the pre-filter, summed over scenes */
+  int64_t records;      /* (view, kept tet) records */
+  int32_t overflow;     /* bit 0: kept capacity, bit 1: entry capacity exceeded */
+  int32_t invalid_index;/* nonzero if some tet had a vertex index outside [0, V) */
+  int64_t entry_capacity, kept_capacity;
+  int64_t entries_needed; /* entries the forward wanted (exact even on overflow) */
+} render_status;
+
+/*
+ * Workspace size in bytes for a forward/backward pair on these scenes and
+ * views.  kept_capacity bounds the total number of tets kept by the
+ * pre-filter (0: the sum of K over scenes, always sufficient);
+ * entry_capacity bounds the number of (tet, tile) entries over all views
+ * (0: 8 per (view, kept tet) record).  Pure host computation.
+ */
+int render_workspace_size(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                          const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                          size_t* bytes);
+
+/*
+ * Forward pass (Sec. 3.2-3.3, Eq. 1-2): writes every view's out[8,H,W] and
+ * leaves the tiling, the sorted lists and the per-pixel state in the
+ * workspace for render_backward.  The capacities are the ones the workspace
+ * was sized for (same arguments as render_workspace_size).  Asynchronous: a
+ * capacity overflow is reported by render_read_status(), not by the return
+ * value.
+ */
+int render_forward(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                   const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Backward pass: given dL/dout (dL_dout[v] is a device [8,H,W] array for view
+ * v) and the workspace of the matching render_forward call (same scenes,
+ * views, params and capacities, inputs unchanged), overwrites grads[s] for
+ * every scene s.  Gradients flow through Eq. 1, the barycentric and
+ * perspective interpolation, the projection, the normal and the colour mean;
+ * clamped, skipped and unreached tets contribute zero.  Per-vertex sums use
+ * float atomics, so the result is reproducible to rounding, not bitwise.
+ */
+int render_backward(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                     const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                     void* workspace, size_t workspace_bytes, const float* const* dL_dout,
+                     render_grads* grads, void* stream);
+
+/* Synchronises the stream and reads the counters of the last forward. */
+int render_read_status(const void* workspace, render_status* status, void* stream);
+
+/*
+ * Device pointers into the workspace for inspection by tests (valid after a
+ * render_forward on that workspace; pure host computation):
+ *   tile_keys[E]        uint32 global tile id of each sorted entry
+ *   entry_record[E]     int32 (view, kept tet) record of each sorted entry
+ *   kept_tet[kept]      int32 tet id of each kept slot, ascending per scene
+ *   view_rec_base[nv]   int32 first record of each view; record r of view v
+ *                       holds kept slot scene_kept_base[scene] + r - base
+ *   scene_kept_base[ns], scene_kept_count[ns]  int32
+ *   ranges[tiles][2]    uint32 half-open entry range of each global tile
+ *   last[pixels], t_last[pixels]  per-pixel compositing state
+ * Global tile ids concatenate the views' row-major tile grids; pixel ids
+ * concatenate the views' row-major pixel grids.
+ */
+typedef struct {
+  const uint32_t* tile_keys;
+  const int32_t* entry_record;
+  const int32_t* kept_tet;
+  const int32_t* view_rec_base;
+  const int32_t* scene_kept_base;
+  const int32_t* scene_kept_count;
+  const uint32_t* ranges;
+  const int32_t* last;
+  const float* t_last;
+  int64_t total_tiles, total_pixels;
+} render_debug_view;
+int render_debug_pointers(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                          const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                          const void* workspace, render_debug_view* out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* render_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TETSPLAT_H */

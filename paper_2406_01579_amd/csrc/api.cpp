@@ -1,0 +1,327 @@
+// Host side of the C ABI declared in include/tetsplat.h: argument checks,
+// workspace layout, and the forward/backward launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ts_internal.h"
+
+namespace ts {
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(RENDER_EHIP, "%s: %s (%s)", where, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool tile_ok(int tw, int th) {
+  const int k = tw * 1000 + th;
+  return k == 8008 || k == 16008 || k == 8016 || k == 16016 || k == 32008;
+}
+
+int check_args(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p) {
+  if (!scenes || !views || !p) return fail(RENDER_EINVAL, "null scenes, views or params");
+  if (ns <= 0 || nv <= 0) return fail(RENDER_EINVAL, "need at least one scene and one view (got %d, %d)", ns, nv);
+  if (!tile_ok(p->tile_w, p->tile_h))
+    return fail(RENDER_EINVAL, "unsupported tile %dx%d (8x8, 16x8, 8x16, 16x16, 32x8)", p->tile_w, p->tile_h);
+  if (p->flags & ~(RENDER_RECOMPUTE_STATE | RENDER_VALIDATE)) return fail(RENDER_EINVAL, "unknown flags 0x%x", p->flags);
+  if (!(p->alpha_clamp > 0.0f && p->alpha_clamp <= 1.0f)) return fail(RENDER_EINVAL, "alpha_clamp must be in (0, 1]");
+  for (int s = 0; s < ns; ++s) {
+    const render_scene& S = scenes[s];
+    if (S.V < 0 || S.K < 0) return fail(RENDER_EINVAL, "scene %d: negative V or K", s);
+    if (S.K > 0 && (!S.verts || !S.tets || !S.sdf || !S.colors))
+      return fail(RENDER_EINVAL, "scene %d: null device pointer", s);
+    if (((uintptr_t)S.tets & 15u) != 0) return fail(RENDER_EINVAL, "scene %d: tets must be 16-byte aligned", s);
+    if (S.K > (1 << 30) || S.V > (1 << 30)) return fail(RENDER_EINVAL, "scene %d: too large", s);
+  }
+  for (int v = 0; v < nv; ++v) {
+    const render_view& V = views[v];
+    if (V.scene < 0 || V.scene >= ns) return fail(RENDER_EINVAL, "view %d: scene index %d out of range", v, V.scene);
+    if (V.width <= 0 || V.height <= 0 || V.width > 16384 || V.height > 16384)
+      return fail(RENDER_EINVAL, "view %d: image size %dx%d out of range", v, V.width, V.height);
+    if (!V.out) return fail(RENDER_EINVAL, "view %d: null output", v);
+  }
+  return RENDER_OK;
+}
+
+void fill_desc(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
+               const Layout& L, std::vector<DevScene>& hs, std::vector<DevView>& hv) {
+  hs.assign(ns, DevScene{});
+  int blk = 0;
+  for (int s = 0; s < ns; ++s) {
+    DevScene& d = hs[s];
+    d.verts = scenes[s].verts;
+    d.tets = scenes[s].tets;
+    d.sdf = scenes[s].sdf;
+    d.colors = scenes[s].colors;
+    d.V = scenes[s].V;
+    d.K = scenes[s].K;
+    d.s = scenes[s].s;
+    d.block_base = blk;
+    d.n_blocks = (scenes[s].K + PF_TILE - 1) / PF_TILE;
+    blk += d.n_blocks;
+  }
+  hv.assign(nv, DevView{});
+  int64_t tb = 0, pb = 0;
+  for (int v = 0; v < nv; ++v) {
+    DevView& d = hv[v];
+    const render_view& V = views[v];
+    std::memcpy(d.R, V.R, sizeof d.R);
+    std::memcpy(d.t, V.t, sizeof d.t);
+    d.fx = V.fx; d.fy = V.fy; d.cx = V.cx; d.cy = V.cy; d.znear = V.znear;
+    std::memcpy(d.bg, V.bg, sizeof d.bg);
+    d.out = V.out;
+    d.dout = nullptr;
+    d.scene = V.scene;
+    d.W = V.width;
+    d.H = V.height;
+    d.tiles_x = (V.width + p->tile_w - 1) / p->tile_w;
+    d.tiles_y = (V.height + p->tile_h - 1) / p->tile_h;
+    d.tile_base = (int32_t)tb;
+    d.pix_base = (int32_t)pb;
+    tb += (int64_t)d.tiles_x * d.tiles_y;
+    pb += (int64_t)V.width * V.height;
+  }
+  (void)L;
+}
+
+}  // namespace
+
+bool plan_layout(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
+                 int64_t kept_cap, int64_t entry_cap, Layout& L, const char** why) {
+  L = Layout{};
+  L.ns = ns;
+  L.nv = nv;
+  int64_t sumK = 0, pf_blocks = 0;
+  for (int s = 0; s < ns; ++s) {
+    sumK += scenes[s].K;
+    pf_blocks += (scenes[s].K + PF_TILE - 1) / PF_TILE;
+  }
+  if (kept_cap <= 0 || kept_cap > sumK) kept_cap = sumK;
+  int64_t rec_cap = 0, tiles = 0, pixels = 0;
+  for (int v = 0; v < nv; ++v) {
+    const int64_t Ks = scenes[views[v].scene].K;
+    rec_cap += Ks < kept_cap ? Ks : kept_cap;
+    tiles += (int64_t)((views[v].width + p->tile_w - 1) / p->tile_w) * ((views[v].height + p->tile_h - 1) / p->tile_h);
+    pixels += (int64_t)views[v].width * views[v].height;
+  }
+  if (entry_cap <= 0) entry_cap = 8 * rec_cap;
+  if (entry_cap < 1) entry_cap = 1;
+  if (rec_cap < 1) rec_cap = 1;
+  if (kept_cap < 1) kept_cap = 1;
+  const int64_t lim = (int64_t)1 << 31;
+  if (rec_cap >= lim || entry_cap >= lim || tiles >= lim || pixels >= lim || kept_cap >= lim) {
+    *why = "problem exceeds 2^31 records, entries, tiles or pixels";
+    return false;
+  }
+  L.kept_cap = kept_cap;
+  L.rec_cap = rec_cap;
+  L.entry_cap = entry_cap;
+  L.pf_blocks = pf_blocks;
+  L.scan_blocks_rec = (rec_cap + SCAN_TILE - 1) / SCAN_TILE;
+  const int64_t smax = rec_cap > entry_cap ? rec_cap : entry_cap;
+  L.sort_blocks_max = (smax + SORT_TILE - 1) / SORT_TILE;
+  L.total_tiles = tiles;
+  L.total_pixels = pixels;
+  int kb = 1;
+  while (((int64_t)1 << kb) < tiles) ++kb;
+  L.key2_bits = kb;
+
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at_ = o; o = align_up(o + bytes, 256); return at_; };
+  L.o_hdr = take(sizeof(DevHeader));
+  L.o_scene = take(sizeof(DevScene) * ns);
+  L.o_view = take(sizeof(DevView) * nv);
+  L.o_view_rec_base = take(4 * (size_t)nv);
+  L.o_scene_kept_base = take(4 * (size_t)ns);
+  L.o_scene_kept_count = take(4 * (size_t)ns);
+  L.o_pf_cnt = take(4 * (size_t)(pf_blocks + 1));
+  L.o_kept_tet = take(4 * (size_t)kept_cap);
+  L.o_trec = take(sizeof(TetRec) * (size_t)kept_cap);
+  L.o_vrec = take(sizeof(ViewRec) * (size_t)rec_cap);
+  L.o_count1 = take(4 * (size_t)rec_cap);
+  L.o_key1a = take(4 * (size_t)rec_cap);
+  L.o_key1b = take(4 * (size_t)rec_cap);
+  L.o_val1a = take(4 * (size_t)rec_cap);
+  L.o_val1b = take(4 * (size_t)rec_cap);
+  L.o_rec_off = take(4 * (size_t)rec_cap);
+  L.o_off_sorted = take(4 * (size_t)rec_cap);
+  L.o_scan_part = take(4 * (size_t)(L.scan_blocks_rec + 1));
+  L.o_hist = take(4 * (size_t)(256 * L.sort_blocks_max + 1));
+  L.o_key2a = take(4 * (size_t)entry_cap);
+  L.o_key2b = take(4 * (size_t)entry_cap);
+  L.o_val2a = take(4 * (size_t)entry_cap);
+  L.o_val2b = take(4 * (size_t)entry_cap);
+  L.o_erec = take(4 * (size_t)entry_cap);
+  L.o_srec = take(4 * (size_t)entry_cap);
+  L.o_inv = take(4 * (size_t)entry_cap);
+  L.o_ranges = take(8 * (size_t)tiles);
+  L.o_proc_end = take(4 * (size_t)tiles);
+  L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE * (size_t)entry_cap);
+  L.o_last = take(4 * (size_t)pixels);
+  L.o_tlast = take(4 * (size_t)pixels);
+  L.bytes = o;
+  return true;
+}
+
+namespace {
+
+int prepare(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
+            int64_t kept_cap, int64_t entry_cap, void* ws, size_t ws_bytes, Layout& L) {
+  int rc = check_args(scenes, ns, views, nv, p);
+  if (rc) return rc;
+  const char* why = nullptr;
+  if (!plan_layout(scenes, ns, views, nv, p, kept_cap, entry_cap, L, &why)) return fail(RENDER_EINVAL, "%s", why);
+  if (!ws) return fail(RENDER_EINVAL, "null workspace");
+  if (((uintptr_t)ws & 255u) != 0) return fail(RENDER_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.bytes)
+    return fail(RENDER_ENOSPC, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
+  return RENDER_OK;
+}
+
+#define TS_TRY(call, name)                        \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, name); \
+  } while (0)
+
+}  // namespace
+}  // namespace ts
+
+using namespace ts;
+
+extern "C" {
+
+const char* render_last_error(void) { return g_err.c_str(); }
+
+int render_workspace_size(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                          const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                          size_t* bytes) {
+  int rc = check_args(scenes, n_scenes, views, n_views, params);
+  if (rc) return rc;
+  if (!bytes) return fail(RENDER_EINVAL, "null bytes");
+  Layout L;
+  const char* why = nullptr;
+  if (!plan_layout(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, L, &why))
+    return fail(RENDER_EINVAL, "%s", why);
+  *bytes = L.bytes;
+  return RENDER_OK;
+}
+
+int render_forward(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                   const render_params* params, int64_t kept_capacity, int64_t entry_capacity, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+  Layout L;
+  int rc = prepare(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, workspace,
+                   workspace_bytes, L);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<DevScene> hs;
+  std::vector<DevView> hv;
+  fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv);
+  TS_TRY(launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, true, st), "upload descriptors");
+  TS_TRY(launch_prefilter(workspace, L, *params, st), "pre-filter");
+  TS_TRY(launch_project(workspace, L, *params, st), "project");
+  TS_TRY(launch_sort_records(workspace, L, st), "depth sort");
+  TS_TRY(launch_count_scan(workspace, L, st), "count scan");
+  TS_TRY(launch_emit(workspace, L, *params, st), "emit");
+  TS_TRY(launch_sort_entries(workspace, L, st), "tile sort");
+  TS_TRY(launch_finalize(workspace, L, st), "tile ranges");
+  TS_TRY(launch_composite(workspace, L, *params, st), "composite");
+  return RENDER_OK;
+}
+
+int render_backward(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                    const render_params* params, int64_t kept_capacity, int64_t entry_capacity, void* workspace,
+                    size_t workspace_bytes, const float* const* dL_dout, render_grads* grads, void* stream) {
+  Layout L;
+  int rc = prepare(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, workspace,
+                   workspace_bytes, L);
+  if (rc) return rc;
+  if (!dL_dout || !grads) return fail(RENDER_EINVAL, "null dL_dout or grads");
+  for (int v = 0; v < n_views; ++v)
+    if (!dL_dout[v]) return fail(RENDER_EINVAL, "view %d: null dL_dout", v);
+  for (int s = 0; s < n_scenes; ++s)
+    if (scenes[s].V > 0 && (!grads[s].dverts || !grads[s].dsdf || !grads[s].dcolors))
+      return fail(RENDER_EINVAL, "scene %d: null gradient buffer", s);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<DevScene> hs;
+  std::vector<DevView> hv;
+  fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv);
+  for (int s = 0; s < n_scenes; ++s) {
+    hs[s].dverts = grads[s].dverts;
+    hs[s].dsdf = grads[s].dsdf;
+    hs[s].dcolors = grads[s].dcolors;
+  }
+  for (int v = 0; v < n_views; ++v) hv[v].dout = dL_dout[v];
+  TS_TRY(launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, false, st), "upload descriptors");
+  TS_TRY(launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
+  TS_TRY(launch_composite_backward(workspace, L, *params, st), "composite backward");
+  TS_TRY(launch_vertex_backward(workspace, L, *params, st), "vertex backward");
+  return RENDER_OK;
+}
+
+int render_read_status(const void* workspace, render_status* status, void* stream) {
+  if (!workspace || !status) return fail(RENDER_EINVAL, "null workspace or status");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DevHeader h;
+  hipError_t e = hipMemcpyAsync(&h, workspace, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "read status");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  status->entries = h.entries_total;
+  status->kept = h.kept_total;
+  status->records = h.records_total;
+  status->overflow = (int32_t)h.overflow;
+  status->invalid_index = (int32_t)h.invalid_index;
+  status->entry_capacity = h.entry_capacity;
+  status->kept_capacity = h.kept_capacity;
+  status->entries_needed = (int64_t)h.entries_needed;
+  return RENDER_OK;
+}
+
+int render_debug_pointers(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                          const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                          const void* workspace, render_debug_view* out) {
+  int rc = check_args(scenes, n_scenes, views, n_views, params);
+  if (rc) return rc;
+  if (!workspace || !out) return fail(RENDER_EINVAL, "null workspace or output");
+  Layout L;
+  const char* why = nullptr;
+  if (!plan_layout(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, L, &why))
+    return fail(RENDER_EINVAL, "%s", why);
+  void* ws = const_cast<void*>(workspace);
+  const int odd = ((L.key2_bits + SORT_BITS - 1) / SORT_BITS) & 1;
+  out->tile_keys = at<const uint32_t>(ws, odd ? L.o_key2b : L.o_key2a);
+  out->entry_record = at<const int32_t>(ws, L.o_srec);
+  out->kept_tet = at<const int32_t>(ws, L.o_kept_tet);
+  out->view_rec_base = at<const int32_t>(ws, L.o_view_rec_base);
+  out->scene_kept_base = at<const int32_t>(ws, L.o_scene_kept_base);
+  out->scene_kept_count = at<const int32_t>(ws, L.o_scene_kept_count);
+  out->ranges = at<const uint32_t>(ws, L.o_ranges);
+  out->last = at<const int32_t>(ws, L.o_last);
+  out->t_last = at<const float>(ws, L.o_tlast);
+  out->total_tiles = L.total_tiles;
+  out->total_pixels = L.total_pixels;
+  return RENDER_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,555 @@
+// Per-scene and per-view preparation kernels of the gfx950 tetrahedron
+// rasterizer: descriptor upload, the alpha_max pre-filter with order-
+// preserving compaction and per-tet normal/colour (Sec. 3.2, App. A.3),
+// projection and tile counting (Sec. 3.3), the device-wide scan of tile
+// counts, tile-duplicated key emission, and tile ranges.
+#include "ts_device.h"
+
+namespace ts {
+
+// ---------------------------------------------------------------------------
+// descriptor upload through kernel arguments (no host-to-device copies, so
+// the whole call sequence can be captured in a graph)
+// ---------------------------------------------------------------------------
+constexpr int BLOB_WORDS = 960;
+struct Blob {
+  uint32_t w[BLOB_WORDS];
+};
+
+__global__ void k_write_blob(Blob b, uint32_t* dst, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = b.w[i];
+}
+
+static hipError_t upload(const void* src, size_t bytes, void* dst, hipStream_t st) {
+  const uint32_t* s = static_cast<const uint32_t*>(src);
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  size_t words = bytes / 4;
+  for (size_t o = 0; o < words; o += BLOB_WORDS) {
+    Blob b;
+    int n = (int)((words - o) < (size_t)BLOB_WORDS ? (words - o) : (size_t)BLOB_WORDS);
+    for (int i = 0; i < n; ++i) b.w[i] = s[o + i];
+    k_write_blob<<<1, 256, 0, st>>>(b, d + o, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, void* ws, const Layout& L,
+                             bool reset_header, hipStream_t st) {
+  hipError_t e;
+  if (reset_header) {
+    // fresh counters for a forward pass (its kernels accumulate into them)
+    DevHeader h{};
+    h.entry_capacity = L.entry_cap;
+    h.kept_capacity = L.kept_cap;
+    e = upload(&h, sizeof h, at<void>(ws, L.o_hdr), st);
+    if (e != hipSuccess) return e;
+  }
+  e = upload(hs, sizeof(DevScene) * ns, at<void>(ws, L.o_scene), st);
+  if (e != hipSuccess) return e;
+  return upload(hv, sizeof(DevView) * nv, at<void>(ws, L.o_view), st);
+}
+
+// ---------------------------------------------------------------------------
+// a1: pre-filter.  alpha_max = Eq. 1 at (max f, min f) over the 4 vertices;
+// keep iff alpha_max >= prefilter_tf.  Kept tets are compacted in ascending
+// tet id per scene (block counts, one-block scan, block-local rescan).
+// ---------------------------------------------------------------------------
+constexpr int PF_THREADS = 256;
+constexpr int PF_PER_THREAD = PF_TILE / PF_THREADS;  // 4 consecutive tets per thread
+
+__device__ __forceinline__ int find_scene_by_block(const DevScene* sc, int ns, int b) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sc[mid].block_base <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Out-of-range vertex indices never reach a memory access: such a tet is
+// dropped (and counted in the header when `invalid` is given).
+__device__ __forceinline__ bool keep_tet(const DevScene& S, int k, float tf, uint32_t* invalid, int4* vi_out) {
+  int4 vi = reinterpret_cast<const int4*>(S.tets)[k];
+  if (vi_out) *vi_out = vi;
+  if ((unsigned)vi.x >= (unsigned)S.V || (unsigned)vi.y >= (unsigned)S.V || (unsigned)vi.z >= (unsigned)S.V ||
+      (unsigned)vi.w >= (unsigned)S.V) {
+    if (invalid) atomicOr(invalid, 1u);
+    return false;
+  }
+  float f0 = S.sdf[vi.x], f1 = S.sdf[vi.y], f2 = S.sdf[vi.z], f3 = S.sdf[vi.w];
+  float fmax = fmaxf(fmaxf(f0, f1), fmaxf(f2, f3));
+  float fmin = fminf(fminf(f0, f1), fminf(f2, f3));
+  return alpha_eq1(fmax, fmin, S.s) >= tf;
+}
+
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* lds /*[8]*/, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+  for (int w = 0; w < PF_THREADS / 64; ++w) {
+    uint32_t t = lds[w];
+    if (w < wave) wbase += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
+
+__global__ __launch_bounds__(PF_THREADS) void k_pf_count(void* ws, Layout L, float tf) {
+  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
+  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+  uint32_t* cnt = at<uint32_t>(ws, L.o_pf_cnt);
+  __shared__ uint32_t lds[8];
+  const int b = blockIdx.x;
+  const int s = find_scene_by_block(sc, L.ns, b);
+  const DevScene S = sc[s];
+  const int k0 = (b - S.block_base) * PF_TILE + threadIdx.x * PF_PER_THREAD;
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < PF_PER_THREAD; ++q) {
+    int k = k0 + q;
+    if (k < S.K) c += keep_tet(S, k, tf, &hdr->invalid_index, nullptr) ? 1u : 0u;
+  }
+  uint32_t tot;
+  block_exclusive_scan_256(c, lds, &tot);
+  if (threadIdx.x == 0) cnt[b] = tot;
+}
+
+// one block: exclusive scan of the block counts, per-scene kept ranges,
+// per-view record bases, totals and capacity checks
+__global__ __launch_bounds__(1024) void k_pf_scan(void* ws, Layout L) {
+  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
+  const DevView* vw = at<const DevView>(ws, L.o_view);
+  uint32_t* cnt = at<uint32_t>(ws, L.o_pf_cnt);
+  int32_t* kbase = at<int32_t>(ws, L.o_scene_kept_base);
+  int32_t* kcount = at<int32_t>(ws, L.o_scene_kept_count);
+  int32_t* rbase = at<int32_t>(ws, L.o_view_rec_base);
+  __shared__ uint32_t part[1024];
+  const int n = (int)L.pf_blocks;
+  const int per = (n + 1023) / 1024;
+  const int t = threadIdx.x;
+  uint32_t sum = 0;
+  for (int i = t * per; i < min(n, (t + 1) * per); ++i) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    uint32_t v = (t >= o) ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (int i = t * per; i < min(n, (t + 1) * per); ++i) {
+    uint32_t c = cnt[i];
+    cnt[i] = run;
+    run += c;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const uint32_t total = part[1023];
+    const uint32_t cap = (uint32_t)L.kept_cap;
+    hdr->kept_total = total;
+    uint32_t ovf = 0;
+    if (total > cap) ovf |= 1u;
+    for (int s = 0; s < L.ns; ++s) {
+      const int bb0 = sc[s].block_base, bb1 = sc[s].block_base + sc[s].n_blocks;
+      uint32_t b0 = (bb0 < n) ? cnt[bb0] : total;
+      uint32_t b1 = (bb1 < n) ? cnt[bb1] : total;
+      if (b0 > cap) b0 = cap;
+      if (b1 > cap) b1 = cap;
+      kbase[s] = (int32_t)b0;
+      kcount[s] = (int32_t)(b1 - b0);
+    }
+    uint64_t r = 0;
+    for (int v = 0; v < L.nv; ++v) {
+      rbase[v] = (int32_t)r;
+      r += (uint64_t)kcount[vw[v].scene];
+    }
+    if (r > (uint64_t)L.rec_cap) { ovf |= 1u; r = (uint64_t)L.rec_cap; }
+    hdr->records_total = (uint32_t)r;
+    hdr->overflow = ovf;
+    hdr->entries_total = 0;
+  }
+}
+
+// rescan and write the kept tets' records: vertices, SDF, normal (App. A.3 via
+// the equivalent 3x3 edge system), mean colour
+__global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, float tf) {
+  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
+  const uint32_t* off = at<const uint32_t>(ws, L.o_pf_cnt);
+  TetRec* trec = at<TetRec>(ws, L.o_trec);
+  int32_t* kept_tet = at<int32_t>(ws, L.o_kept_tet);
+  __shared__ uint32_t lds[8];
+  const int b = blockIdx.x;
+  const int s = find_scene_by_block(sc, L.ns, b);
+  const DevScene S = sc[s];
+  const int k0 = (b - S.block_base) * PF_TILE + threadIdx.x * PF_PER_THREAD;
+  bool kp[PF_PER_THREAD];
+  int4 vi[PF_PER_THREAD];
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < PF_PER_THREAD; ++q) {
+    int k = k0 + q;
+    kp[q] = (k < S.K) && keep_tet(S, k, tf, nullptr, &vi[q]);
+    c += kp[q] ? 1u : 0u;
+  }
+  uint32_t tot;
+  uint32_t slot = off[b] + block_exclusive_scan_256(c, lds, &tot);
+#pragma unroll
+  for (int q = 0; q < PF_PER_THREAD; ++q) {
+    if (!kp[q]) continue;
+    const uint32_t my = slot++;
+    if (my >= (uint32_t)L.kept_cap) continue;
+    const int idx[4] = {vi[q].x, vi[q].y, vi[q].z, vi[q].w};
+    TetRec r;
+    for (int a = 0; a < 4; ++a) {
+      r.x[a][0] = S.verts[3 * (size_t)idx[a] + 0];
+      r.x[a][1] = S.verts[3 * (size_t)idx[a] + 1];
+      r.x[a][2] = S.verts[3 * (size_t)idx[a] + 2];
+      r.f[a] = S.sdf[idx[a]];
+    }
+    // g = E^-1 (f_k - f_0), E rows e_k = x_k - x_0 (k = 1..3)
+    float e[3][3], df[3];
+    for (int a = 0; a < 3; ++a) {
+      for (int j = 0; j < 3; ++j) e[a][j] = r.x[a + 1][j] - r.x[0][j];
+      df[a] = r.f[a + 1] - r.f[0];
+    }
+    float c23[3] = {e[1][1] * e[2][2] - e[1][2] * e[2][1], e[1][2] * e[2][0] - e[1][0] * e[2][2],
+                    e[1][0] * e[2][1] - e[1][1] * e[2][0]};
+    float c31[3] = {e[2][1] * e[0][2] - e[2][2] * e[0][1], e[2][2] * e[0][0] - e[2][0] * e[0][2],
+                    e[2][0] * e[0][1] - e[2][1] * e[0][0]};
+    float c12[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
+                    e[0][0] * e[1][1] - e[0][1] * e[1][0]};
+    float det = e[0][0] * c23[0] + e[0][1] * c23[1] + e[0][2] * c23[2];
+    float g[3];
+    for (int j = 0; j < 3; ++j) g[j] = (det != 0.0f) ? (c23[j] * df[0] + c31[j] * df[1] + c12[j] * df[2]) / det : 0.0f;
+    float gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int j = 0; j < 3; ++j) r.n[j] = (gn > 0.0f) ? g[j] / gn : 0.0f;
+    for (int j = 0; j < 3; ++j) {
+      const float* C = S.colors;
+      r.c[j] = ((C[3 * (size_t)idx[0] + j] + C[3 * (size_t)idx[1] + j]) +
+                (C[3 * (size_t)idx[2] + j] + C[3 * (size_t)idx[3] + j])) * 0.25f;
+    }
+    r.tet = k0 + q;
+    r.scene = s;
+    trec[my] = r;
+    kept_tet[my] = k0 + q;
+  }
+}
+
+hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  if (L.pf_blocks > 0) k_pf_count<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
+  k_pf_scan<<<1, 1024, 0, st>>>(ws, L);
+  if (L.pf_blocks > 0) k_pf_scatter<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a2: per (view, kept tet) record: camera transform, near-plane cull,
+// projection, pixel rectangle, tile count, depth key (float32, fixed op
+// sequence), 2D face determinants, shading features.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2, int th_log2) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const DevView* vw = at<const DevView>(ws, L.o_view);
+  const int32_t* kbase = at<const int32_t>(ws, L.o_scene_kept_base);
+  const int32_t* kcount = at<const int32_t>(ws, L.o_scene_kept_count);
+  const int32_t* rbase = at<const int32_t>(ws, L.o_view_rec_base);
+  const TetRec* trec = at<const TetRec>(ws, L.o_trec);
+  ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
+  uint32_t* count1 = at<uint32_t>(ws, L.o_count1);
+  uint32_t* key1 = at<uint32_t>(ws, L.o_key1a);
+  const int v = blockIdx.y;
+  const DevView V = vw[v];
+  const int n = kcount[V.scene];
+  const int r0 = rbase[v];
+  const int kb = kbase[V.scene];
+  if ((uint64_t)r0 + (uint64_t)n > (uint64_t)hdr->records_total) return;  // capacity overflow guard
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const TetRec T = trec[kb + k];
+    const int r = r0 + k;
+    float X[4], Y[4], Z[4], px[4], py[4];
+    bool culled = false;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const float x = T.x[a][0], y = T.x[a][1], z = T.x[a][2];
+      X[a] = fmaf(V.R[0], x, fmaf(V.R[1], y, fmaf(V.R[2], z, V.t[0])));
+      Y[a] = fmaf(V.R[3], x, fmaf(V.R[4], y, fmaf(V.R[5], z, V.t[1])));
+      Z[a] = fmaf(V.R[6], x, fmaf(V.R[7], y, fmaf(V.R[8], z, V.t[2])));
+      culled |= (Z[a] < V.znear);
+    }
+    ViewRec R;
+    uint32_t cnt = 0, key = 0xffffffffu;
+    if (!culled) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        px[a] = fmaf(V.fx, X[a] / Z[a], V.cx);
+        py[a] = fmaf(V.fy, Y[a] / Z[a], V.cy);
+      }
+      const float zt = ((Z[0] + Z[1]) + (Z[2] + Z[3])) * 0.25f;
+      const float xmin = fminf(fminf(px[0], px[1]), fminf(px[2], px[3]));
+      const float xmax = fmaxf(fmaxf(px[0], px[1]), fmaxf(px[2], px[3]));
+      const float ymin = fminf(fminf(py[0], py[1]), fminf(py[2], py[3]));
+      const float ymax = fmaxf(fmaxf(py[0], py[1]), fmaxf(py[2], py[3]));
+      const int i0 = (int)fminf(fmaxf(ceilf(xmin - 0.5f), 0.0f), (float)V.W);
+      const int i1 = (int)fmaxf(fminf(floorf(xmax - 0.5f), (float)(V.W - 1)), -1.0f);
+      const int j0 = (int)fminf(fmaxf(ceilf(ymin - 0.5f), 0.0f), (float)V.H);
+      const int j1 = (int)fmaxf(fminf(floorf(ymax - 0.5f), (float)(V.H - 1)), -1.0f);
+      if (i0 <= i1 && j0 <= j1) {
+        const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2, ty1 = j1 >> th_log2;
+        cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        key = __float_as_uint(zt);
+        for (int a = 0; a < 4; ++a) {
+          R.px[a] = px[a];
+          R.py[a] = py[a];
+          R.iz[a] = 1.0f / Z[a];
+          R.f[a] = T.f[a];
+        }
+        for (int F = 0; F < 4; ++F) {
+          const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
+          R.D[F] = (px[B] - px[A]) * (py[C] - py[A]) - (py[B] - py[A]) * (px[C] - px[A]);
+        }
+        R.c[0] = T.c[0]; R.c[1] = T.c[1]; R.c[2] = T.c[2];
+        R.zt = zt;
+        R.n[0] = T.n[0]; R.n[1] = T.n[1]; R.n[2] = T.n[2];
+        R.rx = (uint32_t)i0 | ((uint32_t)i1 << 16);
+        R.ry = (uint32_t)j0 | ((uint32_t)j1 << 16);
+        R.kept = kb + k;
+        R.pad[0] = v;
+        R.pad[1] = 0;
+        vrec[r] = R;
+      }
+    }
+    count1[r] = cnt;
+    key1[r] = key;
+  }
+}
+
+hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  int twl = __builtin_ctz((unsigned)p.tile_w), thl = __builtin_ctz((unsigned)p.tile_h);
+  dim3 grid(512, (unsigned)L.nv);
+  k_project<<<grid, 256, 0, st>>>(ws, L, twl, thl);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of the tile counts in depth-sorted order -> entry offsets
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_reduce(void* ws, Layout L, const uint32_t* srec) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
+  uint32_t* part = at<uint32_t>(ws, L.o_scan_part);
+  __shared__ uint32_t lds[8];
+  const uint32_t n = hdr->records_total;
+  const uint32_t q0 = blockIdx.x * SCAN_TILE;
+  if (q0 >= n) return;
+  uint32_t sum = 0;
+  for (uint32_t q = q0 + threadIdx.x; q < min(n, q0 + SCAN_TILE); q += 256) sum += count1[srec[q]];
+  uint32_t tot;
+  block_exclusive_scan_256(sum, lds, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_spine(void* ws, Layout L) {
+  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+  uint32_t* part = at<uint32_t>(ws, L.o_scan_part);
+  __shared__ unsigned long long lp[1024];
+  const uint32_t n = hdr->records_total;
+  const int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
+  const int per = (nb + 1023) / 1024;
+  const int t = threadIdx.x;
+  unsigned long long sum = 0;
+  for (int i = t * per; i < min(nb, (t + 1) * per); ++i) sum += part[i];
+  lp[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    unsigned long long v = (t >= o) ? lp[t - o] : 0ull;
+    __syncthreads();
+    lp[t] += v;
+    __syncthreads();
+  }
+  unsigned long long run = lp[t] - sum;
+  for (int i = t * per; i < min(nb, (t + 1) * per); ++i) {
+    uint32_t c = part[i];
+    part[i] = (uint32_t)run;
+    run += c;
+  }
+  if (t == 1023) {
+    unsigned long long total = lp[1023];
+    uint32_t E = total > (unsigned long long)L.entry_cap ? (uint32_t)L.entry_cap : (uint32_t)total;
+    if (total > (unsigned long long)L.entry_cap) hdr->overflow |= 2u;
+    hdr->entries_total = E;
+    hdr->entries_needed = total;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(void* ws, Layout L, const uint32_t* srec) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
+  const uint32_t* part = at<const uint32_t>(ws, L.o_scan_part);
+  uint32_t* off = at<uint32_t>(ws, L.o_off_sorted);
+  __shared__ uint32_t lds[8];
+  const uint32_t n = hdr->records_total;
+  const uint32_t q0 = blockIdx.x * SCAN_TILE;
+  if (q0 >= n) return;
+  constexpr int PER = SCAN_TILE / 256;
+  // thread t owns PER consecutive items
+  uint32_t c[PER];
+  uint32_t sum = 0;
+  const uint32_t base = q0 + threadIdx.x * PER;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    uint32_t q = base + i;
+    c[i] = (q < n) ? count1[srec[q]] : 0u;
+    sum += c[i];
+  }
+  uint32_t tot;
+  uint32_t run = part[blockIdx.x] + block_exclusive_scan_256(sum, lds, &tot);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    uint32_t q = base + i;
+    if (q < n) off[q] = run;
+    run += c[i];
+  }
+}
+
+// sorted record order lives in the buffer the record sort ended in
+__host__ __device__ static const uint32_t* sorted_records(void* ws, const Layout& L) {
+  // 32-bit keys in 8-bit digits: 4 passes, a->b->a->b->a
+  return at<const uint32_t>(ws, L.o_val1a);
+}
+
+hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st) {
+  const uint32_t* srec = sorted_records(ws, L);
+  unsigned nb = (unsigned)L.scan_blocks_rec;
+  k_scan_reduce<<<nb, 256, 0, st>>>(ws, L, srec);
+  k_scan_spine<<<1, 1024, 0, st>>>(ws, L);
+  k_scan_down<<<nb, 256, 0, st>>>(ws, L, srec);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a4: duplicate each record once per overlapped tile, in depth-sorted record
+// order; key = global tile id, value = entry index (implicit)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, int th_log2) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const DevView* vw = at<const DevView>(ws, L.o_view);
+  const uint32_t* srec = sorted_records(ws, L);
+  const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
+  const uint32_t* off = at<const uint32_t>(ws, L.o_off_sorted);
+  const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
+  uint32_t* rec_off = at<uint32_t>(ws, L.o_rec_off);
+  uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
+  uint32_t* erec = at<uint32_t>(ws, L.o_erec);
+  const uint32_t n = hdr->records_total;
+  const uint64_t cap = (uint64_t)L.entry_cap;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const uint32_t r = srec[q];
+    const uint32_t c = count1[r];
+    if (c == 0) continue;
+    const uint32_t o = off[q];
+    rec_off[r] = o;
+    const ViewRec& R = vrec[r];
+    int i0, i1, j0, j1;
+    unpack_rect(R, i0, i1, j0, j1);
+    const DevView& V = vw[R.pad[0]];
+    const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
+    const int nx = tx1 - tx0 + 1;
+    for (uint32_t j = 0; j < c; ++j) {
+      const uint64_t d = (uint64_t)o + j;
+      if (d >= cap) break;
+      const int ty = ty0 + (int)(j / nx), tx = tx0 + (int)(j % nx);
+      key2[d] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+      erec[d] = r;
+    }
+  }
+}
+
+hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  int twl = __builtin_ctz((unsigned)p.tile_w), thl = __builtin_ctz((unsigned)p.tile_h);
+  k_emit<<<1024, 256, 0, st>>>(ws, L, twl, thl);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a6: tile ranges, record of each sorted entry, inverse permutation
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(void* ws, Layout L, const uint32_t* keys, const uint32_t* vals) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const uint32_t* erec = at<const uint32_t>(ws, L.o_erec);
+  uint32_t* srec = at<uint32_t>(ws, L.o_srec);
+  uint32_t* inv = at<uint32_t>(ws, L.o_inv);
+  uint32_t* ranges = at<uint32_t>(ws, L.o_ranges);
+  const uint32_t n = hdr->entries_total;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const uint32_t t = keys[p];
+    const uint32_t d = vals[p];
+    srec[p] = erec[d];
+    inv[d] = p;
+    if (p == 0 || keys[p - 1] != t) ranges[2 * (size_t)t] = p;
+    if (p + 1 == n || keys[p + 1] != t) ranges[2 * (size_t)t + 1] = p + 1;
+  }
+}
+
+static int passes_for(int bits) { return (bits + SORT_BITS - 1) / SORT_BITS; }
+
+hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
+  const bool odd = passes_for(L.key2_bits) & 1;
+  const uint32_t* keys = at<const uint32_t>(ws, odd ? L.o_key2b : L.o_key2a);
+  const uint32_t* vals = at<const uint32_t>(ws, odd ? L.o_val2b : L.o_val2a);
+  k_fill_u32<<<256, 256, 0, st>>>(at<uint32_t>(ws, L.o_ranges), 2 * (uint64_t)L.total_tiles, 0u);
+  k_finalize<<<2048, 256, 0, st>>>(ws, L, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_records(void* ws, const Layout& L, hipStream_t st) {
+  uint32_t *ko, *vo;
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  return radix_sort_pairs(at<uint32_t>(ws, L.o_key1a), at<uint32_t>(ws, L.o_val1a), at<uint32_t>(ws, L.o_key1b),
+                          at<uint32_t>(ws, L.o_val1b), true, &hdr->records_total, L.rec_cap, 32,
+                          at<uint32_t>(ws, L.o_hist), L.sort_blocks_max, st, &ko, &vo);
+}
+
+hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st) {
+  uint32_t *ko, *vo;
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  return radix_sort_pairs(at<uint32_t>(ws, L.o_key2a), at<uint32_t>(ws, L.o_val2a), at<uint32_t>(ws, L.o_key2b),
+                          at<uint32_t>(ws, L.o_val2b), true, &hdr->entries_total, L.entry_cap, L.key2_bits,
+                          at<uint32_t>(ws, L.o_hist), L.sort_blocks_max, st, &ko, &vo);
+}
+
+// ---------------------------------------------------------------------------
+// gradient buffers are overwritten: clear them first
+// ---------------------------------------------------------------------------
+__global__ void k_zero_grads(void* ws, Layout L) {
+  const DevScene& S = at<const DevScene>(ws, L.o_scene)[blockIdx.y];
+  const size_t n3 = 3 * (size_t)S.V;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n3; i += (size_t)gridDim.x * blockDim.x) {
+    S.dverts[i] = 0.0f;
+    S.dcolors[i] = 0.0f;
+    if (i < (size_t)S.V) S.dsdf[i] = 0.0f;
+  }
+}
+
+hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene*, hipStream_t st) {
+  dim3 grid(256, (unsigned)L.ns);
+  k_zero_grads<<<grid, 256, 0, st>>>(ws, L);
+  return hipGetLastError();
+}
+
+}  // namespace ts

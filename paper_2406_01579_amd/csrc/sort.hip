@@ -1,0 +1,149 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs for gfx950, in
+// the reduce-then-scan form of Merrill & Grimshaw (2010), the GPU radix sort
+// the paper cites (Sec. 3.3).  Per 8-bit digit pass:
+//   upsweep   - per-block digit histogram (LDS atomics)
+//   spine     - one-block exclusive scan of the digit-major histogram table,
+//               giving every (digit, block) its global output offset
+//   downsweep - per block, in input order, the rank of every key among the
+//               equal digits before it (wave ballots + per-wave LDS counts),
+//               then a scatter to offset + rank.
+// The element count lives on the device (it is produced by earlier kernels),
+// so grids are sized for the capacity and idle blocks exit at once.
+#include "ts_internal.h"
+
+namespace ts {
+
+namespace {
+constexpr int RADIX = 1 << SORT_BITS;
+constexpr int WAVES = SORT_THREADS / 64;
+
+__device__ __forceinline__ uint32_t sort_n(const uint32_t* n_dev, int64_t cap) {
+  uint32_t n = *n_dev;
+  return (int64_t)n > cap ? (uint32_t)cap : n;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_up(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
+                                                           int64_t cap, int shift, int digit_bits,
+                                                           uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[RADIX];
+  const uint32_t n = sort_n(n_dev, cap);
+  const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t b = blockIdx.x;
+  if (b >= nb) return;
+  const uint32_t mask = (1u << digit_bits) - 1u;
+  for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) h[d] = 0;
+  __syncthreads();
+  const uint32_t i0 = b * SORT_TILE;
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    uint32_t i = i0 + it * SORT_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) hist[(size_t)d * nb + b] = h[d];
+}
+
+__global__ __launch_bounds__(1024) void k_radix_spine(uint32_t* hist, const uint32_t* n_dev, int64_t cap,
+                                                      int digit_bits) {
+  __shared__ uint32_t part[1024];
+  const uint32_t n = sort_n(n_dev, cap);
+  const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t m = nb << digit_bits;
+  const uint32_t per = (m + 1023) / 1024;
+  const uint32_t t = threadIdx.x;
+  const uint32_t lo = min(m, t * per), hi = min(m, (t + 1) * per);
+  uint32_t sum = 0;
+  for (uint32_t i = lo; i < hi; ++i) sum += hist[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    uint32_t v = (t >= (uint32_t)o) ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (uint32_t i = lo; i < hi; ++i) {
+    uint32_t c = hist[i];
+    hist[i] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __restrict__ kin,
+                                                             const uint32_t* __restrict__ vin,
+                                                             uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             const uint32_t* n_dev, int64_t cap, int shift,
+                                                             int digit_bits, const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t base[RADIX];
+  __shared__ uint32_t wcnt[WAVES][RADIX];
+  const uint32_t n = sort_n(n_dev, cap);
+  const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t b = blockIdx.x;
+  if (b >= nb) return;
+  const uint32_t mask = (1u << digit_bits) - 1u;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) base[d] = hist[(size_t)d * nb + b];
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const uint32_t i = b * SORT_TILE + it * SORT_THREADS + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? (vin ? vin[i] : i) : 0u;
+    const uint32_t digit = (key >> shift) & mask;
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+    for (int bit = 0; bit < digit_bits; ++bit) {
+      const bool set = (digit >> bit) & 1u;
+      const uint64_t bb = __ballot(set);
+      peers &= set ? bb : ~bb;
+    }
+    for (int d = threadIdx.x; d < WAVES * RADIX; d += SORT_THREADS) (&wcnt[0][0])[d] = 0;
+    __syncthreads();
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
+      uint32_t s = base[d];
+      for (int w = 0; w < WAVES; ++w) {
+        uint32_t c = wcnt[w][d];
+        wcnt[w][d] = s;
+        s += c;
+      }
+      base[d] = s;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wcnt[wave][digit] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+}  // namespace
+
+hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool identity,
+                            const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
+                            hipStream_t st, uint32_t** keys_out, uint32_t** vals_out) {
+  const unsigned nb = (unsigned)((cap + SORT_TILE - 1) / SORT_TILE);
+  (void)hist_blocks;
+  uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
+  bool first = true;
+  for (int shift = 0; shift < bits; shift += SORT_BITS) {
+    const int db = (bits - shift) < SORT_BITS ? (bits - shift) : SORT_BITS;
+    if (nb > 0) {
+      k_radix_up<<<nb, SORT_THREADS, 0, st>>>(ki, n_dev, cap, shift, db, hist);
+      k_radix_spine<<<1, 1024, 0, st>>>(hist, n_dev, cap, db);
+      k_radix_down<<<nb, SORT_THREADS, 0, st>>>(ki, (first && identity) ? nullptr : vi, ko, vo, n_dev, cap, shift, db,
+                                                  hist);
+    }
+    first = false;
+    uint32_t* t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+  }
+  *keys_out = ki;
+  *vals_out = vi;
+  return hipGetLastError();
+}
+
+}  // namespace ts

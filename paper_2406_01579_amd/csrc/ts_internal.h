@@ -1,0 +1,149 @@
+// Internal declarations of the gfx950 tetrahedron rasterizer: device-side
+// descriptors, the workspace layout, and the host-side launchers that the
+// C ABI (api.cpp) strings together.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/tetsplat.h"
+
+namespace ts {
+
+// ---------------------------------------------------------------------------
+// device descriptors (written into the workspace by k_write_desc)
+// ---------------------------------------------------------------------------
+struct DevScene {
+  const float* verts;
+  const int32_t* tets;
+  const float* sdf;
+  const float* colors;
+  float* dverts;
+  float* dsdf;
+  float* dcolors;
+  int32_t V, K;
+  float s;
+  int32_t block_base;   // first pre-filter block of this scene
+  int32_t n_blocks;
+  int32_t pad[3];
+};
+
+struct DevView {
+  float R[9], t[3];
+  float fx, fy, cx, cy, znear;
+  float bg[3];
+  float* out;
+  const float* dout;
+  int32_t scene, W, H;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_base;    // first global tile id of this view
+  int32_t pix_base;     // first global pixel id of this view
+  int32_t pad;
+};
+
+// device-written counters at the start of the workspace
+struct DevHeader {
+  uint32_t kept_total;
+  uint32_t records_total;
+  uint32_t entries_total;
+  uint32_t overflow;
+  uint32_t invalid_index;
+  uint32_t pad0[3];
+  int64_t entry_capacity, kept_capacity;
+  uint64_t entries_needed;  // entries the last forward wanted (exact, also on overflow)
+  uint32_t pad1[50];
+};
+static_assert(sizeof(DevHeader) == 256, "header is 256 bytes");
+
+// Per kept tet, view independent (96 B): vertex positions, SDF, normal,
+// mean colour, tet id.
+struct TetRec {
+  float x[4][3];
+  float f[4];
+  float n[3];
+  float c[3];
+  int32_t tet;
+  int32_t scene;
+};
+static_assert(sizeof(TetRec) == 96, "tet record is 96 bytes");
+
+// Per (view, kept tet) record read by the compositing kernels (128 B, one
+// cache line): projected vertices, inverse camera depths, SDF, 2D face
+// determinants, shading features, pixel rectangle.
+struct ViewRec {
+  float px[4], py[4];
+  float iz[4];      // 1 / Z_k
+  float f[4];
+  float D[4];       // 2D determinant of each projected face (exact sign)
+  float c[3];
+  float zt;         // mean camera depth (blend depth, sort key)
+  float n[3];
+  uint32_t rx;      // i0 | i1 << 16 (inclusive pixel columns)
+  uint32_t ry;      // j0 | j1 << 16
+  int32_t kept;     // global kept slot
+  int32_t pad[2];
+};
+static_assert(sizeof(ViewRec) == 128, "view record is 128 bytes");
+
+constexpr int TGRAD_STRIDE = 24;  // floats per per-entry gradient
+// per-entry gradient layout (screen space of one record)
+enum { G_PX = 0, G_PY = 4, G_IZ = 8, G_F = 12, G_C = 16, G_ZT = 19, G_N = 20 };
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+constexpr int PF_TILE = 1024;      // tets per pre-filter block
+constexpr int SCAN_TILE = 2048;    // items per scan block
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+constexpr int SORT_BITS = 8;
+
+struct Layout {
+  int ns, nv;
+  int64_t kept_cap, rec_cap, entry_cap;
+  int64_t pf_blocks, scan_blocks_rec, sort_blocks_max, total_tiles, total_pixels;
+  int key2_bits;
+  size_t o_hdr, o_scene, o_view, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
+  size_t o_pf_cnt, o_kept_tet, o_trec;
+  size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_rec_off, o_off_sorted, o_scan_part;
+  size_t o_hist;
+  size_t o_key2a, o_key2b, o_val2a, o_val2b, o_erec, o_srec, o_inv;
+  size_t o_ranges, o_proc_end, o_tgrad, o_last, o_tlast;
+  size_t bytes;
+};
+
+bool plan_layout(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
+                 int64_t kept_cap, int64_t entry_cap, Layout& L, const char** why);
+
+template <class T>
+__host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+// ---------------------------------------------------------------------------
+// launchers (each returns hipSuccess or the launch error)
+// ---------------------------------------------------------------------------
+hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, void* ws, const Layout& L,
+                             bool reset_header, hipStream_t st);
+hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_sort_records(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_composite(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_composite_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene* hs, hipStream_t st);
+
+// radix sort of (uint32 key, uint32 value) pairs, stable, LSD over key bits
+// [0, bits).  n is read on the device from *n_dev (clamped to cap).  The
+// first pass takes vals_in == nullptr as the identity permutation.  On
+// return the sorted data is in (*keys_out, *vals_out), which point at one of
+// the two buffer pairs.
+hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool identity,
+                            const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
+                            hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
+
+}  // namespace ts
