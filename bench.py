@@ -1,0 +1,228 @@
+"""Throughput benchmark of the gfx950 tetrahedron rasterizer.
+
+One step = forward + backward of the whole rendering path (pre-filter,
+projection, depth sort, tile binning and sort, compositing, reverse-order
+backward, vertex chain) through the autograd Function, on the training-shaped
+workload: a 64^3-cube Kuhn grid (1,572,864 tets, 274,625 vertices) with a
+sphere/torus smooth-union SDF plus noise, per-vertex RGB, 4 orbit views at
+512x512, s = 320.  Inputs are resident on the device before timing starts.
+
+Prints one JSON line (rank 0, one GPU).  Besides the headline it reports the
+plain path (one launch sequence per view), step latency percentiles, per-stage
+times from HIP events on the rendering stream, the roofline of the dominant
+compositing kernel and the CPU oracle timed on a bounded pixel sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpixels/s (64³ grid, 512², 4 views) + p99 latency vs plain path"
+HBM_PEAK_GBS = 8000.0
+REC_BYTES = 128          # one ViewRec per tile entry
+ENTRY_LIST_BYTES = 4     # sorted record index per entry
+TGRAD_BYTES = 96         # per-entry screen-space gradient written by the backward
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--s", type=float, default=320.0)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--check", default="lazy", choices=["sync", "lazy"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-view path")
+    ap.add_argument("--cpu-pixels", type=int, default=400000)
+    return ap.parse_args()
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
+              "build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2406_01579_amd import Params, Renderer, SceneT, TetSplatFunction
+    from paper_2406_01579_amd import _lib
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    wl = synth.training(s=args.s)
+    sc = wl.scenes[0]
+    cams = wl.cams
+    nv = cams.shape[0]
+    W, H = int(cams[0, 0]), int(cams[0, 1])
+    pixels = nv * W * H
+    st = SceneT.from_numpy(sc, dev)
+    verts = st.verts.clone().requires_grad_(True)
+    sdf = st.sdf.clone().requires_grad_(True)
+    colors = st.colors.clone().requires_grad_(True)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    dout = torch.randn((nv, 8, H, W), device=dev, generator=gen)
+    params = Params(tile_w=tw, tile_h=th)
+    renderer = Renderer(params, device=dev, check=args.check)
+
+    def step(cam_subset=None):
+        cs = cams if cam_subset is None else cams[cam_subset]
+        out = TetSplatFunction.apply(verts, sdf, colors, st.tets, cs, args.s, renderer)
+        g = dout if cam_subset is None else dout[cam_subset]
+        torch.autograd.backward(out, g)
+        verts.grad = None
+        sdf.grad = None
+        colors.grad = None
+
+    # warm-up (also sizes the workspaces)
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, HIP events per step and per pipeline stage
+    _lib.profile(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record()
+        step()
+        evs[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = _lib.profile_read()
+    _lib.profile(False)
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_per_step = 1000.0 * wall / args.steps
+    value = pixels / (ms_per_step * 1e-3) / 1e6
+
+    # workload facts of the last forward (for the roofline)
+    plan = renderer.forward([SceneT(verts.detach(), st.tets, sdf.detach(), colors.detach(), args.s)], cams)
+    stt = renderer.read_status(plan)
+    dbg = renderer.debug(plan)
+    E = int(stt.entries)
+    tiles = dbg["ranges"].shape[0]
+    last = dbg["last"]
+    # entries each tile had to walk: up to its last blended entry (what the
+    # backward reads); the forward walks the same prefix plus its final chunk
+    rng_ = dbg["ranges"].astype(np.int64)
+    # per-tile max last-blended position from the per-pixel state
+    tile_of_pix = []
+    tx_n, ty_n = (W + tw - 1) // tw, (H + th - 1) // th
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    tloc = (jj // th) * tx_n + (ii // tw)
+    e_proc = 0
+    for v in range(nv):
+        lv = last[v * W * H:(v + 1) * W * H].reshape(H, W)
+        mx = np.full(tx_n * ty_n, -1, np.int64)
+        np.maximum.at(mx, tloc.ravel(), lv.ravel())
+        base = v * tx_n * ty_n
+        st_ = rng_[base:base + tx_n * ty_n, 0]
+        e_proc += int(np.maximum(mx + 1 - st_, 0)[mx >= 0].sum())
+    del plan
+
+    comp_ms, comp_n = stages["composite"]
+    bwd_ms, bwd_n = stages["composite_bwd"]
+    fwd_avg = comp_ms / max(comp_n, 1)
+    bwd_avg = bwd_ms / max(bwd_n, 1)
+    # algorithmic HBM bytes per launch (one launch covers all 4 views)
+    fwd_bytes = (REC_BYTES + ENTRY_LIST_BYTES) * E + 8 * tiles + (32 + 8) * pixels
+    bwd_bytes = (REC_BYTES + ENTRY_LIST_BYTES + TGRAD_BYTES) * e_proc + 8 * tiles + 4 * tiles + (32 + 8) * pixels
+    kern = {
+        "composite": dict(ms=fwd_avg, bytes=fwd_bytes),
+        "composite_bwd": dict(ms=bwd_avg, bytes=bwd_bytes),
+    }
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    ach = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "kernel_ms": round(kern[dom]["ms"], 4), "algorithmic_bytes": int(kern[dom]["bytes"])}
+
+    # plain path: one launch sequence per view
+    plain = None
+    if not args.no_plain:
+        for _ in range(3):
+            for v in range(nv):
+                step([v])
+        torch.cuda.synchronize()
+        n_plain = max(5, args.steps // 2)
+        t0 = time.perf_counter()
+        pev = []
+        for _ in range(n_plain):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for v in range(nv):
+                step([v])
+            b.record()
+            pev.append((a, b))
+        torch.cuda.synchronize()
+        pw = (time.perf_counter() - t0) / n_plain
+        pms = [a.elapsed_time(b) for a, b in pev]
+        plain = {"ms_per_step": round(1000 * pw, 4), "mpx_s": round(pixels / pw / 1e6, 2),
+                 "p50_ms": round(pct(pms, 50), 4), "p99_ms": round(pct(pms, 99), 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(sc, cams, args.s, args.cpu_pixels)
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "training-shaped: 64^3-cube Kuhn grid (1,572,864 tets), sphere+torus smooth-union "
+                               "SDF + N(0,0.005), per-vertex RGB, 4 orbit views 512x512, s=320, fwd+bwd",
+                   "views": nv, "width": W, "height": H, "tile": args.tile, "s": args.s,
+                   "path": "one launch sequence for all views", "status_check": args.check},
+        "p50_ms": round(pct(step_ms, 50), 4), "p99_ms": round(pct(step_ms, 99), 4),
+        "plain_path": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items()},
+        "workload_stats": {"entries": E, "entries_walked_bwd": e_proc, "kept_tets": int(stt.kept),
+                           "records": int(stt.records), "tiles": tiles},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(sc, cams, s, npix):
+    """The oracle as it stands, float32, forward + backward on a bounded
+    sample of pixels of the same workload (every k-th pixel of every view)."""
+    import oracle
+    g = oracle.Geometry.of(sc)
+    P = oracle.params_array(s)
+    pix = oracle.all_pixels(cams)
+    step = max(1, pix.shape[0] // npix)
+    sample = np.ascontiguousarray(pix[::step][:npix])
+    rng = np.random.default_rng(0)
+    dout = rng.normal(size=(sample.shape[0], 8))
+    t0 = time.perf_counter()
+    oracle.render(g, cams, P, sample, prec=32)
+    t1 = time.perf_counter()
+    oracle.backward(g, cams, P, sample, dout, prec=32)
+    t2 = time.perf_counter()
+    secs = t2 - t0
+    return {"value": round(sample.shape[0] / secs / 1e6, 6), "unit": "Mpixels/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{sample.shape[0]} pixels (every {step}th of the 4x512x512 views), float32 forward "
+                      f"({t1 - t0:.2f} s) + backward ({t2 - t1:.2f} s), per-pixel loop over every kept tet"}
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,15 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
 int render_read_status(const void* workspace, render_status* status, void* stream);
 
 /*
+ * For callers that do not want a synchronisation after every forward: copy
+ * the first RENDER_STATUS_BYTES bytes of the workspace to host memory
+ * asynchronously (e.g. into pinned memory on the same stream), wait for that
+ * copy when convenient, and decode it here.  Pure host computation.
+ */
+#define RENDER_STATUS_BYTES 256
+int render_decode_status(const void* header_copy, render_status* status);
+
+/*
  * Device pointers into the workspace for inspection by tests (valid after a
  * render_forward on that workspace; pure host computation):
  *   tile_keys[E]        uint32 global tile id of each sorted entry
@@ -179,6 +188,33 @@ typedef struct {
 int render_debug_pointers(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
                           const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
                           const void* workspace, render_debug_view* out);
+
+/*
+ * Stage timing.  render_profile(1) resets the totals and, from then on,
+ * brackets every pipeline stage of render_forward / render_backward with a
+ * pair of HIP events recorded on the call's stream (the stream the stage's
+ * kernels run on); render_profile(0) stops.  render_profile_read waits for
+ * the recorded events and returns, per stage, the summed milliseconds and the
+ * number of timed launches.  Not for use under stream capture.  Not thread
+ * safe: profile from one host thread.
+ */
+enum {
+  RENDER_STAGE_UPLOAD = 0,      /* descriptor upload (and header reset) */
+  RENDER_STAGE_PREFILTER = 1,   /* alpha_max pre-filter, compaction, normals */
+  RENDER_STAGE_PROJECT = 2,     /* per-view projection and tile counts */
+  RENDER_STAGE_DEPTH_SORT = 3,  /* radix sort of records by depth */
+  RENDER_STAGE_SCAN = 4,        /* scan of tile counts */
+  RENDER_STAGE_EMIT = 5,        /* tile-duplicated keys */
+  RENDER_STAGE_TILE_SORT = 6,   /* radix sort of entries by tile */
+  RENDER_STAGE_RANGES = 7,      /* tile ranges and entry records */
+  RENDER_STAGE_COMPOSITE = 8,   /* forward compositing */
+  RENDER_STAGE_ZERO_GRADS = 9,  /* gradient buffer clear */
+  RENDER_STAGE_COMPOSITE_BWD = 10, /* reverse-order compositing backward */
+  RENDER_STAGE_VERTEX_BWD = 11, /* per-record chain to vertices */
+  RENDER_NSTAGES = 12
+};
+int render_profile(int enable);
+int render_profile_read(double* ms /* [RENDER_NSTAGES] */, int64_t* counts /* [RENDER_NSTAGES] */);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* render_last_error(void);

@@ -54,7 +54,12 @@ class RenderError(RuntimeError):
 _lib = None
 
 EXPORTS = ("render_workspace_size", "render_forward", "render_backward", "render_read_status",
-           "render_debug_pointers", "render_last_error")
+           "render_debug_pointers", "render_last_error", "render_profile", "render_profile_read",
+           "render_decode_status")
+STATUS_BYTES = 256
+
+STAGES = ("upload", "prefilter", "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "composite",
+          "zero_grads", "composite_bwd", "vertex_bwd")
 
 
 def lib():
@@ -72,6 +77,9 @@ def lib():
         L.render_read_status.argtypes = [P, P, P]
         L.render_debug_pointers.argtypes = [P, I, P, I, P, I64, I64, P, P]
         L.render_last_error.restype = C.c_char_p
+        L.render_profile.argtypes = [I]
+        L.render_profile_read.argtypes = [P, P]
+        L.render_decode_status.argtypes = [P, P]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -82,3 +90,15 @@ def check(rc: int):
     if rc != RENDER_OK:
         raise RenderError(rc, lib().render_last_error().decode())
     return rc
+
+
+def profile(enable: bool):
+    check(lib().render_profile(1 if enable else 0))
+
+
+def profile_read() -> dict:
+    """{stage: (total_ms, launches)} accumulated since profile(True)."""
+    ms = (C.c_double * len(STAGES))()
+    cnt = (C.c_int64 * len(STAGES))()
+    check(lib().render_profile_read(ms, cnt))
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}

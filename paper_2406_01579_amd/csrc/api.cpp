@@ -15,6 +15,26 @@ namespace {
 
 thread_local std::string g_err;
 
+// Optional per-stage timing with HIP events recorded on the caller's stream.
+struct StageEvent {
+  int stage;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<StageEvent> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[RENDER_NSTAGES] = {};
+  int64_t count[RENDER_NSTAGES] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler g_prof;
+
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -203,6 +223,22 @@ int prepare(const render_scene* scenes, int ns, const render_view* views, int nv
     if (e_ != hipSuccess) return hip_fail(e_, name); \
   } while (0)
 
+// run one pipeline stage, bracketed by events when profiling is on
+#define TS_STAGE(stage, call, name)                                   \
+  do {                                                                \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                          \
+    if (g_prof.on) {                                                  \
+      ea_ = g_prof.get();                                             \
+      eb_ = g_prof.get();                                             \
+      if (ea_) hipEventRecord(ea_, st);                               \
+    }                                                                 \
+    TS_TRY(call, name);                                               \
+    if (ea_ && eb_) {                                                 \
+      hipEventRecord(eb_, st);                                        \
+      g_prof.pending.push_back(StageEvent{stage, ea_, eb_});          \
+    }                                                                 \
+  } while (0)
+
 }  // namespace
 }  // namespace ts
 
@@ -237,15 +273,16 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
   std::vector<DevScene> hs;
   std::vector<DevView> hv;
   fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv);
-  TS_TRY(launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, true, st), "upload descriptors");
-  TS_TRY(launch_prefilter(workspace, L, *params, st), "pre-filter");
-  TS_TRY(launch_project(workspace, L, *params, st), "project");
-  TS_TRY(launch_sort_records(workspace, L, st), "depth sort");
-  TS_TRY(launch_count_scan(workspace, L, st), "count scan");
-  TS_TRY(launch_emit(workspace, L, *params, st), "emit");
-  TS_TRY(launch_sort_entries(workspace, L, st), "tile sort");
-  TS_TRY(launch_finalize(workspace, L, st), "tile ranges");
-  TS_TRY(launch_composite(workspace, L, *params, st), "composite");
+  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, true, st),
+           "upload descriptors");
+  TS_STAGE(RENDER_STAGE_PREFILTER, launch_prefilter(workspace, L, *params, st), "pre-filter");
+  TS_STAGE(RENDER_STAGE_PROJECT, launch_project(workspace, L, *params, st), "project");
+  TS_STAGE(RENDER_STAGE_DEPTH_SORT, launch_sort_records(workspace, L, st), "depth sort");
+  TS_STAGE(RENDER_STAGE_SCAN, launch_count_scan(workspace, L, st), "count scan");
+  TS_STAGE(RENDER_STAGE_EMIT, launch_emit(workspace, L, *params, st), "emit");
+  TS_STAGE(RENDER_STAGE_TILE_SORT, launch_sort_entries(workspace, L, st), "tile sort");
+  TS_STAGE(RENDER_STAGE_RANGES, launch_finalize(workspace, L, st), "tile ranges");
+  TS_STAGE(RENDER_STAGE_COMPOSITE, launch_composite(workspace, L, *params, st), "composite");
   return RENDER_OK;
 }
 
@@ -272,10 +309,26 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
     hs[s].dcolors = grads[s].dcolors;
   }
   for (int v = 0; v < n_views; ++v) hv[v].dout = dL_dout[v];
-  TS_TRY(launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, false, st), "upload descriptors");
-  TS_TRY(launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
-  TS_TRY(launch_composite_backward(workspace, L, *params, st), "composite backward");
-  TS_TRY(launch_vertex_backward(workspace, L, *params, st), "vertex backward");
+  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, false, st),
+           "upload descriptors");
+  TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
+  TS_STAGE(RENDER_STAGE_COMPOSITE_BWD, launch_composite_backward(workspace, L, *params, st), "composite backward");
+  TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
+  return RENDER_OK;
+}
+
+int render_decode_status(const void* header_copy, render_status* status) {
+  if (!header_copy || !status) return fail(RENDER_EINVAL, "null header copy or status");
+  DevHeader h;
+  std::memcpy(&h, header_copy, sizeof h);
+  status->entries = h.entries_total;
+  status->kept = h.kept_total;
+  status->records = h.records_total;
+  status->overflow = (int32_t)h.overflow;
+  status->invalid_index = (int32_t)h.invalid_index;
+  status->entry_capacity = h.entry_capacity;
+  status->kept_capacity = h.kept_capacity;
+  status->entries_needed = (int64_t)h.entries_needed;
   return RENDER_OK;
 }
 
@@ -321,6 +374,36 @@ int render_debug_pointers(const render_scene* scenes, int n_scenes, const render
   out->t_last = at<const float>(ws, L.o_tlast);
   out->total_tiles = L.total_tiles;
   out->total_pixels = L.total_pixels;
+  return RENDER_OK;
+}
+
+int render_profile(int enable) {
+  // drop pending events and totals
+  for (auto& p : g_prof.pending) {
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.clear();
+  for (int i = 0; i < RENDER_NSTAGES; ++i) { g_prof.ms[i] = 0.0; g_prof.count[i] = 0; }
+  g_prof.on = enable != 0;
+  return RENDER_OK;
+}
+
+int render_profile_read(double* ms, int64_t* counts) {
+  if (!ms || !counts) return fail(RENDER_EINVAL, "null output");
+  for (auto& p : g_prof.pending) {
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e != hipSuccess) return hip_fail(e, "event synchronize");
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, p.a, p.b);
+    if (e != hipSuccess) return hip_fail(e, "event elapsed time");
+    g_prof.ms[p.stage] += t;
+    g_prof.count[p.stage] += 1;
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.clear();
+  for (int i = 0; i < RENDER_NSTAGES; ++i) { ms[i] = g_prof.ms[i]; counts[i] = g_prof.count[i]; }
   return RENDER_OK;
 }
 

@@ -92,6 +92,10 @@ def make_views(cams: np.ndarray, view_scene, outs) -> C.Array:
     return arr
 
 
+class CapacityError(RuntimeError):
+    pass
+
+
 @dataclass
 class Plan:
     """One forward's workspace and the arguments its backward must repeat."""
@@ -105,11 +109,21 @@ class Plan:
     outs: list
     status: _lib.render_status | None = None
     keep: list = field(default_factory=list)  # tensors the pointers refer to
+    header_copy: torch.Tensor | None = None    # pinned copy of the status header (lazy check)
+    header_event: object = None
+    sig: tuple = ()
 
 
 class Renderer:
     """Holds parameters and capacity estimates; every forward gets its own
-    workspace tensor, so several forwards may await their backward."""
+    workspace tensor, so several forwards may await their backward.
+
+    check="sync": every forward waits for its status (exact re-planning on a
+    capacity overflow, the forward is re-run).  check="lazy": the status is
+    copied to pinned memory without waiting and verified before the backward
+    and at the next forward of the same shape; an overflow there raises
+    CapacityError (never a silent wrong result), and the capacities are
+    enlarged for later calls."""
 
     def __init__(self, params: Params | None = None, device="cuda", check: str = "sync"):
         self.params = params or Params()
@@ -153,7 +167,14 @@ class Renderer:
             check(_lib.lib().render_forward(C.byref(scene_c), len(scenes), C.byref(view_c), nv, C.byref(params_c),
                                             kept_cap, entry_cap, ws.data_ptr(), nbytes, st))
             plan = Plan(scenes, scene_c, view_c, params_c, kept_cap, entry_cap, ws, outs)
-            if self.check != "sync":
+            if self.check != "sync" and sig in self._caps:
+                self._verify_pending()
+                plan.header_copy = torch.empty(_lib.STATUS_BYTES, dtype=torch.uint8, pin_memory=True)
+                plan.header_copy.copy_(ws[:_lib.STATUS_BYTES], non_blocking=True)
+                plan.header_event = torch.cuda.Event()
+                plan.header_event.record()
+                plan.sig = sig
+                self._pending = plan
                 return plan
             stt = self.read_status(plan, st)
             if stt.invalid_index:
@@ -175,6 +196,29 @@ class Renderer:
                 entry_cap = max(entry_cap, 2 * entry_cap)
         raise RuntimeError("could not size the workspace")
 
+    def _verify(self, plan: Plan):
+        if plan.header_copy is None:
+            return
+        plan.header_event.synchronize()
+        s = _lib.render_status()
+        check(_lib.lib().render_decode_status(plan.header_copy.data_ptr(), C.byref(s)))
+        plan.status = s
+        plan.header_copy = None
+        if s.overflow:
+            k, e = self._caps.get(plan.sig, (0, 0))
+            self._caps[plan.sig] = (int(s.kept * 1.25) + 1024 if s.overflow & 1 else k,
+                                    int(s.entries_needed * 1.3) + 4096 if s.overflow & 2 else e)
+            raise CapacityError("workspace capacity exceeded in a forward pass; its outputs are invalid "
+                                "(capacities enlarged for the next call)")
+        if s.invalid_index:
+            raise ValueError("a tet has a vertex index outside [0, V)")
+
+    def _verify_pending(self):
+        p = getattr(self, "_pending", None)
+        if p is not None:
+            self._pending = None
+            self._verify(p)
+
     def read_status(self, plan: Plan, stream=None) -> _lib.render_status:
         st = torch.cuda.current_stream(self.device).cuda_stream if stream is None else stream
         s = _lib.render_status()
@@ -184,6 +228,10 @@ class Renderer:
 
     # -- backward ---------------------------------------------------------------
     def backward(self, plan: Plan, douts, stream=None):
+        if plan.header_copy is not None:
+            if getattr(self, "_pending", None) is plan:
+                self._pending = None
+            self._verify(plan)
         st = torch.cuda.current_stream(self.device).cuda_stream if stream is None else stream
         douts = [d.float().contiguous() for d in douts]
         dptr = (C.c_void_p * len(douts))(*[d.data_ptr() for d in douts])

@@ -1,0 +1,123 @@
+"""The autograd Function against central finite differences of the float64
+oracle (64 sampled parameters, training-shaped workload) and against the
+oracle's own gradient (tiny workload)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import check_gradient, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _autograd(scene, cams, P, weights, s):
+    import torch
+    from paper_2406_01579_amd import Renderer, TetSplatFunction
+    dev = "cuda"
+    v = torch.tensor(scene.verts, device=dev, requires_grad=True)
+    f = torch.tensor(scene.sdf, device=dev, requires_grad=True)
+    c = torch.tensor(scene.colors, device=dev, requires_grad=True)
+    t = torch.tensor(scene.tets, device=dev)
+    out = TetSplatFunction.apply(v, f, c, t, cams, s, Renderer(P))
+    loss = (out * torch.as_tensor(weights, device=dev)).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return out.detach().cpu().numpy(), v.grad.cpu().numpy(), f.grad.cpu().numpy(), c.grad.cpu().numpy()
+
+
+def test_autograd_matches_oracle_gradient_tiny():
+    from paper_2406_01579_amd import Params
+    w = synth.tiny(s=20.0, bg=(0.2, 0.2, 0.2))
+    sc = w.scenes[0]
+    P = Params()
+    wts = np.random.default_rng(1).normal(size=(1, 8, 64, 64)).astype(np.float32)
+    _, dv, ds, dc = _autograd(sc, w.cams, P, wts, 20.0)
+    pix = oracle.all_pixels(w.cams)
+    g = oracle.Geometry.of(sc)
+    d = wts[0].reshape(8, -1).T.astype(np.float64)
+    ref32 = oracle.backward(g, w.cams, oracle_params(P, 20.0), pix, d, prec=32)
+    ref64 = oracle.backward(g, w.cams, oracle_params(P, 20.0), pix, d, prec=64)
+    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
+        check_gradient(name, got, r32, r64, "autograd tiny")
+
+
+def test_autograd_central_differences_training():
+    """64 parameters (22 SDF, 21 colour, 21 position) of vertices of visible
+    kept tets; loss = sum(w * out) over all pixels; the finite difference is
+    taken on the float64 oracle over the pixels the perturbed vertex can reach
+    (the pixel rectangles of its incident kept tets)."""
+    from paper_2406_01579_amd import Params
+    s = 320.0
+    w = synth.training(s=s)
+    sc = w.scenes[0]
+    P = Params.exact()
+    rng = np.random.default_rng(11)
+    nv, H, W = w.cams.shape[0], 512, 512
+    wts = rng.normal(size=(nv, 8, H, W)).astype(np.float32)
+    out, dv, ds, dc = _autograd(sc, w.cams, P, wts, s)
+    g = oracle.Geometry.of(sc)
+    op = oracle_params(P, s)
+    b = oracle.binning(g, w.cams, op, want_rect=True)
+    rect = b["rect"]                                    # [nv, K, 4], -1 if dropped or culled
+    keep, *_ = oracle.prefilter(g, op)
+    # vertices of kept tets that cover opaque-ish pixels in view 0
+    cand_tets = np.nonzero(keep & (rect[0, :, 0] >= 0))[0]
+    cx = (rect[0, cand_tets, 0] + rect[0, cand_tets, 1]) // 2
+    cy = (rect[0, cand_tets, 2] + rect[0, cand_tets, 3]) // 2
+    vis = cand_tets[out[0, 3, cy, cx] > 0.3]
+    verts = np.unique(sc.tets[rng.choice(vis, 200, replace=False)].ravel())
+    verts = rng.choice(verts, 64, replace=False)
+    # vertex -> incident tets
+    inc = {int(x): [] for x in verts}
+    hit = np.isin(sc.tets, verts)
+    for k in np.nonzero(hit.any(1))[0]:
+        for x in sc.tets[k]:
+            if int(x) in inc:
+                inc[int(x)].append(k)
+    kinds = ["sdf"] * 22 + ["color"] * 21 + ["pos"] * 21
+    n_ok, worst = 0, 0.0
+    for q, (x, kind) in enumerate(zip(verts, kinds)):
+        x = int(x)
+        pix = []
+        for v in range(nv):
+            for k in inc[x]:
+                i0, i1, j0, j1 = rect[v, k]
+                if i0 < 0:
+                    continue
+                jj, ii = np.meshgrid(np.arange(max(0, j0 - 1), min(H, j1 + 2)),
+                                     np.arange(max(0, i0 - 1), min(W, i1 + 2)), indexing="ij")
+                pix.append(np.stack([np.full(ii.size, v), ii.ravel(), jj.ravel()], 1))
+        if not pix:
+            continue
+        pix = np.unique(np.concatenate(pix, 0), axis=0).astype(np.int32)
+        wsel = np.stack([wts[v, :, j, i] for (v, i, j) in pix], 0).astype(np.float64)
+        comp = q % 3
+
+        def loss(delta):
+            gg = oracle.Geometry(g.verts.copy(), g.tets, g.sdf.copy(), g.colors.copy())
+            if kind == "sdf":
+                gg.sdf[x] += delta
+            elif kind == "color":
+                gg.colors[x, comp] += delta
+            else:
+                gg.verts[x, comp] += delta
+            return float((oracle.render(gg, w.cams, op, pix, prec=64) * wsel).sum())
+
+        h = 1e-3 if kind == "color" else 1e-6
+        fd = (loss(h) - loss(-h)) / (2 * h)
+        ana = {"sdf": ds[x], "color": dc[x, comp], "pos": dv[x, comp]}[kind]
+        err = abs(ana - fd) / (abs(fd) + 1e-2)
+        worst = max(worst, err)
+        print(f"param {q} {kind} v={x}: autograd {ana:+.6e} fd {fd:+.6e} rel {err:.2e}")
+        assert err <= 2e-3, (q, kind, x, ana, fd)
+        n_ok += 1
+    assert n_ok >= 60
+    print(f"64-parameter FD check: worst rel {worst:.2e}")

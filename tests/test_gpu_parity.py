@@ -1,0 +1,338 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (stated by the build's contract): tile ids, per-tile ranges and
+sort order bit-exact; images within 1e-5 max-abs and gradients within 1e-4
+relative (|g-r| / (|r| + 1e-3 max|r|)) of the float32 oracle.  The error
+against the float64 oracle is printed per output.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import (IMG_TOL, check_gradient, compare_images, gpu_forward, gpu_tiling,
+                               oracle_params)
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _params(mode, tile=(16, 16), **kw):
+    from paper_2406_01579_amd import Params
+    base = Params.exact if mode == "exact" else Params
+    return base(tile_w=tile[0], tile_h=tile[1], **kw)
+
+
+# ---------------------------------------------------------------------------
+# tiny grid: full images, full tiling, full gradients
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("s", [20.0, 100.0])
+@pytest.mark.parametrize("mode", ["exact", "default"])
+def test_tiny_images(mode, s):
+    w = synth.tiny(s=s, bg=(0.1, 0.2, 0.3))
+    sc = w.scenes[0]
+    P = _params(mode)
+    _, _, imgs = gpu_forward(sc, w.cams, P)
+    g = oracle.Geometry.of(sc)
+    op = oracle_params(P, s)
+    err32, n_ex, n = compare_images(imgs, g, w.cams, op, s)
+    err64 = np.abs(imgs[0] - oracle.render_images(g, w.cams, op, prec=64)[0]).reshape(8, -1).max(1)
+    print(f"tiny {mode} s={s}: max-abs vs f32 {err32:.3e} (excluded {n_ex}/{n}); vs f64 per channel {err64}")
+    assert err32 <= IMG_TOL
+    assert n_ex <= max(1, int(1e-4 * n))
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_tiny_tiling_bit_exact(tile):
+    s = 20.0
+    w = synth.tiny(s=s)
+    sc = w.scenes[0]
+    P = _params("default", tile)
+    r, plan, _ = gpu_forward(sc, w.cams, P)
+    d, tets = gpu_tiling(r, plan)
+    g = oracle.Geometry.of(sc)
+    op = oracle_params(P, s)
+    keep, *_ = oracle.prefilter(g, op)
+    assert np.array_equal(np.sort(d["kept_tet"]), np.nonzero(keep)[0])
+    assert np.all(np.diff(d["kept_tet"]) > 0)  # compaction keeps ascending tet order
+    ref = oracle.binning(g, w.cams, op)
+    assert d["entries"] == ref["E"]
+    assert np.array_equal(d["tile_keys"], ref["tile"].astype(np.uint32))
+    assert np.array_equal(tets, ref["tet"])
+    assert np.array_equal(d["ranges"].astype(np.int64), ref["ranges"].astype(np.int64))
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_tile_shape_does_not_change_image(tile):
+    """Per-pixel blend order and arithmetic do not depend on the tiling."""
+    w = synth.tiny(s=100.0, bg=(0.3, 0.3, 0.3))
+    _, _, a = gpu_forward(w.scenes[0], w.cams, _params("default", (16, 16)))
+    _, _, b = gpu_forward(w.scenes[0], w.cams, _params("default", tile))
+    assert np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("recompute", [False, True])
+@pytest.mark.parametrize("s", [20.0, 100.0])
+@pytest.mark.parametrize("mode", ["exact", "default"])
+def test_tiny_gradients(mode, s, recompute):
+    import torch
+    w = synth.tiny(s=s, bg=(0.3, 0.1, 0.2))
+    sc = w.scenes[0]
+    P = _params(mode, recompute_state=recompute)
+    r, plan, _ = gpu_forward(sc, w.cams, P)
+    rng = np.random.default_rng(5)
+    dout = rng.normal(size=(8, 64, 64)).astype(np.float32)
+    (dv, ds, dc), = r.backward(plan, [torch.from_numpy(dout).cuda()])
+    torch.cuda.synchronize()
+    g = oracle.Geometry.of(sc)
+    op = oracle_params(P, s)
+    pix = oracle.all_pixels(w.cams)
+    dflat = dout.reshape(8, -1).T.copy()
+    ref32 = oracle.backward(g, w.cams, op, pix, dflat, prec=32)
+    ref64 = oracle.backward(g, w.cams, op, pix, dflat, prec=64)
+    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
+        check_gradient(name, got.cpu().numpy(), r32, r64, f"tiny {mode} s={s} recompute={recompute}")
+
+
+def test_recompute_state_matches_stored_state():
+    import torch
+    w = synth.tiny(s=100.0)
+    sc = w.scenes[0]
+    dout = torch.from_numpy(np.random.default_rng(6).normal(size=(8, 64, 64)).astype(np.float32)).cuda()
+    res = []
+    for rc in (False, True):
+        r, plan, _ = gpu_forward(sc, w.cams, _params("default", recompute_state=rc))
+        res.append([t.cpu().numpy() for t in r.backward(plan, [dout])[0]])
+    for a, b in zip(*res):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * np.abs(b).max())
+
+
+# ---------------------------------------------------------------------------
+# batches of views and scenes
+# ---------------------------------------------------------------------------
+def test_views_in_one_launch_equal_views_alone():
+    w = synth.training(s=320.0, R=16, size=96, views=3)
+    sc = w.scenes[0]
+    P = _params("default")
+    _, _, together = gpu_forward(sc, w.cams, P)
+    for v in range(3):
+        _, _, alone = gpu_forward(sc, w.cams[v:v + 1], P)
+        assert np.array_equal(together[v], alone[0]), v
+
+
+def test_scenes_of_uneven_size_in_one_launch():
+    import torch
+    from paper_2406_01579_amd import Renderer, SceneT
+    rng = np.random.default_rng(9)
+    scenes = [synth.scene_blob(R, rng, 320.0) for R in (12, 20, 8)]
+    cams = synth.random_orbit_cameras(rng, 5, [64, 48, 80, 64, 40])
+    vs = np.array([0, 1, 2, 1, 0], np.int32)
+    P = _params("default")
+    r = Renderer(P)
+    sts = [SceneT.from_numpy(s) for s in scenes]
+    plan = r.forward(sts, cams, vs)
+    torch.cuda.synchronize()
+    for v in range(5):
+        p1 = Renderer(P).forward([sts[vs[v]]], cams[v:v + 1])
+        torch.cuda.synchronize()
+        assert np.array_equal(plan.outs[v].cpu().numpy(), p1.outs[0].cpu().numpy()), v
+        g = oracle.Geometry.of(scenes[vs[v]])
+        err, n_ex, n = compare_images([plan.outs[v].cpu().numpy()], g, cams[v:v + 1],
+                                      oracle_params(P, 320.0), 320.0)
+        assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n))
+    # gradients of a multi-scene batch: each scene against the oracle
+    douts = [torch.randn(o.shape, device="cuda") for o in plan.outs]
+    grads = r.backward(plan, douts)
+    torch.cuda.synchronize()
+    for si, sc in enumerate(scenes):
+        sel = [v for v in range(5) if vs[v] == si]
+        pix = oracle.all_pixels(cams[sel])
+        dflat = np.concatenate([douts[v].cpu().numpy().reshape(8, -1).T for v in sel], 0)
+        gg = oracle.Geometry.of(sc)
+        ref32 = oracle.backward(gg, cams[sel], oracle_params(P, 320.0), pix, dflat, prec=32)
+        ref64 = oracle.backward(gg, cams[sel], oracle_params(P, 320.0), pix, dflat, prec=64)
+        for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads[si], ref32, ref64):
+            check_gradient(name, got.cpu().numpy(), r32, r64, f"multi-scene scene {si}")
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("size", [(1, 1), (50, 37), (8, 8), (130, 9)])
+def test_ragged_image_sizes(size):
+    s = 100.0
+    w = synth.tiny(s=s, bg=(0.2, 0.5, 0.1))
+    Wd, Hd = size
+    cam = synth.orbit_camera(0.7, 0.35, 2.5, 50.0, Wd, Hd, bg=(0.2, 0.5, 0.1))[None]
+    cam[0, 17] = Hd / 2.0
+    for tile in [(16, 16), (32, 8), (8, 8)]:
+        P = _params("default", tile)
+        _, _, imgs = gpu_forward(w.scenes[0], cam, P)
+        err, n_ex, n = compare_images(imgs, oracle.Geometry.of(w.scenes[0]), cam, oracle_params(P, s), s)
+        assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n)), (size, tile)
+
+
+def test_empty_scene_and_culled_views():
+    import torch
+    w = synth.tiny(s=20.0, bg=(0.25, 0.5, 0.75))
+    sc = w.scenes[0]
+    empty = synth.Scene(sc.verts, sc.tets, np.full_like(sc.sdf, 2.0), sc.colors, 20.0)
+    # camera facing away from the grid: everything culled by the near plane / screen
+    away = synth.orbit_camera(0.7, 0.35, 2.5, 50.0, 64, 64, bg=(0.25, 0.5, 0.75))
+    R = away[2:11].reshape(3, 3).astype(np.float64)
+    C = -R.T @ away[11:14].astype(np.float64)      # camera centre
+    R[2] *= -1
+    R[0] *= -1
+    away[2:11] = R.ravel()
+    away[11:14] = -R @ C
+    for scene, cams in ((empty, w.cams), (sc, away[None])):
+        r, plan, imgs = gpu_forward(scene, cams, _params("default"))
+        bg = np.array([0.25, 0.5, 0.75], np.float32)
+        assert np.array_equal(imgs[0][0:3], np.broadcast_to(bg[:, None, None], (3, 64, 64)))
+        assert np.all(imgs[0][3:] == 0)
+        (dv, ds, dc), = r.backward(plan, [torch.ones(8, 64, 64, device="cuda")])
+        assert float(dv.abs().max()) == 0 and float(ds.abs().max()) == 0 and float(dc.abs().max()) == 0
+    # a scene with no tets at all
+    none = synth.Scene(sc.verts, np.zeros((0, 4), np.int32), sc.sdf, sc.colors, 20.0)
+    _, _, imgs = gpu_forward(none, w.cams, _params("default"))
+    assert np.all(imgs[0][3:] == 0)
+
+
+def test_out_of_range_indices_are_dropped_and_reported():
+    import torch
+    from paper_2406_01579_amd import Renderer, SceneT
+    w = synth.tiny(s=20.0)
+    sc = w.scenes[0]
+    bad = sc.tets.copy()
+    bad[5, 2] = sc.V + 7
+    bad[9, 0] = -3
+    r = Renderer(_params("default"))
+    with pytest.raises(ValueError, match="outside"):
+        r.forward([SceneT.from_numpy(synth.Scene(sc.verts, bad, sc.sdf, sc.colors, 20.0))], w.cams)
+    torch.cuda.synchronize()
+
+
+def test_capacity_overflow_is_detected_and_replanned():
+    import torch
+    from paper_2406_01579_amd import Renderer, SceneT
+    from paper_2406_01579_amd.frontend import CapacityError
+    w = synth.tiny(s=20.0)
+    sc = w.scenes[0]
+    P = _params("default")
+    st = SceneT.from_numpy(sc)
+    _, _, ref = gpu_forward(sc, w.cams, P)
+    r = Renderer(P)
+    sig = r._signature([st], w.cams, np.zeros(1, np.int32))
+    r._caps[sig] = (2000, 10)       # far too few entries: the forward overflows, sync mode re-plans
+    plan = r.forward([st], w.cams)
+    assert plan.status.overflow == 0 and plan.entry_cap >= plan.status.entries
+    assert np.array_equal(plan.outs[0].cpu().numpy(), ref[0])
+    # lazy mode: the overflow surfaces before the backward, never silently
+    r2 = Renderer(P, check="lazy")
+    r2._caps[sig] = (2000, 10)
+    plan2 = r2.forward([st], w.cams)
+    with pytest.raises(CapacityError):
+        r2.backward(plan2, [torch.zeros(8, 64, 64, device="cuda")])
+    plan3 = r2.forward([st], w.cams)          # enlarged capacities now suffice
+    r2.backward(plan3, [torch.zeros(8, 64, 64, device="cuda")])
+    assert np.array_equal(plan3.outs[0].cpu().numpy(), ref[0])
+
+
+# ---------------------------------------------------------------------------
+# training-shaped workload at full size (64^3 grid, 4 views 512^2, s = 320):
+# tiling in full, sampled pixels, gradients of a sparse upstream gradient
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def training():
+    w = synth.training(s=320.0)
+    return w, oracle.Geometry.of(w.scenes[0])
+
+
+def test_training_tiling_bit_exact(training):
+    w, g = training
+    P = _params("default")
+    r, plan, _ = gpu_forward(w.scenes[0], w.cams, P)
+    d, tets = gpu_tiling(r, plan)
+    op = oracle_params(P, 320.0)
+    keep, amax, *_ = oracle.prefilter(g, op)
+    gk = np.zeros(g.K, bool)
+    gk[d["kept_tet"]] = True
+    diff = np.nonzero(gk != keep)[0]
+    # a kept-set difference may only come from exp/expm1 rounding at T_f
+    tf = np.float32(1 / 255)
+    assert np.all(np.abs(amax[diff] - tf) <= 4 * np.spacing(tf)), diff
+    ref = oracle.binning(g, w.cams, op)
+    if diff.size == 0:
+        assert d["entries"] == ref["E"]
+        assert np.array_equal(d["tile_keys"], ref["tile"].astype(np.uint32))
+        assert np.array_equal(tets, ref["tet"])
+        assert np.array_equal(d["ranges"].astype(np.int64), ref["ranges"].astype(np.int64))
+    else:
+        m_gpu = ~np.isin(tets, diff)
+        m_ref = ~np.isin(ref["tet"], diff)
+        assert np.array_equal(d["tile_keys"][m_gpu], ref["tile"][m_ref].astype(np.uint32))
+        assert np.array_equal(tets[m_gpu], ref["tet"][m_ref])
+    print(f"training tiling: E={d['entries']}, kept={d['kept']}, kept-set differences {diff.size}")
+
+
+def _sample_pixels(w, n, seed):
+    rng = np.random.default_rng(seed)
+    nv = w.cams.shape[0]
+    W, H = int(w.cams[0, 0]), int(w.cams[0, 1])
+    pix = np.stack([rng.integers(0, nv, n), rng.integers(0, W, n), rng.integers(0, H, n)], 1)
+    return np.ascontiguousarray(pix, dtype=np.int32)
+
+
+@pytest.mark.parametrize("mode", ["exact", "default"])
+def test_training_sampled_pixels(training, mode):
+    w, g = training
+    P = _params(mode)
+    _, _, imgs = gpu_forward(w.scenes[0], w.cams, P)
+    pix = _sample_pixels(w, 3000, 1)
+    # bias the sample toward the object: half of it from covered pixels
+    cov = np.argwhere(np.stack(imgs)[:, 3] > 0.01)
+    pick = cov[np.random.default_rng(2).choice(len(cov), 1500, replace=False)]
+    pix = np.concatenate([pix, pick[:, [0, 2, 1]].astype(np.int32)], 0)
+    op = oracle_params(P, 320.0)
+    err, n_ex, n = compare_images(imgs, g, w.cams, op, 320.0, pix=pix)
+    got = np.stack([imgs[v][:, j, i] for (v, i, j) in pix], 0)
+    e64 = np.abs(got - oracle.render(g, w.cams, op, pix, prec=64)).max(0)
+    print(f"training {mode}: sampled max-abs vs f32 {err:.3e} (excluded {n_ex}/{n}); vs f64 per channel {e64}")
+    assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n))
+
+
+def test_training_gradients_of_sparse_upstream(training):
+    """dL/dout nonzero on a pixel sample only: the oracle computes that
+    backward exactly at full size."""
+    import torch
+    w, g = training
+    P = _params("default")
+    r, plan, imgs = gpu_forward(w.scenes[0], w.cams, P)
+    cov = np.argwhere(np.stack(imgs)[:, 3] > 0.01)
+    pick = cov[np.random.default_rng(3).choice(len(cov), 2000, replace=False)]
+    pix = np.ascontiguousarray(pick[:, [0, 2, 1]], dtype=np.int32)
+    rng = np.random.default_rng(4)
+    vals = rng.normal(size=(pix.shape[0], 8)).astype(np.float32)
+    douts = [np.zeros((8, 512, 512), np.float32) for _ in range(4)]
+    for (v, i, j), x in zip(pix, vals):
+        douts[v][:, j, i] += x
+    # merge duplicates the same way for the oracle
+    key = pix[:, 0] * 512 * 512 + pix[:, 2] * 512 + pix[:, 1]
+    uk, first = np.unique(key, return_index=True)
+    upix = pix[first]
+    dflat = np.stack([douts[v][:, j, i] for (v, i, j) in upix], 0).astype(np.float64)
+    grads, = r.backward(plan, [torch.from_numpy(d).cuda() for d in douts])
+    torch.cuda.synchronize()
+    op = oracle_params(P, 320.0)
+    ref32 = oracle.backward(g, w.cams, op, upix, dflat, prec=32)
+    ref64 = oracle.backward(g, w.cams, op, upix, dflat, prec=64)
+    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads, ref32, ref64):
+        check_gradient(name, got.cpu().numpy(), r32, r64, "training sparse-upstream")
