@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--s", type=float, default=320.0)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="8x8")
     ap.add_argument("--check", default="lazy", choices=["sync", "lazy"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-view path")

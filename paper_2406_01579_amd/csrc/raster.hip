@@ -2,8 +2,8 @@
 //
 // One workgroup per screen tile; each 64-lane wave owns an 8x8 block of the
 // tile (one pixel per lane).  The tile's depth-sorted record list is staged
-// through LDS in chunks; every wave skips, with a wave-uniform test, records
-// whose pixel rectangle misses its 8x8 block.
+// through LDS in chunks; with tiles larger than 8x8 every wave skips, with a
+// wave-uniform test, records whose pixel rectangle misses its block.
 //
 // Forward (Eq. 1, Eq. 2, Sec. 3.3): front-to-back blending of colour, depth,
 // normal and opacity with the 3DGS thresholds; stores per pixel the position
@@ -14,9 +14,10 @@
 //   dL/dalpha_i = T_i (s_i - R),   R <- alpha_i s_i + (1 - alpha_i) R,
 // where s_i = g . (c_i, 1, z_i, n_i) and T_i is recovered by
 // T_i = T_{i+1} / (1 - alpha_i) starting from the stored T before the last
-// blended entry (so an entry with alpha = 1 never needs a division).  The
-// per-entry gradient of the record's screen-space parameters is summed over
-// the tile (wave butterfly + LDS) and stored per entry, deterministically.
+// blended entry (so an entry with alpha = 1 never needs a division).  Each
+// lane's gradient of the record's screen-space parameters is summed over the
+// wave with a transposed permlane/DPP reduction and over the waves of the
+// tile in LDS, then stored per entry (deterministic order across tiles).
 #include "ts_device.h"
 
 namespace ts {
@@ -58,7 +59,9 @@ __device__ __forceinline__ void load_chunk(ViewRec* recs, const ViewRec* __restr
   }
 }
 
+template <int TW, int TH>
 __device__ __forceinline__ bool rect_hits_block(const ViewRec& R, int wi0, int wj0) {
+  if (TW == 8 && TH == 8) return true;  // a tile's list only holds records that overlap it
   int i0, i1, j0, j1;
   unpack_rect(R, i0, i1, j0, j1);
   return !(i1 < wi0 || i0 > wi0 + 7 || j1 < wj0 || j0 > wj0 + 7);
@@ -105,10 +108,10 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
     if (__ballot(!done) != 0ull) {
       for (int e = 0; e < n; ++e) {
         const ViewRec& R = recs[e];
-        if (!rect_hits_block(R, c.wi0, c.wj0)) continue;
+        if (!rect_hits_block<TW, TH>(R, c.wi0, c.wj0)) continue;
         if (done || !rect_has_pixel(R, c.i, c.j)) continue;
-        PixHit h;
-        if (!pixel_hit(R, qx, qy, s, h)) continue;
+        PixEval h;
+        if (!pixel_eval(R, qx, qy, s, h)) continue;
         float a = h.alpha;
         if (a < alpha_min) continue;
         a = fminf(a, alpha_clamp);
@@ -152,27 +155,24 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
-// d f(face) / d (record parameters): f = sum N_k w_k f_k / S, S = sum N_k w_k,
-// N = the face's cross products of (vertex - pixel) pairs.
-__device__ __forceinline__ void face_grad(const ViewRec& R, const PixHit& h, const FaceSel& fs, float df, float* g) {
-  const int A = face_vertex(fs.face, 0), B = face_vertex(fs.face, 1), C = face_vertex(fs.face, 2);
-  const int I[3] = {A, B, C};
-  const float invS = 1.0f / fs.S;
+// d f(face F) / d(record parameters) times df, added to g.  F is a
+// compile-time constant, so every index below is static.
+// f = sum N_k w_k f_k / S, S = sum N_k w_k, N the face's cross products.
+template <int F>
+__device__ __forceinline__ void face_grad(const ViewRec& R, const PixEval& h, float df, float (&g)[32]) {
+  constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
+  constexpr int I[3] = {A, B, C};
+  const float invS = rcp(h.S[F]);
+  const float fF = h.f[F];
   float a[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int v = I[k];
     const float wk = R.iz[v];
-    const float diff = R.f[v] - fs.f;
-    g[G_F + v] = fmaf(fs.N[k] * wk * invS, df, g[G_F + v]);          // d/df_k
-    g[G_IZ + v] = fmaf(fs.N[k] * diff * invS, df, g[G_IZ + v]);      // d/dw_k
-    a[k] = wk * diff * invS * df;                                     // d/dN_k
+    const float diff = (R.f[v] - fF) * invS * df;
+    g[G_F + v] = fmaf(h.N[F][k] * wk * invS, df, g[G_F + v]);   // d/df_k
+    g[G_IZ + v] = fmaf(h.N[F][k], diff, g[G_IZ + v]);            // d/dw_k
+    a[k] = wk * diff;                                             // d/dN_k
   }
   const float Ax = h.ax[A], Ay = h.ay[A], Bx = h.ax[B], By = h.ay[B], Cx = h.ax[C], Cy = h.ay[C];
   // N0 = cross(B', C'), N1 = cross(C', A'), N2 = cross(A', B')
@@ -209,6 +209,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   const size_t plane = (size_t)V.W * V.H;
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
+  const unsigned lane = threadIdx.x & 63u;
 
   int last = -1;
   float Tb = 1.0f;
@@ -223,10 +224,10 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
       __syncthreads();
       for (int e = 0; e < n; ++e) {
         const ViewRec& R = recs[e];
-        if (!rect_hits_block(R, c.wi0, c.wj0)) continue;
+        if (!rect_hits_block<TW, TH>(R, c.wi0, c.wj0)) continue;
         if (done || !rect_has_pixel(R, c.i, c.j)) continue;
-        PixHit h;
-        if (!pixel_hit(R, qx, qy, s, h)) continue;
+        PixEval h;
+        if (!pixel_eval(R, qx, qy, s, h)) continue;
         float a = h.alpha;
         if (a < alpha_min) continue;
         a = fminf(a, alpha_clamp);
@@ -240,9 +241,9 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
       __syncthreads();
     }
   } else if (c.inside) {
-    const size_t g = (size_t)V.pix_base + px;
-    last = last_in[g];
-    Tb = tlast_in[g];
+    const size_t gi = (size_t)V.pix_base + px;
+    last = last_in[gi];
+    Tb = tlast_in[gi];
   }
 
   // upstream gradient
@@ -255,38 +256,41 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   int wmax = last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
-  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = wmax;
-  __syncthreads();
-  int tmax = -1;
-  for (int w = 0; w < NW; ++w) tmax = max(tmax, smax[w]);
+  if (NW > 1) {
+    if (lane == 0) smax[threadIdx.x >> 6] = wmax;
+    __syncthreads();
+    for (int w = 0; w < NW; ++w) wmax = max(wmax, smax[w]);
+  }
+  const int tmax = wmax;
   const uint32_t pend = (tmax >= (int)start) ? (uint32_t)tmax + 1u : start;
   if (threadIdx.x == 0) proc_end[c.tile] = pend;
 
   bool first = true;
   float Tnext = 1.0f;
-  for (int64_t cb = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CH) * CH; cb >= (int64_t)start && pend > start;
-       cb -= CH) {
+  for (int64_t cb = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CH) * CH;
+       cb >= (int64_t)start && pend > start; cb -= CH) {
     const uint32_t base = (uint32_t)cb;
     const int n = (int)min((uint32_t)CH, pend - base);
     load_chunk(recs, vrec, srec, base, n, NT);
-    for (int q = threadIdx.x; q < CH * TGRAD_STRIDE; q += NT) (&gacc[0][0])[q] = 0.0f;
+    if (NW > 1)
+      for (int q = threadIdx.x; q < CH * TGRAD_STRIDE; q += NT) (&gacc[0][0])[q] = 0.0f;
     __syncthreads();
     for (int e = n - 1; e >= 0; --e) {
       const ViewRec& R = recs[e];
-      if (!rect_hits_block(R, c.wi0, c.wj0)) continue;
+      if (!rect_hits_block<TW, TH>(R, c.wi0, c.wj0)) continue;
       const int p = (int)(base + e);
-      float g[TGRAD_STRIDE];
+      float g[32];
 #pragma unroll
-      for (int q = 0; q < TGRAD_STRIDE; ++q) g[q] = 0.0f;
+      for (int q = 0; q < 32; ++q) g[q] = 0.0f;
       bool contrib = false;
       if (c.inside && p <= last && rect_has_pixel(R, c.i, c.j)) {
-        PixHit h;
-        if (pixel_hit(R, qx, qy, s, h) && h.alpha >= alpha_min) {
+        PixEval h;
+        if (pixel_eval(R, qx, qy, s, h) && h.alpha >= alpha_min) {
           const float a = fminf(h.alpha, alpha_clamp);
           const bool clamped = h.alpha > alpha_clamp;
           float T;
           if (first) { T = Tb; first = false; }
-          else T = Tnext / (1.0f - a);
+          else T = Tnext * rcp(1.0f - a);
           Tnext = T;
           const float w = T * a;
           const float sdot = gr[0] * R.c[0] + gr[1] * R.c[1] + gr[2] * R.c[2] + gr[3] + gr[4] * R.zt +
@@ -300,28 +304,36 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
           g[G_N + 0] = w * gr[5];
           g[G_N + 1] = w * gr[6];
           g[G_N + 2] = w * gr[7];
-          const float d = h.in.f - h.out.f;
-          if (!clamped && d > 0.0f) {
+          if (!clamped && h.alpha > 0.0f) {
             // alpha = A / B, A = -expm1(-s d), B = 1 + exp(s f_next)
-            const float e1 = expm1f(-(s * d));
-            const float e2 = expf(s * h.out.f);
-            const float B = 1.0f + e2;
-            const float dA = da / B;
-            const float dB = -da * h.alpha / B;
-            const float dd = dA * s * (e1 + 1.0f);
-            const float dfn = dB * s * e2 - dd;
-            face_grad(R, h, h.in, dd, g);
-            face_grad(R, h, h.out, dfn, g);
+            const float invB = rcp(1.0f + h.e2);
+            const float dA = da * invB;
+            const float dB = -da * h.alpha * invB;
+            const float dd = dA * s * (h.e1 + 1.0f);     // d/df_prev
+            const float dfn = dB * s * h.e2 - dd;         // d/df_next
+#pragma unroll
+            for (int F = 0; F < 4; ++F) {
+              const float wF = (h.fe == F ? dd : 0.0f) + (h.fx == F ? dfn : 0.0f);
+              if (wF != 0.0f) {
+                if (F == 0) face_grad<0>(R, h, wF, g);
+                if (F == 1) face_grad<1>(R, h, wF, g);
+                if (F == 2) face_grad<2>(R, h, wF, g);
+                if (F == 3) face_grad<3>(R, h, wF, g);
+              }
+            }
           }
           contrib = true;
         }
       }
-      if (__ballot(contrib) == 0ull) continue;
-#pragma unroll
-      for (int q = 0; q < 23; ++q) g[q] = wave_sum(g[q]);
-      if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int q = 0; q < 23; ++q) atomicAdd(&gacc[e][q], g[q]);
+      if (__ballot(contrib) == 0ull) {
+        if (NW == 1 && lane < TGRAD_STRIDE) gacc[e][lane] = 0.0f;
+        continue;
+      }
+      const float tot = wave_transpose_sum32(g);   // lane L: sum of g[L >> 1]
+      const unsigned q = lane >> 1;
+      if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) {
+        if (NW == 1) gacc[e][q] = tot;
+        else atomicAdd(&gacc[e][q], tot);
       }
     }
     __syncthreads();

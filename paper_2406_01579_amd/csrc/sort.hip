@@ -2,8 +2,9 @@
 // the reduce-then-scan form of Merrill & Grimshaw (2010), the GPU radix sort
 // the paper cites (Sec. 3.3).  Per 8-bit digit pass:
 //   upsweep   - per-block digit histogram (LDS atomics)
-//   spine     - one-block exclusive scan of the digit-major histogram table,
-//               giving every (digit, block) its global output offset
+//   spine     - one block per digit: exclusive scan of that digit's block
+//               counts and the digit total; (digit start + block prefix) is
+//               every (digit, block)'s global output offset
 //   downsweep - per block, in input order, the rank of every key among the
 //               equal digits before it (wave ballots + per-wave LDS counts),
 //               then a scatter to offset + rank.
@@ -16,6 +17,7 @@ namespace ts {
 namespace {
 constexpr int RADIX = 1 << SORT_BITS;
 constexpr int WAVES = SORT_THREADS / 64;
+static_assert(RADIX == SORT_THREADS, "one thread per digit in the spine and downsweep prologue");
 
 __device__ __forceinline__ uint32_t sort_n(const uint32_t* n_dev, int64_t cap) {
   uint32_t n = *n_dev;
@@ -42,40 +44,53 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_up(const uint32_t* __res
   for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) hist[(size_t)d * nb + b] = h[d];
 }
 
-__global__ __launch_bounds__(1024) void k_radix_spine(uint32_t* hist, const uint32_t* n_dev, int64_t cap,
-                                                      int digit_bits) {
-  __shared__ uint32_t part[1024];
+// one block per digit: exclusive scan of that digit's per-block counts (in
+// place) and the digit total
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_spine(uint32_t* hist, uint32_t* totals,
+                                                              const uint32_t* n_dev, int64_t cap) {
+  __shared__ uint32_t part[SORT_THREADS];
   const uint32_t n = sort_n(n_dev, cap);
   const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
-  const uint32_t m = nb << digit_bits;
-  const uint32_t per = (m + 1023) / 1024;
+  const uint32_t d = blockIdx.x;
+  uint32_t* row = hist + (size_t)d * nb;
+  const uint32_t per = (nb + SORT_THREADS - 1) / SORT_THREADS;
   const uint32_t t = threadIdx.x;
-  const uint32_t lo = min(m, t * per), hi = min(m, (t + 1) * per);
+  const uint32_t lo = min(nb, t * per), hi = min(nb, (t + 1) * per);
   uint32_t sum = 0;
-  for (uint32_t i = lo; i < hi; ++i) sum += hist[i];
-  part[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t v = (t >= (uint32_t)o) ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  for (uint32_t i = lo; i < hi; ++i) sum += row[i];
+  // block-wide exclusive scan of the per-thread sums (wave scan + wave totals)
+  const int lane = t & 63, wave = t >> 6;
+  uint32_t x = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  uint32_t run = part[t] - sum;
+  if (lane == 63) part[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+  for (int w = 0; w < WAVES; ++w) {
+    if (w < wave) wbase += part[w];
+    tot += part[w];
+  }
+  uint32_t run = wbase + x - sum;
   for (uint32_t i = lo; i < hi; ++i) {
-    uint32_t c = hist[i];
-    hist[i] = run;
+    uint32_t c = row[i];
+    row[i] = run;
     run += c;
   }
+  if (t == 0) totals[d] = tot;
 }
 
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              const uint32_t* n_dev, int64_t cap, int shift,
-                                                             int digit_bits, const uint32_t* __restrict__ hist) {
+                                                             int digit_bits, const uint32_t* __restrict__ hist,
+                                                             const uint32_t* __restrict__ totals) {
   __shared__ uint32_t base[RADIX];
   __shared__ uint32_t wcnt[WAVES][RADIX];
+  __shared__ uint32_t part[WAVES];
   const uint32_t n = sort_n(n_dev, cap);
   const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
   const uint32_t b = blockIdx.x;
@@ -83,7 +98,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
   const uint32_t mask = (1u << digit_bits) - 1u;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) base[d] = hist[(size_t)d * nb + b];
+  {
+    // digit start = exclusive scan of the digit totals (RADIX == SORT_THREADS)
+    const uint32_t tot = totals[threadIdx.x];
+    uint32_t x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) part[wave] = x;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += part[w];
+    base[threadIdx.x] = wbase + x - tot + hist[(size_t)threadIdx.x * nb + b];
+  }
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const uint32_t i = b * SORT_TILE + it * SORT_THREADS + threadIdx.x;
     const bool valid = i < n;
@@ -126,16 +155,17 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
                             const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
                             hipStream_t st, uint32_t** keys_out, uint32_t** vals_out) {
   const unsigned nb = (unsigned)((cap + SORT_TILE - 1) / SORT_TILE);
-  (void)hist_blocks;
+  // digit totals live after the (digit, block) table
+  uint32_t* totals = hist + (size_t)RADIX * (size_t)hist_blocks;
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
   bool first = true;
   for (int shift = 0; shift < bits; shift += SORT_BITS) {
     const int db = (bits - shift) < SORT_BITS ? (bits - shift) : SORT_BITS;
     if (nb > 0) {
       k_radix_up<<<nb, SORT_THREADS, 0, st>>>(ki, n_dev, cap, shift, db, hist);
-      k_radix_spine<<<1, 1024, 0, st>>>(hist, n_dev, cap, db);
+      k_radix_spine<<<RADIX, SORT_THREADS, 0, st>>>(hist, totals, n_dev, cap);
       k_radix_down<<<nb, SORT_THREADS, 0, st>>>(ki, (first && identity) ? nullptr : vi, ko, vo, n_dev, cap, shift, db,
-                                                  hist);
+                                                  hist, totals);
     }
     first = false;
     uint32_t* t = ki; ki = ko; ko = t;

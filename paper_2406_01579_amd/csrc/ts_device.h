@@ -22,6 +22,8 @@ __device__ __forceinline__ int find_view_by_tile(const DevView* views, int nv, i
   return lo;
 }
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Eq. 1 in the stable form alpha = -expm1(-s d) / (1 + exp(s f_next)),
 // d = f_prev - f_next; zero unless d > 0 (the max(., 0) of Eq. 1).
 __device__ __forceinline__ float alpha_eq1(float fprev, float fnext, float s) {
@@ -30,35 +32,13 @@ __device__ __forceinline__ float alpha_eq1(float fprev, float fnext, float s) {
   return -expm1f(-(s * d)) / (1.0f + expf(s * fnext));
 }
 
-// Coverage and entry/exit of one pixel centre (qx, qy) against one record.
-// The inside test of each projected face uses the sign of the three 2D
-// cross products N_k (rows of the inverse barycentric system times [p;1],
-// App. A.1) against the sign of the face determinant D; a face with D == 0
-// never contains the pixel.  Values along the ray use the perspective-
-// correct barycentrics of App. A.2: with w_k = 1/Z_k,
-//   f = sum N_k w_k f_k / sum N_k w_k,   1/z = sum N_k w_k / D.
-struct FaceSel {
-  int face;        // 0..3
-  float N[3];
-  float S;         // sum N_k w_k
-  float f;         // SDF at the hit point
-};
-
 // face vertex table: (0,1,2) (0,1,3) (0,2,3) (1,2,3)
-__device__ __forceinline__ int face_vertex(int F, int k) {
-  // packed 2 bits per entry
-  const uint32_t tbl = (0u << 0) | (1u << 2) | (2u << 4) |     // face 0
-                       (0u << 6) | (1u << 8) | (3u << 10) |    // face 1
-                       (0u << 12) | (2u << 14) | (3u << 16) |  // face 2
-                       (1u << 18) | (2u << 20) | (3u << 22);   // face 3
-  return (tbl >> (2 * (3 * F + k))) & 3u;
+__host__ __device__ constexpr int face_vertex(int F, int k) {
+  return F == 0 ? (k == 0 ? 0 : k == 1 ? 1 : 2)
+       : F == 1 ? (k == 0 ? 0 : k == 1 ? 1 : 3)
+       : F == 2 ? (k == 0 ? 0 : k == 1 ? 2 : 3)
+                : (k == 0 ? 1 : k == 1 ? 2 : 3);
 }
-
-struct PixHit {
-  FaceSel in, out;
-  float alpha;
-  float ax[4], ay[4];  // projected vertex minus pixel centre
-};
 
 __device__ __forceinline__ bool face_inside(float N0, float N1, float N2, float D) {
   if (D > 0.0f) return N0 >= 0.0f && N1 >= 0.0f && N2 >= 0.0f;
@@ -66,45 +46,76 @@ __device__ __forceinline__ bool face_inside(float N0, float N1, float N2, float 
   return false;
 }
 
-// Returns true if at least two faces contain the pixel centre; fills h.
-__device__ __forceinline__ bool pixel_hit(const ViewRec& r, float qx, float qy, float s, PixHit& h) {
+// One pixel centre against one record.  For a projected face (A,B,C) the
+// rows of the inverse barycentric system times [p;1] (App. A.1) are
+// N = (cross(B',C'), cross(C',A'), cross(A',B')) over D, with X' = X - p;
+// the pixel is inside iff the three N have the sign of D (D == 0: never).
+// The six edge cross products e_ij = cross(P_i - p, P_j - p) give every N
+// exactly (a swapped pair is an exact negation).  Along the ray, with
+// w_k = 1/Z_k (App. A.2):  f = sum N_k w_k f_k / sum N_k w_k,
+// 1/z = sum N_k w_k / D.  Entry = nearest hit face, exit = farthest.
+struct PixEval {
+  float ax[4], ay[4];
+  float N[4][3];
+  float S[4], f[4];
+  int fe, fx;      // entry / exit face
+  float alpha;     // Eq. 1 (unclamped)
+  float e1, e2;    // expm1(-s d), exp(s f_next) (for the derivative)
+};
+
+__device__ __forceinline__ bool pixel_eval(const ViewRec& r, float qx, float qy, float s, PixEval& h) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     h.ax[k] = r.px[k] - qx;
     h.ay[k] = r.py[k] - qy;
   }
-  // e_ij = cross(P_i - q, P_j - q)
   const float e01 = h.ax[0] * h.ay[1] - h.ay[0] * h.ax[1];
   const float e02 = h.ax[0] * h.ay[2] - h.ay[0] * h.ax[2];
   const float e03 = h.ax[0] * h.ay[3] - h.ay[0] * h.ax[3];
   const float e12 = h.ax[1] * h.ay[2] - h.ay[1] * h.ax[2];
   const float e13 = h.ax[1] * h.ay[3] - h.ay[1] * h.ax[3];
   const float e23 = h.ax[2] * h.ay[3] - h.ay[2] * h.ax[3];
-  // (N0, N1, N2) of face (A,B,C) = (cross(B',C'), cross(C',A'), cross(A',B'))
-  float N[4][3] = {{e12, -e02, e01}, {e13, -e03, e01}, {e23, -e03, e02}, {e23, -e13, e12}};
+  h.N[0][0] = e12; h.N[0][1] = -e02; h.N[0][2] = e01;
+  h.N[1][0] = e13; h.N[1][1] = -e03; h.N[1][2] = e01;
+  h.N[2][0] = e23; h.N[2][1] = -e03; h.N[2][2] = e02;
+  h.N[3][0] = e23; h.N[3][1] = -e13; h.N[3][2] = e12;
   int nh = 0;
   float best_in = -INFINITY, best_out = INFINITY;
+  h.fe = 0;
+  h.fx = 0;
 #pragma unroll
   for (int F = 0; F < 4; ++F) {
-    if (!face_inside(N[F][0], N[F][1], N[F][2], r.D[F])) continue;
+    h.S[F] = 1.0f;
+    h.f[F] = 0.0f;
+    if (!face_inside(h.N[F][0], h.N[F][1], h.N[F][2], r.D[F])) continue;
     ++nh;
     const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
-    const float qa = N[F][0] * r.iz[A], qb = N[F][1] * r.iz[B], qc = N[F][2] * r.iz[C];
+    const float qa = h.N[F][0] * r.iz[A], qb = h.N[F][1] * r.iz[B], qc = h.N[F][2] * r.iz[C];
     const float S = (qa + qb) + qc;
     const float num = fmaf(qa, r.f[A], fmaf(qb, r.f[B], qc * r.f[C]));
-    const float f = num / S;
-    const float invz = S / r.D[F];  // 1 / depth at the hit: larger is nearer
-    if (invz > best_in) {
-      best_in = invz;
-      h.in.face = F; h.in.N[0] = N[F][0]; h.in.N[1] = N[F][1]; h.in.N[2] = N[F][2]; h.in.S = S; h.in.f = f;
-    }
-    if (invz < best_out) {
-      best_out = invz;
-      h.out.face = F; h.out.N[0] = N[F][0]; h.out.N[1] = N[F][1]; h.out.N[2] = N[F][2]; h.out.S = S; h.out.f = f;
-    }
+    const float f = num * rcp(S);
+    const float invz = S * rcp(r.D[F]);  // 1 / depth at the hit: larger is nearer
+    h.S[F] = S;
+    h.f[F] = f;
+    if (invz > best_in) { best_in = invz; h.fe = F; }
+    if (invz < best_out) { best_out = invz; h.fx = F; }
   }
   if (nh < 2) return false;
-  h.alpha = alpha_eq1(h.in.f, h.out.f, s);
+  float fin = h.f[0], fout = h.f[0];
+#pragma unroll
+  for (int F = 1; F < 4; ++F) {
+    if (h.fe == F) fin = h.f[F];
+    if (h.fx == F) fout = h.f[F];
+  }
+  const float d = fin - fout;
+  h.e1 = 0.0f;
+  h.e2 = 0.0f;
+  h.alpha = 0.0f;
+  if (d > 0.0f) {
+    h.e1 = expm1f(-(s * d));
+    h.e2 = expf(s * fout);
+    h.alpha = -h.e1 / (1.0f + h.e2);
+  }
   return true;
 }
 
@@ -113,6 +124,53 @@ __device__ __forceinline__ void unpack_rect(const ViewRec& r, int& i0, int& i1, 
   i1 = (int)(r.rx >> 16);
   j0 = (int)(r.ry & 0xffffu);
   j1 = (int)(r.ry >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// wave-wide transposed sum of 32 per-lane values (gfx950 permlane swaps and
+// DPP): afterwards lane L holds the sum over all 64 lanes of v[L >> 1].
+// Each step halves the values per lane while pairing lanes across a 32-,
+// 16-, 8-, 4-, 2- and 1-lane distance: 16+8 swaps, 4+2+1 DPP-fused adds.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_transpose_sum32(const float (&v)[32]) {
+  float u[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 16]), false, false);
+    u[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  float w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(u[k]), __float_as_uint(u[k + 8]), false, false);
+    w[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const unsigned lane = __lane_id();
+  const bool b3 = lane & 8u, b2 = lane & 4u, b1 = lane & 2u;
+  float x[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float send = b3 ? w[k] : w[k + 4];
+    const float keep = b3 ? w[k + 4] : w[k];
+    x[k] = keep + dpp<0x128>(send);   // row_ror:8  (lane j <-> j ^ 8)
+  }
+  float y[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float send = b2 ? x[k] : x[k + 2];
+    const float keep = b2 ? x[k + 2] : x[k];
+    y[k] = keep + dpp<0x141>(send);   // row_half_mirror (j <-> 7 - j)
+  }
+  const float send = b1 ? y[0] : y[1];
+  const float keep = b1 ? y[1] : y[0];
+  float z = keep + dpp<0x4E>(send);   // quad_perm [2,3,0,1]
+  z = z + dpp<0xB1>(z);               // quad_perm [1,0,3,2]
+  return z;
 }
 
 }  // namespace ts

@@ -24,8 +24,8 @@ class Params:
     """Blending and tiling parameters.  The thresholds are the ones of the
     3DGS rasterizer the paper builds on (Sec. 3.3); prefilter_tf is the
     paper's T_f (Sec. 3.2)."""
-    tile_w: int = 16
-    tile_h: int = 16
+    tile_w: int = 8
+    tile_h: int = 8
     alpha_min: float = 1.0 / 255.0
     alpha_clamp: float = 0.99
     t_min: float = 1e-4
