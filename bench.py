@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--s", type=float, default=320.0)
     ap.add_argument("--tile", default="8x8")
+    ap.add_argument("--waves", type=int, default=4, help="waves sharing one 8x8 tile")
     ap.add_argument("--check", default="lazy", choices=["sync", "lazy"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-view path")
@@ -79,7 +80,7 @@ def main():
     gen = torch.Generator(device=dev)
     gen.manual_seed(0)
     dout = torch.randn((nv, 8, H, W), device=dev, generator=gen)
-    params = Params(tile_w=tw, tile_h=th)
+    params = Params(tile_w=tw, tile_h=th, waves=args.waves)
     renderer = Renderer(params, device=dev, check=args.check)
 
     def step(cam_subset=None):
@@ -188,7 +189,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "training-shaped: 64^3-cube Kuhn grid (1,572,864 tets), sphere+torus smooth-union "
                                "SDF + N(0,0.005), per-vertex RGB, 4 orbit views 512x512, s=320, fwd+bwd",
-                   "views": nv, "width": W, "height": H, "tile": args.tile, "s": args.s,
+                   "views": nv, "width": W, "height": H, "tile": args.tile, "waves": args.waves, "s": args.s,
                    "path": "one launch sequence for all views", "status_check": args.check},
         "p50_ms": round(pct(step_ms, 50), 4), "p99_ms": round(pct(step_ms, 99), 4),
         "plain_path": plain,

@@ -88,6 +88,8 @@ typedef struct {
 typedef struct {
   int32_t tile_w, tile_h; /* screen tile; supported: 8x8, 16x8, 8x16, 16x16, 32x8 */
   int32_t flags;          /* RENDER_* flags above */
+  int32_t waves;          /* 64-lane waves sharing one 8x8 tile (1, 2, 4, 8; 0: 4); larger
+                             tiles use one wave per 8x8 block of pixels */
   float alpha_min;        /* skip a tet whose alpha is below this (3DGS: 1/255) */
   float alpha_clamp;      /* clamp alpha to at most this (3DGS: 0.99) */
   float t_min;            /* stop before a tet that takes T below this (3DGS: 1e-4) */

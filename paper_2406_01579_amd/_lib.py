@@ -24,7 +24,8 @@ class render_view(C.Structure):
 
 
 class render_params(C.Structure):
-    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("flags", C.c_int32), ("alpha_min", C.c_float),
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("flags", C.c_int32), ("waves", C.c_int32),
+                ("alpha_min", C.c_float),
                 ("alpha_clamp", C.c_float), ("t_min", C.c_float), ("prefilter_tf", C.c_float)]
 
 

@@ -64,6 +64,8 @@ int check_args(const render_scene* scenes, int ns, const render_view* views, int
     return fail(RENDER_EINVAL, "unsupported tile %dx%d (8x8, 16x8, 8x16, 16x16, 32x8)", p->tile_w, p->tile_h);
   if (p->flags & ~(RENDER_RECOMPUTE_STATE | RENDER_VALIDATE)) return fail(RENDER_EINVAL, "unknown flags 0x%x", p->flags);
   if (!(p->alpha_clamp > 0.0f && p->alpha_clamp <= 1.0f)) return fail(RENDER_EINVAL, "alpha_clamp must be in (0, 1]");
+  if (!(p->waves == 0 || p->waves == 1 || p->waves == 2 || p->waves == 4 || p->waves == 8))
+    return fail(RENDER_EINVAL, "waves must be 0, 1, 2, 4 or 8 (got %d)", p->waves);
   for (int s = 0; s < ns; ++s) {
     const render_scene& S = scenes[s];
     if (S.V < 0 || S.K < 0) return fail(RENDER_EINVAL, "scene %d: negative V or K", s);
@@ -194,6 +196,8 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_srec = take(4 * (size_t)entry_cap);
   L.o_inv = take(4 * (size_t)entry_cap);
   L.o_ranges = take(8 * (size_t)tiles);
+  L.o_tile_hist = take(4 * 2 * (size_t)TILE_BUCKETS);  // right after the ranges: cleared together
+  L.o_tile_order = take(4 * (size_t)tiles);
   L.o_proc_end = take(4 * (size_t)tiles);
   L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE * (size_t)entry_cap);
   L.o_last = take(4 * (size_t)pixels);
@@ -215,6 +219,14 @@ int prepare(const render_scene* scenes, int ns, const render_view* views, int nv
   if (ws_bytes < L.bytes)
     return fail(RENDER_ENOSPC, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
   return RENDER_OK;
+}
+
+// 8x8 tiles with more than one wave use the multi-wave compositing kernels
+int effective_waves(const render_params& p) { return p.waves == 0 ? 4 : p.waves; }
+bool multiwave(const render_params& p) { return p.tile_w == 8 && p.tile_h == 8 && effective_waves(p) > 1; }
+render_params with_waves(render_params p) {
+  p.waves = effective_waves(p);
+  return p;
 }
 
 #define TS_TRY(call, name)                        \
@@ -282,7 +294,11 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
   TS_STAGE(RENDER_STAGE_EMIT, launch_emit(workspace, L, *params, st), "emit");
   TS_STAGE(RENDER_STAGE_TILE_SORT, launch_sort_entries(workspace, L, st), "tile sort");
   TS_STAGE(RENDER_STAGE_RANGES, launch_finalize(workspace, L, st), "tile ranges");
-  TS_STAGE(RENDER_STAGE_COMPOSITE, launch_composite(workspace, L, *params, st), "composite");
+  TS_STAGE(RENDER_STAGE_RANGES, launch_tile_order(workspace, L, st), "tile order");
+  TS_STAGE(RENDER_STAGE_COMPOSITE,
+           multiwave(*params) ? launch_composite_mw(workspace, L, with_waves(*params), st)
+                              : launch_composite(workspace, L, *params, st),
+           "composite");
   return RENDER_OK;
 }
 
@@ -312,7 +328,10 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
   TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, false, st),
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
-  TS_STAGE(RENDER_STAGE_COMPOSITE_BWD, launch_composite_backward(workspace, L, *params, st), "composite backward");
+  TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,
+           multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)
+                              : launch_composite_backward(workspace, L, *params, st),
+           "composite backward");
   TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
   return RENDER_OK;
 }

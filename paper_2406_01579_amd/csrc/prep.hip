@@ -512,8 +512,71 @@ hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
   const bool odd = passes_for(L.key2_bits) & 1;
   const uint32_t* keys = at<const uint32_t>(ws, odd ? L.o_key2b : L.o_key2a);
   const uint32_t* vals = at<const uint32_t>(ws, odd ? L.o_val2b : L.o_val2a);
-  k_fill_u32<<<256, 256, 0, st>>>(at<uint32_t>(ws, L.o_ranges), 2 * (uint64_t)L.total_tiles, 0u);
+  // ranges and the tile-length histogram are adjacent: clear both
+  k_fill_u32<<<256, 256, 0, st>>>(at<uint32_t>(ws, L.o_ranges),
+                                  (L.o_tile_hist - L.o_ranges) / 4 + 2 * (uint64_t)TILE_BUCKETS, 0u);
   k_finalize<<<2048, 256, 0, st>>>(ws, L, keys, vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dispatch order of the compositing workgroups: tiles with the longest lists
+// first (bucketed by the bit length of the list size), so the longest
+// sequential walks start in the first scheduling round.  The order inside a
+// bucket is whatever the atomics give; results do not depend on it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0 ? 0 : 32 - __clz(len); }
+
+__global__ __launch_bounds__(256) void k_tile_hist(void* ws, Layout L) {
+  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
+  uint32_t* hist = at<uint32_t>(ws, L.o_tile_hist);
+  __shared__ uint32_t h[TILE_BUCKETS];
+  if (threadIdx.x < TILE_BUCKETS) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t < (uint32_t)L.total_tiles) atomicAdd(&h[len_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < TILE_BUCKETS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_tile_scan(void* ws, Layout L) {
+  uint32_t* hist = at<uint32_t>(ws, L.o_tile_hist);
+  uint32_t* off = hist + TILE_BUCKETS;
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = TILE_BUCKETS - 1; b >= 0; --b) {
+      off[b] = run;
+      run += hist[b];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
+  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
+  uint32_t* off = at<uint32_t>(ws, L.o_tile_hist) + TILE_BUCKETS;
+  uint32_t* order = at<uint32_t>(ws, L.o_tile_order);
+  __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS];
+  if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  int b = 0;
+  uint32_t rank = 0;
+  if (t < (uint32_t)L.total_tiles) {
+    b = len_bucket(ranges[2 * t + 1] - ranges[2 * t]);
+    rank = atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&off[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (t < (uint32_t)L.total_tiles) order[base[b] + rank] = t;
+}
+
+hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
+  k_tile_hist<<<nb, 256, 0, st>>>(ws, L);
+  k_tile_scan<<<1, 64, 0, st>>>(ws, L);
+  k_tile_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 

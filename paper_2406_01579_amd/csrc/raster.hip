@@ -32,9 +32,9 @@ struct TileCtx {
 };
 
 template <int TW, int TH>
-__device__ __forceinline__ TileCtx tile_ctx(const DevView* vw, int nv) {
+__device__ __forceinline__ TileCtx tile_ctx(const DevView* vw, int nv, const uint32_t* order) {
   TileCtx c;
-  c.tile = blockIdx.x;
+  c.tile = (int)order[blockIdx.x];
   c.view = find_view_by_tile(vw, nv, c.tile);
   const DevView& V = vw[c.view];
   c.lt = c.tile - V.tile_base;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
   float* tlast_out = at<float>(ws, L.o_tlast);
   __shared__ ViewRec recs[CH];
 
-  const TileCtx c = tile_ctx<TW, TH>(vw, L.nv);
+  const TileCtx c = tile_ctx<TW, TH>(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
   const float s = sc[V.scene].s;
   const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   __shared__ float gacc[CH][TGRAD_STRIDE];
   __shared__ int smax[NW];
 
-  const TileCtx c = tile_ctx<TW, TH>(vw, L.nv);
+  const TileCtx c = tile_ctx<TW, TH>(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
   const float s = sc[V.scene].s;
   const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];

@@ -1,0 +1,386 @@
+// Multi-wave compositing kernels for 8x8 tiles.
+//
+// A tile's entry list is walked front to back (forward) or back to front
+// (backward) by one pixel per lane, and the per-pixel state along the list
+// (transmittance, the colour behind) is a short sequential recurrence.  The
+// expensive part of every (pixel, entry) pair -- coverage of the projected
+// hull, entry/exit SDF values and Eq. 1, and in the backward the chain to the
+// record's screen-space parameters and the wave reduction -- does not depend
+// on that state.  So NWV waves share one 8x8 tile: for each LDS chunk of
+// entries they evaluate interleaved entries in parallel into LDS, one wave
+// runs the recurrence over the chunk, and (backward) the waves then build and
+// reduce the per-entry gradients in parallel.  Results are bit-identical to
+// the one-wave kernels: the same per-pair arithmetic in the same order.
+#include "ts_device.h"
+
+namespace ts {
+
+namespace {
+
+__device__ __forceinline__ void load_recs(ViewRec* recs, const ViewRec* __restrict__ vrec,
+                                          const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads) {
+  for (int q = threadIdx.x; q < n * 8; q += nthreads) {
+    const int e = q >> 3, part = q & 7;
+    const uint32_t r = srec[base + e];
+    reinterpret_cast<float4*>(&recs[e])[part] = reinterpret_cast<const float4*>(&vrec[r])[part];
+  }
+}
+
+__device__ __forceinline__ bool has_pixel(const ViewRec& R, int i, int j) {
+  int i0, i1, j0, j1;
+  unpack_rect(R, i0, i1, j0, j1);
+  return i >= i0 && i <= i1 && j >= j0 && j <= j1;
+}
+
+struct Tile8 {
+  int view, tile;
+  int i, j;
+  bool inside;
+};
+
+__device__ __forceinline__ Tile8 tile8(const DevView* vw, int nv, const uint32_t* order) {
+  Tile8 c;
+  c.tile = (int)order[blockIdx.x];
+  c.view = find_view_by_tile(vw, nv, c.tile);
+  const DevView& V = vw[c.view];
+  const int lt = c.tile - V.tile_base;
+  const int lane = threadIdx.x & 63;
+  c.i = (lt % V.tiles_x) * 8 + (lane & 7);
+  c.j = (lt / V.tiles_x) * 8 + (lane >> 3);
+  c.inside = c.i < V.W && c.j < V.H;
+  return c;
+}
+
+// Forward sweep over [start, end) with NWV waves; wave 0 ends with the
+// pixel's blend state.  Used by the forward kernel and by the backward's
+// state replay.
+template <int NWV, int CHN>
+__device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, const uint32_t* __restrict__ srec,
+                                              uint32_t start, uint32_t end, const Tile8& c, float s, float alpha_min,
+                                              float alpha_clamp, float t_min, ViewRec* recs, float (*alds)[64],
+                                              unsigned long long* done_mask, float& T, float& Tb, float& O,
+                                              float (&acc)[7], int& last, bool want_acc) {
+  constexpr int NT = 64 * NWV;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
+  bool done = !c.inside;
+  if (threadIdx.x == 0) *done_mask = 0ull;
+  __syncthreads();
+  if (wave == 0) {
+    const unsigned long long m = __ballot(done);
+    if (lane == 0) *done_mask = m;
+  }
+  for (uint32_t base = start; base < end; base += CHN) {
+    __syncthreads();
+    if (*done_mask == ~0ull) break;
+    const int n = (int)min((uint32_t)CHN, end - base);
+    load_recs(recs, vrec, srec, base, n, NT);
+    __syncthreads();
+    const bool mydone = (*done_mask >> lane) & 1ull;
+    for (int e = wave; e < n; e += NWV) {
+      float a = -1.0f;
+      const ViewRec& R = recs[e];
+      if (!mydone && has_pixel(R, c.i, c.j)) {
+        PixEval h;
+        if (pixel_eval(R, qx, qy, s, h)) a = h.alpha;
+      }
+      alds[e][lane] = a;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int e = 0; e < n; ++e) {
+        float a = alds[e][lane];
+        if (done || a < 0.0f) continue;
+        if (a < alpha_min) continue;
+        a = fminf(a, alpha_clamp);
+        const float Tn = T * (1.0f - a);
+        if (Tn < t_min) { done = true; continue; }
+        const float w = T * a;
+        if (want_acc) {
+          const ViewRec& R = recs[e];
+          acc[0] = fmaf(w, R.c[0], acc[0]);
+          acc[1] = fmaf(w, R.c[1], acc[1]);
+          acc[2] = fmaf(w, R.c[2], acc[2]);
+          acc[3] = fmaf(w, R.zt, acc[3]);
+          acc[4] = fmaf(w, R.n[0], acc[4]);
+          acc[5] = fmaf(w, R.n[1], acc[5]);
+          acc[6] = fmaf(w, R.n[2], acc[6]);
+          O += w;
+        }
+        Tb = T;
+        T = Tn;
+        last = (int)(base + e);
+        if (T == 0.0f) done = true;
+      }
+      const unsigned long long m = __ballot(done);
+      if (lane == 0) *done_mask = m;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, float alpha_min, float alpha_clamp,
+                                                           float t_min) {
+  constexpr int CHN = 64;
+  const DevView* vw = at<const DevView>(ws, L.o_view);
+  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
+  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
+  const uint32_t* srec = at<const uint32_t>(ws, L.o_srec);
+  const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
+  int32_t* last_out = at<int32_t>(ws, L.o_last);
+  float* tlast_out = at<float>(ws, L.o_tlast);
+  __shared__ ViewRec recs[CHN];
+  __shared__ float alds[CHN][64];
+  __shared__ unsigned long long done_mask;
+
+  const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const DevView& V = vw[c.view];
+  const float s = sc[V.scene].s;
+  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  float T = 1.0f, Tb = 1.0f, O = 0.0f;
+  float acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  int last = -1;
+  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, &done_mask, T,
+                          Tb, O, acc, last, true);
+  if ((threadIdx.x >> 6) == 0 && c.inside) {
+    const size_t plane = (size_t)V.W * V.H;
+    const size_t px = (size_t)c.j * V.W + c.i;
+    float* out = V.out;
+    out[0 * plane + px] = fmaf(T, V.bg[0], acc[0]);
+    out[1 * plane + px] = fmaf(T, V.bg[1], acc[1]);
+    out[2 * plane + px] = fmaf(T, V.bg[2], acc[2]);
+    out[3 * plane + px] = O;
+    out[4 * plane + px] = acc[3];
+    out[5 * plane + px] = acc[4];
+    out[6 * plane + px] = acc[5];
+    out[7 * plane + px] = acc[6];
+    const size_t g = (size_t)V.pix_base + px;
+    last_out[g] = last;
+    tlast_out[g] = Tb;
+  }
+}
+
+// d f(face F) / d(record parameters) times df, added to g (static indices)
+template <int F>
+__device__ __forceinline__ void face_grad_mw(const ViewRec& R, const PixEval& h, float df, float (&g)[32]) {
+  constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
+  constexpr int I[3] = {A, B, C};
+  const float invS = rcp(h.S[F]);
+  const float fF = h.f[F];
+  float a[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int v = I[k];
+    const float wk = R.iz[v];
+    const float diff = (R.f[v] - fF) * invS * df;
+    g[G_F + v] = fmaf(h.N[F][k] * wk * invS, df, g[G_F + v]);
+    g[G_IZ + v] = fmaf(h.N[F][k], diff, g[G_IZ + v]);
+    a[k] = wk * diff;
+  }
+  const float Ax = h.ax[A], Ay = h.ay[A], Bx = h.ax[B], By = h.ay[B], Cx = h.ax[C], Cy = h.ay[C];
+  g[G_PX + A] += a[2] * By - a[1] * Cy;
+  g[G_PY + A] += a[1] * Cx - a[2] * Bx;
+  g[G_PX + B] += a[0] * Cy - a[2] * Ay;
+  g[G_PY + B] += a[2] * Ax - a[0] * Cx;
+  g[G_PX + C] += a[1] * Ay - a[0] * By;
+  g[G_PY + C] += a[0] * Bx - a[1] * Ax;
+}
+
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout L, float alpha_min,
+                                                               float alpha_clamp, float t_min, int recompute) {
+  constexpr int NT = 64 * NWV;
+  constexpr int CHB = 32;
+  const DevView* vw = at<const DevView>(ws, L.o_view);
+  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
+  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
+  const uint32_t* srec = at<const uint32_t>(ws, L.o_srec);
+  const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
+  const int32_t* last_in = at<const int32_t>(ws, L.o_last);
+  const float* tlast_in = at<const float>(ws, L.o_tlast);
+  uint32_t* proc_end = at<uint32_t>(ws, L.o_proc_end);
+  float* tgrad = at<float>(ws, L.o_tgrad);
+  __shared__ ViewRec recs[CHB];
+  __shared__ float abuf[CHB][64];   // raw alpha, then dL/dalpha (0 when clamped)
+  __shared__ float wbuf[CHB][64];   // blend weight T alpha (0: no contribution)
+  __shared__ float gacc[CHB][TGRAD_STRIDE];
+  __shared__ unsigned long long done_mask;
+  __shared__ int smax;
+
+  const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const DevView& V = vw[c.view];
+  const float s = sc[V.scene].s;
+  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
+  const size_t plane = (size_t)V.W * V.H;
+  const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
+  const unsigned lane = threadIdx.x & 63u;
+  const int wave = threadIdx.x >> 6;
+
+  int last = -1;
+  float Tb = 1.0f;
+  if (recompute) {
+    float T = 1.0f, O = 0.0f;
+    float acc[7];
+    forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, &done_mask, T,
+                            Tb, O, acc, last, false);
+    // the replayed state lives in wave 0; share `last` for the chunk bounds
+  } else if (c.inside) {
+    const size_t gi = (size_t)V.pix_base + px;
+    last = last_in[gi];
+    Tb = tlast_in[gi];
+  }
+  // every wave needs this pixel's `last`; wave 0 holds it after a replay
+  if (recompute) {
+    __syncthreads();
+    if (wave == 0) abuf[0][lane] = __int_as_float(last);
+    __syncthreads();
+    last = __float_as_int(abuf[0][lane]);
+    __syncthreads();
+  }
+
+  float gr[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
+  float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
+
+  int wmax = last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+  if (threadIdx.x == 0) smax = wmax;
+  __syncthreads();
+  const int tmax = smax;
+  const uint32_t pend = (tmax >= (int)start) ? (uint32_t)tmax + 1u : start;
+  if (threadIdx.x == 0) proc_end[c.tile] = pend;
+
+  bool first = true;
+  float Tnext = 1.0f;
+  for (int64_t cb = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CHB) * CHB;
+       cb >= (int64_t)start && pend > start; cb -= CHB) {
+    const uint32_t base = (uint32_t)cb;
+    const int n = (int)min((uint32_t)CHB, pend - base);
+    __syncthreads();
+    load_recs(recs, vrec, srec, base, n, NT);
+    __syncthreads();
+    // phase A: raw alpha of every (entry, pixel) the pixel's walk reached
+    for (int e = wave; e < n; e += NWV) {
+      float a = -1.0f;
+      const ViewRec& R = recs[e];
+      if (c.inside && (int)(base + e) <= last && has_pixel(R, c.i, c.j)) {
+        PixEval h;
+        if (pixel_eval(R, qx, qy, s, h)) a = h.alpha;
+      }
+      abuf[e][lane] = a;
+    }
+    __syncthreads();
+    // phase B: reverse recurrence (one wave)
+    if (wave == 0) {
+      for (int e = n - 1; e >= 0; --e) {
+        const float araw = abuf[e][lane];
+        float da = 0.0f, w = 0.0f;
+        if (araw >= 0.0f && araw >= alpha_min) {
+          const ViewRec& R = recs[e];
+          const float a = fminf(araw, alpha_clamp);
+          float T;
+          if (first) { T = Tb; first = false; }
+          else T = Tnext * rcp(1.0f - a);
+          Tnext = T;
+          w = T * a;
+          const float sdot = gr[0] * R.c[0] + gr[1] * R.c[1] + gr[2] * R.c[2] + gr[3] + gr[4] * R.zt +
+                             gr[5] * R.n[0] + gr[6] * R.n[1] + gr[7] * R.n[2];
+          da = T * (sdot - Rbehind);
+          Rbehind = a * sdot + (1.0f - a) * Rbehind;
+          if (araw > alpha_clamp) da = 0.0f;
+        }
+        abuf[e][lane] = da;
+        wbuf[e][lane] = w;
+      }
+    }
+    __syncthreads();
+    // phase C: per-entry gradients, reduced over the tile
+    for (int e = wave; e < n; e += NWV) {
+      const float da = abuf[e][lane], w = wbuf[e][lane];
+      const bool contrib = (da != 0.0f) || (w != 0.0f);
+      if (__ballot(contrib) == 0ull) {
+        if (lane < (unsigned)TGRAD_STRIDE) gacc[e][lane] = 0.0f;
+        continue;
+      }
+      float g[32];
+#pragma unroll
+      for (int q = 0; q < 32; ++q) g[q] = 0.0f;
+      if (contrib) {
+        const ViewRec& R = recs[e];
+        g[G_C + 0] = w * gr[0];
+        g[G_C + 1] = w * gr[1];
+        g[G_C + 2] = w * gr[2];
+        g[G_ZT] = w * gr[4];
+        g[G_N + 0] = w * gr[5];
+        g[G_N + 1] = w * gr[6];
+        g[G_N + 2] = w * gr[7];
+        if (da != 0.0f) {
+          PixEval h;
+          pixel_eval(R, qx, qy, s, h);
+          if (h.alpha > 0.0f) {
+            const float invB = rcp(1.0f + h.e2);
+            const float dA = da * invB;
+            const float dB = -da * h.alpha * invB;
+            const float dd = dA * s * (h.e1 + 1.0f);
+            const float dfn = dB * s * h.e2 - dd;
+#pragma unroll
+            for (int F = 0; F < 4; ++F) {
+              const float wF = (h.fe == F ? dd : 0.0f) + (h.fx == F ? dfn : 0.0f);
+              if (wF != 0.0f) {
+                if (F == 0) face_grad_mw<0>(R, h, wF, g);
+                if (F == 1) face_grad_mw<1>(R, h, wF, g);
+                if (F == 2) face_grad_mw<2>(R, h, wF, g);
+                if (F == 3) face_grad_mw<3>(R, h, wF, g);
+              }
+            }
+          }
+        }
+      }
+      const float tot = wave_transpose_sum32(g);
+      const unsigned q = lane >> 1;
+      if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) tgrad[(size_t)base * TGRAD_STRIDE + q] = (&gacc[0][0])[q];
+  }
+}
+
+template <int NWV>
+static void launch_fwd_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  k_composite_mw<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp, p.t_min);
+}
+template <int NWV>
+static void launch_bwd_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  k_composite_bwd_mw<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(
+      ws, L, p.alpha_min, p.alpha_clamp, p.t_min, (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0);
+}
+
+hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  switch (p.waves) {
+    case 2: launch_fwd_mw<2>(ws, L, p, st); break;
+    case 4: launch_fwd_mw<4>(ws, L, p, st); break;
+    case 8: launch_fwd_mw<8>(ws, L, p, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_backward_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  switch (p.waves) {
+    case 2: launch_bwd_mw<2>(ws, L, p, st); break;
+    case 4: launch_bwd_mw<4>(ws, L, p, st); break;
+    case 8: launch_bwd_mw<8>(ws, L, p, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ts

@@ -63,6 +63,23 @@ struct PixEval {
   float e1, e2;    // expm1(-s d), exp(s f_next) (for the derivative)
 };
 
+// exp(x) from the hardware base-2 exponential
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// expm1(x) for x <= 0: Taylor series through x^7/5040 on [-0.25, 0] (truncation
+// below 1e-9 relative), exp(x) - 1 below (no cancellation there).
+__device__ __forceinline__ float fast_expm1_neg(float x) {
+  float p = fmaf(x, 1.0f / 5040.0f, 1.0f / 720.0f);
+  p = fmaf(x, p, 1.0f / 120.0f);
+  p = fmaf(x, p, 1.0f / 24.0f);
+  p = fmaf(x, p, 1.0f / 6.0f);
+  p = fmaf(x, p, 0.5f);
+  p = fmaf(x, p, 1.0f);
+  const float small = x * p;
+  const float big = fast_exp(x) - 1.0f;
+  return x > -0.25f ? small : big;
+}
+
 __device__ __forceinline__ bool pixel_eval(const ViewRec& r, float qx, float qy, float s, PixEval& h) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -79,16 +96,14 @@ __device__ __forceinline__ bool pixel_eval(const ViewRec& r, float qx, float qy,
   h.N[1][0] = e13; h.N[1][1] = -e03; h.N[1][2] = e01;
   h.N[2][0] = e23; h.N[2][1] = -e03; h.N[2][2] = e02;
   h.N[3][0] = e23; h.N[3][1] = -e13; h.N[3][2] = e12;
+  // every face is evaluated (no branches); only inside faces are selected
   int nh = 0;
-  float best_in = -INFINITY, best_out = INFINITY;
+  float best_in = -INFINITY, best_out = INFINITY, fin = 0.0f, fout = 0.0f;
   h.fe = 0;
   h.fx = 0;
 #pragma unroll
   for (int F = 0; F < 4; ++F) {
-    h.S[F] = 1.0f;
-    h.f[F] = 0.0f;
-    if (!face_inside(h.N[F][0], h.N[F][1], h.N[F][2], r.D[F])) continue;
-    ++nh;
+    const bool in = face_inside(h.N[F][0], h.N[F][1], h.N[F][2], r.D[F]);
     const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
     const float qa = h.N[F][0] * r.iz[A], qb = h.N[F][1] * r.iz[B], qc = h.N[F][2] * r.iz[C];
     const float S = (qa + qb) + qc;
@@ -97,26 +112,23 @@ __device__ __forceinline__ bool pixel_eval(const ViewRec& r, float qx, float qy,
     const float invz = S * rcp(r.D[F]);  // 1 / depth at the hit: larger is nearer
     h.S[F] = S;
     h.f[F] = f;
-    if (invz > best_in) { best_in = invz; h.fe = F; }
-    if (invz < best_out) { best_out = invz; h.fx = F; }
+    nh += in ? 1 : 0;
+    const bool bi = in && invz > best_in, bo = in && invz < best_out;
+    best_in = bi ? invz : best_in;
+    fin = bi ? f : fin;
+    h.fe = bi ? F : h.fe;
+    best_out = bo ? invz : best_out;
+    fout = bo ? f : fout;
+    h.fx = bo ? F : h.fx;
   }
-  if (nh < 2) return false;
-  float fin = h.f[0], fout = h.f[0];
-#pragma unroll
-  for (int F = 1; F < 4; ++F) {
-    if (h.fe == F) fin = h.f[F];
-    if (h.fx == F) fout = h.f[F];
-  }
+  // Eq. 1, stable form, with the hardware exponential
   const float d = fin - fout;
-  h.e1 = 0.0f;
-  h.e2 = 0.0f;
-  h.alpha = 0.0f;
-  if (d > 0.0f) {
-    h.e1 = expm1f(-(s * d));
-    h.e2 = expf(s * fout);
-    h.alpha = -h.e1 / (1.0f + h.e2);
-  }
-  return true;
+  const bool pos = d > 0.0f;
+  const float x = pos ? -(s * d) : 0.0f;
+  h.e1 = fast_expm1_neg(x);
+  h.e2 = pos ? fast_exp(s * fout) : 0.0f;
+  h.alpha = pos ? -h.e1 * rcp(1.0f + h.e2) : 0.0f;
+  return nh >= 2;
 }
 
 __device__ __forceinline__ void unpack_rect(const ViewRec& r, int& i0, int& i1, int& j0, int& j1) {

@@ -110,7 +110,7 @@ struct Layout {
   size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_rec_off, o_off_sorted, o_scan_part;
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_erec, o_srec, o_inv;
-  size_t o_ranges, o_proc_end, o_tgrad, o_last, o_tlast;
+  size_t o_ranges, o_tile_hist, o_tile_order, o_proc_end, o_tgrad, o_last, o_tlast;
   size_t bytes;
 };
 
@@ -132,8 +132,12 @@ hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st);
+constexpr int TILE_BUCKETS = 33;  // tiles bucketed by bit length of their list size
 hipError_t launch_composite(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_composite_backward_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene* hs, hipStream_t st);
 

@@ -31,10 +31,11 @@ class Params:
     t_min: float = 1e-4
     prefilter_tf: float = 1.0 / 255.0
     recompute_state: bool = False
+    waves: int = 4   # waves sharing one 8x8 tile
 
     def c(self) -> _lib.render_params:
         return _lib.render_params(self.tile_w, self.tile_h,
-                                  _lib.RENDER_RECOMPUTE_STATE if self.recompute_state else 0,
+                                  _lib.RENDER_RECOMPUTE_STATE if self.recompute_state else 0, self.waves,
                                   self.alpha_min, self.alpha_clamp, self.t_min, self.prefilter_tf)
 
     @classmethod

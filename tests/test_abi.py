@@ -135,6 +135,11 @@ def test_bad_arguments_rejected_before_device_work(L):
     assert lib.render_forward(C.byref(scenes), 1, C.byref(views), 1, C.byref(p), 0, 0, ws, 1 << 30,
                               None) == L.RENDER_EINVAL
     p.alpha_clamp = 0.99
+    p.waves = 3
+    assert lib.render_forward(C.byref(scenes), 1, C.byref(views), 1, C.byref(p), 0, 0, ws, 1 << 30,
+                              None) == L.RENDER_EINVAL
+    assert b"waves" in lib.render_last_error()
+    p.waves = 4
     # misaligned workspace
     assert lib.render_forward(C.byref(scenes), 1, C.byref(views), 1, C.byref(p), 0, 0, ws + 4, 1 << 30,
                               None) == L.RENDER_EINVAL

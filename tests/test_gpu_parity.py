@@ -336,3 +336,23 @@ def test_training_gradients_of_sparse_upstream(training):
     ref64 = oracle.backward(g, w.cams, op, upix, dflat, prec=64)
     for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads, ref32, ref64):
         check_gradient(name, got.cpu().numpy(), r32, r64, "training sparse-upstream")
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+def test_waves_per_tile_do_not_change_results(waves):
+    """Several waves sharing an 8x8 tile evaluate the same per-pair arithmetic."""
+    import torch
+    w = synth.tiny(s=100.0, bg=(0.3, 0.3, 0.3))
+    sc = w.scenes[0]
+    dout = torch.from_numpy(np.random.default_rng(8).normal(size=(8, 64, 64)).astype(np.float32)).cuda()
+    res = []
+    for wv in (1, waves):
+        for rc in (False, True):
+            r, plan, imgs = gpu_forward(sc, w.cams, _params("default", (8, 8), waves=wv, recompute_state=rc))
+            grads = [t.cpu().numpy() for t in r.backward(plan, [dout])[0]]
+            res.append((imgs[0], grads))
+    ref_img, ref_g = res[0]
+    for img, grads in res[1:]:
+        assert np.array_equal(img, ref_img)
+        for a, b in zip(grads, ref_g):
+            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * np.abs(b).max())
