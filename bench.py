@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-view path")
     ap.add_argument("--cpu-pixels", type=int, default=400000)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a device buffer of this many MiB three times (a plain copy "
+                         "kernel of known size, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -178,6 +181,15 @@ def main():
         pms = [a.elapsed_time(b) for a, b in pev]
         plain = {"ms_per_step": round(1000 * pw, 4), "mpx_s": round(pixels / pw / 1e6, 2),
                  "p50_ms": round(pct(pms, 50), 4), "p99_ms": round(pct(pms, 99), 4)}
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu:
