@@ -85,7 +85,7 @@ int check_args(const render_scene* scenes, int ns, const render_view* views, int
 }
 
 void fill_desc(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
-               const Layout& L, std::vector<DevScene>& hs, std::vector<DevView>& hv) {
+               const Layout& L, std::vector<DevScene>& hs, std::vector<DevView>& hv, std::vector<int32_t>& sv) {
   hs.assign(ns, DevScene{});
   int blk = 0;
   for (int s = 0; s < ns; ++s) {
@@ -100,6 +100,14 @@ void fill_desc(const render_scene* scenes, int ns, const render_view* views, int
     d.block_base = blk;
     d.n_blocks = (scenes[s].K + PF_TILE - 1) / PF_TILE;
     blk += d.n_blocks;
+  }
+  // views grouped by scene (stable): scene s owns sv[view_first .. + view_count)
+  sv.clear();
+  for (int s = 0; s < ns; ++s) {
+    hs[s].view_first = (int32_t)sv.size();
+    for (int v = 0; v < nv; ++v)
+      if (views[v].scene == s) sv.push_back(v);
+    hs[s].view_count = (int32_t)sv.size() - hs[s].view_first;
   }
   hv.assign(nv, DevView{});
   int64_t tb = 0, pb = 0;
@@ -172,6 +180,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_hdr = take(sizeof(DevHeader));
   L.o_scene = take(sizeof(DevScene) * ns);
   L.o_view = take(sizeof(DevView) * nv);
+  L.o_scene_views = take(4 * (size_t)nv);
   L.o_view_rec_base = take(4 * (size_t)nv);
   L.o_scene_kept_base = take(4 * (size_t)ns);
   L.o_scene_kept_count = take(4 * (size_t)ns);
@@ -284,8 +293,9 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<DevScene> hs;
   std::vector<DevView> hv;
-  fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv);
-  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, true, st),
+  std::vector<int32_t> sv;
+  fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv, sv);
+  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, true, st),
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_PREFILTER, launch_prefilter(workspace, L, *params, st), "pre-filter");
   TS_STAGE(RENDER_STAGE_PROJECT, launch_project(workspace, L, *params, st), "project");
@@ -318,14 +328,15 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<DevScene> hs;
   std::vector<DevView> hv;
-  fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv);
+  std::vector<int32_t> sv;
+  fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv, sv);
   for (int s = 0; s < n_scenes; ++s) {
     hs[s].dverts = grads[s].dverts;
     hs[s].dsdf = grads[s].dsdf;
     hs[s].dcolors = grads[s].dcolors;
   }
   for (int v = 0; v < n_views; ++v) hv[v].dout = dL_dout[v];
-  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, workspace, L, false, st),
+  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, false, st),
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
   TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,

@@ -33,8 +33,8 @@ static hipError_t upload(const void* src, size_t bytes, void* dst, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, void* ws, const Layout& L,
-                             bool reset_header, hipStream_t st) {
+hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                             void* ws, const Layout& L, bool reset_header, hipStream_t st) {
   hipError_t e;
   if (reset_header) {
     // fresh counters for a forward pass (its kernels accumulate into them)
@@ -45,6 +45,8 @@ hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int 
     if (e != hipSuccess) return e;
   }
   e = upload(hs, sizeof(DevScene) * ns, at<void>(ws, L.o_scene), st);
+  if (e != hipSuccess) return e;
+  e = upload(scene_views, sizeof(int32_t) * nv, at<void>(ws, L.o_scene_views), st);
   if (e != hipSuccess) return e;
   return upload(hv, sizeof(DevView) * nv, at<void>(ws, L.o_view), st);
 }

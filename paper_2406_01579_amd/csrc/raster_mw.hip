@@ -163,24 +163,32 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   }
 }
 
-// d f(face F) / d(record parameters) times df, added to g (static indices)
+// d f(face F) / d(record parameters) times df, added to g.  F is a
+// compile-time constant, so every index is static; the face's values (S, f)
+// are recomputed from its cross products N.
+// f = sum N_k w_k f_k / S, S = sum N_k w_k.
 template <int F>
-__device__ __forceinline__ void face_grad_mw(const ViewRec& R, const PixEval& h, float df, float (&g)[32]) {
+__device__ __forceinline__ void face_geom_grad(const ViewRec& R, const float (&ax)[4], const float (&ay)[4],
+                                               float N0, float N1, float N2, float df, float (&g)[32]) {
   constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
   constexpr int I[3] = {A, B, C};
-  const float invS = rcp(h.S[F]);
-  const float fF = h.f[F];
+  const float N[3] = {N0, N1, N2};
+  const float qa = N0 * R.iz[A], qb = N1 * R.iz[B], qc = N2 * R.iz[C];
+  const float S = (qa + qb) + qc;
+  const float invS = rcp(S);
+  const float fF = fmaf(qa, R.f[A], fmaf(qb, R.f[B], qc * R.f[C])) * invS;
   float a[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int v = I[k];
     const float wk = R.iz[v];
     const float diff = (R.f[v] - fF) * invS * df;
-    g[G_F + v] = fmaf(h.N[F][k] * wk * invS, df, g[G_F + v]);
-    g[G_IZ + v] = fmaf(h.N[F][k], diff, g[G_IZ + v]);
-    a[k] = wk * diff;
+    g[G_F + v] = fmaf(N[k] * wk * invS, df, g[G_F + v]);   // d/df_k
+    g[G_IZ + v] = fmaf(N[k], diff, g[G_IZ + v]);            // d/dw_k
+    a[k] = wk * diff;                                       // d/dN_k
   }
-  const float Ax = h.ax[A], Ay = h.ay[A], Bx = h.ax[B], By = h.ay[B], Cx = h.ax[C], Cy = h.ay[C];
+  const float Ax = ax[A], Ay = ay[A], Bx = ax[B], By = ay[B], Cx = ax[C], Cy = ay[C];
+  // N0 = cross(B', C'), N1 = cross(C', A'), N2 = cross(A', B')
   g[G_PX + A] += a[2] * By - a[1] * Cy;
   g[G_PY + A] += a[1] * Cx - a[2] * Bx;
   g[G_PX + B] += a[0] * Cy - a[2] * Ay;
@@ -204,9 +212,14 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   uint32_t* proc_end = at<uint32_t>(ws, L.o_proc_end);
   float* tgrad = at<float>(ws, L.o_tgrad);
   __shared__ ViewRec recs[CHB];
-  __shared__ float abuf[CHB][64];   // raw alpha, then dL/dalpha (0 when clamped)
-  __shared__ float wbuf[CHB][64];   // blend weight T alpha (0: no contribution)
+  __shared__ float abuf[CHB][64];    // raw alpha (-1: no hit / not reached)
+  __shared__ float e2buf[CHB][64];   // exp(s f_next)
+  __shared__ uint8_t sel[CHB][64];   // entry face | exit face << 2
+  __shared__ float dabuf[CHB][64];   // dL/dalpha (0 when clamped)
+  __shared__ float wbuf[CHB][64];    // blend weight T alpha
   __shared__ float gacc[CHB][TGRAD_STRIDE];
+  __shared__ float grs[8][64];       // upstream gradient of each pixel
+  __shared__ int lasts[64];
   __shared__ unsigned long long done_mask;
   __shared__ int smax;
 
@@ -220,6 +233,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const unsigned lane = threadIdx.x & 63u;
   const int wave = threadIdx.x >> 6;
 
+  // per-pixel state (wave 0): last blended entry, T before it, upstream gradient
   int last = -1;
   float Tb = 1.0f;
   if (recompute) {
@@ -227,31 +241,31 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     float acc[7];
     forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, &done_mask, T,
                             Tb, O, acc, last, false);
-    // the replayed state lives in wave 0; share `last` for the chunk bounds
-  } else if (c.inside) {
+  } else if (wave == 0 && c.inside) {
     const size_t gi = (size_t)V.pix_base + px;
     last = last_in[gi];
     Tb = tlast_in[gi];
   }
-  // every wave needs this pixel's `last`; wave 0 holds it after a replay
-  if (recompute) {
-    __syncthreads();
-    if (wave == 0) abuf[0][lane] = __int_as_float(last);
-    __syncthreads();
-    last = __float_as_int(abuf[0][lane]);
-    __syncthreads();
-  }
-
   float gr[8];
+  if (wave == 0) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
-  float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
-
-  int wmax = last;
+    for (int q = 0; q < 8; ++q) {
+      gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
+      grs[q][lane] = gr[q];
+    }
+    lasts[lane] = last;
+    int wmax = last;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
-  if (threadIdx.x == 0) smax = wmax;
+    for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+    if (lane == 0) smax = wmax;
+  }
   __syncthreads();
+  if (wave != 0) {
+    last = lasts[lane];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) gr[q] = grs[q][lane];
+  }
+  float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
   const int tmax = smax;
   const uint32_t pend = (tmax >= (int)start) ? (uint32_t)tmax + 1u : start;
   if (threadIdx.x == 0) proc_end[c.tile] = pend;
@@ -265,15 +279,22 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     __syncthreads();
     load_recs(recs, vrec, srec, base, n, NT);
     __syncthreads();
-    // phase A: raw alpha of every (entry, pixel) the pixel's walk reached
+    // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's walk reached
     for (int e = wave; e < n; e += NWV) {
-      float a = -1.0f;
+      float a = -1.0f, e2 = 0.0f;
+      uint8_t fs = 0;
       const ViewRec& R = recs[e];
       if (c.inside && (int)(base + e) <= last && has_pixel(R, c.i, c.j)) {
         PixEval h;
-        if (pixel_eval(R, qx, qy, s, h)) a = h.alpha;
+        if (pixel_eval(R, qx, qy, s, h)) {
+          a = h.alpha;
+          e2 = h.e2;
+          fs = (uint8_t)(h.fe | (h.fx << 2));
+        }
       }
       abuf[e][lane] = a;
+      e2buf[e][lane] = e2;
+      sel[e][lane] = fs;
     }
     __syncthreads();
     // phase B: reverse recurrence (one wave)
@@ -295,14 +316,14 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
           Rbehind = a * sdot + (1.0f - a) * Rbehind;
           if (araw > alpha_clamp) da = 0.0f;
         }
-        abuf[e][lane] = da;
+        dabuf[e][lane] = da;
         wbuf[e][lane] = w;
       }
     }
     __syncthreads();
     // phase C: per-entry gradients, reduced over the tile
     for (int e = wave; e < n; e += NWV) {
-      const float da = abuf[e][lane], w = wbuf[e][lane];
+      const float da = dabuf[e][lane], w = wbuf[e][lane];
       const bool contrib = (da != 0.0f) || (w != 0.0f);
       if (__ballot(contrib) == 0ull) {
         if (lane < (unsigned)TGRAD_STRIDE) gacc[e][lane] = 0.0f;
@@ -312,7 +333,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
 #pragma unroll
       for (int q = 0; q < 32; ++q) g[q] = 0.0f;
       if (contrib) {
-        const ViewRec& R = recs[e];
         g[G_C + 0] = w * gr[0];
         g[G_C + 1] = w * gr[1];
         g[G_C + 2] = w * gr[2];
@@ -320,26 +340,40 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         g[G_N + 0] = w * gr[5];
         g[G_N + 1] = w * gr[6];
         g[G_N + 2] = w * gr[7];
-        if (da != 0.0f) {
-          PixEval h;
-          pixel_eval(R, qx, qy, s, h);
-          if (h.alpha > 0.0f) {
-            const float invB = rcp(1.0f + h.e2);
-            const float dA = da * invB;
-            const float dB = -da * h.alpha * invB;
-            const float dd = dA * s * (h.e1 + 1.0f);
-            const float dfn = dB * s * h.e2 - dd;
+        const float alpha = abuf[e][lane];
+        if (da != 0.0f && alpha > 0.0f) {
+          const ViewRec& R = recs[e];
+          // alpha = A / B, A = -expm1(-s d), B = 1 + exp(s f_next)
+          const float e2 = e2buf[e][lane];
+          const float B = 1.0f + e2;
+          const float invB = rcp(B);
+          const float e1p1 = 1.0f - alpha * B;                 // exp(-s d) = 1 + expm1(-s d)
+          const float dA = da * invB;
+          const float dB = -da * alpha * invB;
+          const float dd = dA * s * e1p1;                      // d/df_prev
+          const float dfn = dB * s * e2 - dd;                  // d/df_next
+          const int fs = sel[e][lane];
+          const int fe = fs & 3, fx = fs >> 2;
+          float ax[4], ay[4];
 #pragma unroll
-            for (int F = 0; F < 4; ++F) {
-              const float wF = (h.fe == F ? dd : 0.0f) + (h.fx == F ? dfn : 0.0f);
-              if (wF != 0.0f) {
-                if (F == 0) face_grad_mw<0>(R, h, wF, g);
-                if (F == 1) face_grad_mw<1>(R, h, wF, g);
-                if (F == 2) face_grad_mw<2>(R, h, wF, g);
-                if (F == 3) face_grad_mw<3>(R, h, wF, g);
-              }
-            }
+          for (int k = 0; k < 4; ++k) {
+            ax[k] = R.px[k] - qx;
+            ay[k] = R.py[k] - qy;
           }
+          const float e01 = ax[0] * ay[1] - ay[0] * ax[1];
+          const float e02 = ax[0] * ay[2] - ay[0] * ax[2];
+          const float e03 = ax[0] * ay[3] - ay[0] * ax[3];
+          const float e12 = ax[1] * ay[2] - ay[1] * ax[2];
+          const float e13 = ax[1] * ay[3] - ay[1] * ax[3];
+          const float e23 = ax[2] * ay[3] - ay[2] * ax[3];
+          const float w0 = (fe == 0 ? dd : 0.0f) + (fx == 0 ? dfn : 0.0f);
+          const float w1 = (fe == 1 ? dd : 0.0f) + (fx == 1 ? dfn : 0.0f);
+          const float w2 = (fe == 2 ? dd : 0.0f) + (fx == 2 ? dfn : 0.0f);
+          const float w3 = (fe == 3 ? dd : 0.0f) + (fx == 3 ? dfn : 0.0f);
+          if (w0 != 0.0f) face_geom_grad<0>(R, ax, ay, e12, -e02, e01, w0, g);
+          if (w1 != 0.0f) face_geom_grad<1>(R, ax, ay, e13, -e03, e01, w1, g);
+          if (w2 != 0.0f) face_geom_grad<2>(R, ax, ay, e23, -e03, e02, w2, g);
+          if (w3 != 0.0f) face_geom_grad<3>(R, ax, ay, e23, -e13, e12, w3, g);
         }
       }
       const float tot = wave_transpose_sum32(g);

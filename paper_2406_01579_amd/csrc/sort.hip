@@ -6,8 +6,8 @@
 //               counts and the digit total; (digit start + block prefix) is
 //               every (digit, block)'s global output offset
 //   downsweep - per block, in input order, the rank of every key among the
-//               equal digits before it (wave ballots + per-wave LDS counts),
-//               then a scatter to offset + rank.
+//               equal digits before it (wave ballots + wave-private LDS
+//               counts), then a scatter to offset + rank.
 // The element count lives on the device (it is produced by earlier kernels),
 // so grids are sized for the capacity and idle blocks exit at once.
 #include "ts_internal.h"
@@ -82,6 +82,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_spine(uint32_t* hist, ui
   if (t == 0) totals[d] = tot;
 }
 
+// Each wave ranks a contiguous quarter of the block's tile with ballot
+// matching and wave-private running counts in LDS (no block barriers while
+// ranking); one exclusive prefix across the waves then turns the ranks into
+// output positions.  Input order is preserved for equal digits (stable).
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
                                                              int digit_bits, const uint32_t* __restrict__ hist,
                                                              const uint32_t* __restrict__ totals) {
   __shared__ uint32_t base[RADIX];
-  __shared__ uint32_t wcnt[WAVES][RADIX];
+  __shared__ uint32_t wrun[WAVES][RADIX];
   __shared__ uint32_t part[WAVES];
   const uint32_t n = sort_n(n_dev, cap);
   const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
@@ -108,45 +112,53 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
       if (lane >= o) x += y;
     }
     if (lane == 63) part[wave] = x;
+    for (int w = 0; w < WAVES; ++w) wrun[w][threadIdx.x] = 0;
     __syncthreads();
     uint32_t wbase = 0;
     for (int w = 0; w < wave; ++w) wbase += part[w];
     base[threadIdx.x] = wbase + x - tot + hist[(size_t)threadIdx.x * nb + b];
   }
+  // ranking: wave w owns items [b*TILE + w*SUB, b*TILE + (w+1)*SUB)
+  constexpr int SUB = SORT_ITEMS * 64;
+  const uint32_t i0 = b * SORT_TILE + wave * SUB + lane;
+  uint32_t keys[SORT_ITEMS], rank[SORT_ITEMS];
+#pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    const uint32_t i = b * SORT_TILE + it * SORT_THREADS + threadIdx.x;
+    const uint32_t i = i0 + it * 64;
     const bool valid = i < n;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? (vin ? vin[i] : i) : 0u;
-    const uint32_t digit = (key >> shift) & mask;
-    // lanes of this wave holding the same digit
+    keys[it] = valid ? kin[i] : 0u;
+    const uint32_t digit = (keys[it] >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int bit = 0; bit < digit_bits; ++bit) {
       const bool set = (digit >> bit) & 1u;
       const uint64_t bb = __ballot(set);
       peers &= set ? bb : ~bb;
     }
-    for (int d = threadIdx.x; d < WAVES * RADIX; d += SORT_THREADS) (&wcnt[0][0])[d] = 0;
-    __syncthreads();
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) {
-      uint32_t s = base[d];
-      for (int w = 0; w < WAVES; ++w) {
-        uint32_t c = wcnt[w][d];
-        wcnt[w][d] = s;
-        s += c;
-      }
-      base[d] = s;
+    const uint32_t within = (uint32_t)__popcll(peers & lt);
+    const uint32_t before = valid ? wrun[wave][digit] : 0u;   // every peer reads before the leader writes
+    rank[it] = before + within;
+    if (valid && within == 0) wrun[wave][digit] = before + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;
+    uint32_t s = base[d];
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t c = wrun[w][d];
+      wrun[w][d] = s;
+      s += c;
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t pos = wcnt[wave][digit] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const uint32_t i = i0 + it * 64;
+    if (i < n) {
+      const uint32_t digit = (keys[it] >> shift) & mask;
+      const uint32_t pos = wrun[wave][digit] + rank[it];
+      kout[pos] = keys[it];
+      vout[pos] = vin ? vin[i] : i;
     }
-    __syncthreads();
   }
 }
 }  // namespace

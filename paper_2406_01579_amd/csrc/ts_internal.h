@@ -26,7 +26,9 @@ struct DevScene {
   float s;
   int32_t block_base;   // first pre-filter block of this scene
   int32_t n_blocks;
-  int32_t pad[3];
+  int32_t view_first;   // this scene's views: scene_views[view_first .. + view_count)
+  int32_t view_count;
+  int32_t pad;
 };
 
 struct DevView {
@@ -96,7 +98,7 @@ enum { G_PX = 0, G_PY = 4, G_IZ = 8, G_F = 12, G_C = 16, G_ZT = 19, G_N = 20 };
 constexpr int PF_TILE = 1024;      // tets per pre-filter block
 constexpr int SCAN_TILE = 2048;    // items per scan block
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
+constexpr int SORT_ITEMS = 4;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 constexpr int SORT_BITS = 8;
 
@@ -105,7 +107,7 @@ struct Layout {
   int64_t kept_cap, rec_cap, entry_cap;
   int64_t pf_blocks, scan_blocks_rec, sort_blocks_max, total_tiles, total_pixels;
   int key2_bits;
-  size_t o_hdr, o_scene, o_view, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
+  size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_rec_off, o_off_sorted, o_scan_part;
   size_t o_hist;
@@ -123,8 +125,8 @@ __host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast
 // ---------------------------------------------------------------------------
 // launchers (each returns hipSuccess or the launch error)
 // ---------------------------------------------------------------------------
-hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, void* ws, const Layout& L,
-                             bool reset_header, hipStream_t st);
+hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                             void* ws, const Layout& L, bool reset_header, hipStream_t st);
 hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_sort_records(void* ws, const Layout& L, hipStream_t st);
