@@ -201,13 +201,10 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_key2b = take(4 * (size_t)entry_cap);
   L.o_val2a = take(4 * (size_t)entry_cap);
   L.o_val2b = take(4 * (size_t)entry_cap);
-  L.o_erec = take(4 * (size_t)entry_cap);
-  L.o_srec = take(4 * (size_t)entry_cap);
-  L.o_inv = take(4 * (size_t)entry_cap);
+  L.o_eflag = take((size_t)entry_cap + 4);
   L.o_ranges = take(8 * (size_t)tiles);
   L.o_tile_hist = take(4 * 2 * (size_t)TILE_BUCKETS);  // right after the ranges: cleared together
   L.o_tile_order = take(4 * (size_t)tiles);
-  L.o_proc_end = take(4 * (size_t)tiles);
   L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE * (size_t)entry_cap);
   L.o_last = take(4 * (size_t)pixels);
   L.o_tlast = take(4 * (size_t)pixels);
@@ -392,9 +389,8 @@ int render_debug_pointers(const render_scene* scenes, int n_scenes, const render
   if (!plan_layout(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, L, &why))
     return fail(RENDER_EINVAL, "%s", why);
   void* ws = const_cast<void*>(workspace);
-  const int odd = ((L.key2_bits + SORT_BITS - 1) / SORT_BITS) & 1;
-  out->tile_keys = at<const uint32_t>(ws, odd ? L.o_key2b : L.o_key2a);
-  out->entry_record = at<const int32_t>(ws, L.o_srec);
+  out->tile_keys = at<const uint32_t>(ws, sorted_tile_keys(L));
+  out->entry_record = at<const int32_t>(ws, sorted_entry_records(L));
   out->kept_tet = at<const int32_t>(ws, L.o_kept_tet);
   out->view_rec_base = at<const int32_t>(ws, L.o_view_rec_base);
   out->scene_kept_base = at<const int32_t>(ws, L.o_scene_kept_base);

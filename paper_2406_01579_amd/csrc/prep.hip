@@ -326,8 +326,8 @@ __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2
         R.rx = (uint32_t)i0 | ((uint32_t)i1 << 16);
         R.ry = (uint32_t)j0 | ((uint32_t)j1 << 16);
         R.kept = kb + k;
-        R.pad[0] = v;
-        R.pad[1] = 0;
+        R.view = v;
+        R.entry0 = 0;
         vrec[r] = R;
       }
     }
@@ -449,10 +449,10 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   const uint32_t* srec = sorted_records(ws, L);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   const uint32_t* off = at<const uint32_t>(ws, L.o_off_sorted);
-  const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
+  ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
   uint32_t* rec_off = at<uint32_t>(ws, L.o_rec_off);
   uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
-  uint32_t* erec = at<uint32_t>(ws, L.o_erec);
+  uint32_t* val2 = at<uint32_t>(ws, L.o_val2a);
   const uint32_t n = hdr->records_total;
   const uint64_t cap = (uint64_t)L.entry_cap;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
@@ -461,10 +461,11 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
     if (c == 0) continue;
     const uint32_t o = off[q];
     rec_off[r] = o;
+    vrec[r].entry0 = o;
     const ViewRec& R = vrec[r];
     int i0, i1, j0, j1;
     unpack_rect(R, i0, i1, j0, j1);
-    const DevView& V = vw[R.pad[0]];
+    const DevView& V = vw[R.view];
     const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
     const int nx = tx1 - tx0 + 1;
     for (uint32_t j = 0; j < c; ++j) {
@@ -472,7 +473,7 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
       if (d >= cap) break;
       const int ty = ty0 + (int)(j / nx), tx = tx0 + (int)(j % nx);
       key2[d] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
-      erec[d] = r;
+      val2[d] = r;
     }
   }
 }
@@ -491,33 +492,23 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
     p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(void* ws, Layout L, const uint32_t* keys, const uint32_t* vals) {
+__global__ __launch_bounds__(256) void k_finalize(void* ws, Layout L) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
-  const uint32_t* erec = at<const uint32_t>(ws, L.o_erec);
-  uint32_t* srec = at<uint32_t>(ws, L.o_srec);
-  uint32_t* inv = at<uint32_t>(ws, L.o_inv);
+  const uint32_t* keys = at<const uint32_t>(ws, sorted_tile_keys(L));
   uint32_t* ranges = at<uint32_t>(ws, L.o_ranges);
   const uint32_t n = hdr->entries_total;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
     const uint32_t t = keys[p];
-    const uint32_t d = vals[p];
-    srec[p] = erec[d];
-    inv[d] = p;
     if (p == 0 || keys[p - 1] != t) ranges[2 * (size_t)t] = p;
     if (p + 1 == n || keys[p + 1] != t) ranges[2 * (size_t)t + 1] = p + 1;
   }
 }
 
-static int passes_for(int bits) { return (bits + SORT_BITS - 1) / SORT_BITS; }
-
 hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
-  const bool odd = passes_for(L.key2_bits) & 1;
-  const uint32_t* keys = at<const uint32_t>(ws, odd ? L.o_key2b : L.o_key2a);
-  const uint32_t* vals = at<const uint32_t>(ws, odd ? L.o_val2b : L.o_val2a);
   // ranges and the tile-length histogram are adjacent: clear both
   k_fill_u32<<<256, 256, 0, st>>>(at<uint32_t>(ws, L.o_ranges),
                                   (L.o_tile_hist - L.o_ranges) / 4 + 2 * (uint64_t)TILE_BUCKETS, 0u);
-  k_finalize<<<2048, 256, 0, st>>>(ws, L, keys, vals);
+  k_finalize<<<2048, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 
@@ -594,7 +585,7 @@ hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st) {
   uint32_t *ko, *vo;
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   return radix_sort_pairs(at<uint32_t>(ws, L.o_key2a), at<uint32_t>(ws, L.o_val2a), at<uint32_t>(ws, L.o_key2b),
-                          at<uint32_t>(ws, L.o_val2b), true, &hdr->entries_total, L.entry_cap, L.key2_bits,
+                          at<uint32_t>(ws, L.o_val2b), false, &hdr->entries_total, L.entry_cap, L.key2_bits,
                           at<uint32_t>(ws, L.o_hist), L.sort_blocks_max, st, &ko, &vo);
 }
 
@@ -611,9 +602,18 @@ __global__ void k_zero_grads(void* ws, Layout L) {
   }
 }
 
+// entry flags of the last forward's entries (the backward sets the ones it reaches)
+__global__ void k_zero_eflags(void* ws, Layout L) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  uint32_t* f = at<uint32_t>(ws, L.o_eflag);
+  const uint32_t words = (hdr->entries_total + 3u) / 4u;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) f[i] = 0u;
+}
+
 hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene*, hipStream_t st) {
   dim3 grid(256, (unsigned)L.ns);
   k_zero_grads<<<grid, 256, 0, st>>>(ws, L);
+  k_zero_eflags<<<512, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 

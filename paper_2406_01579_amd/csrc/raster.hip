@@ -83,7 +83,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
-  const uint32_t* srec = at<const uint32_t>(ws, L.o_srec);
+  const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   int32_t* last_out = at<int32_t>(ws, L.o_last);
   float* tlast_out = at<float>(ws, L.o_tlast);
@@ -192,12 +192,12 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
-  const uint32_t* srec = at<const uint32_t>(ws, L.o_srec);
+  const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const int32_t* last_in = at<const int32_t>(ws, L.o_last);
   const float* tlast_in = at<const float>(ws, L.o_tlast);
-  uint32_t* proc_end = at<uint32_t>(ws, L.o_proc_end);
   float* tgrad = at<float>(ws, L.o_tgrad);
+  uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
   __shared__ ViewRec recs[CH];
   __shared__ float gacc[CH][TGRAD_STRIDE];
   __shared__ int smax[NW];
@@ -263,7 +263,6 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   }
   const int tmax = wmax;
   const uint32_t pend = (tmax >= (int)start) ? (uint32_t)tmax + 1u : start;
-  if (threadIdx.x == 0) proc_end[c.tile] = pend;
 
   bool first = true;
   float Tnext = 1.0f;
@@ -337,7 +336,18 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
       }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) tgrad[(size_t)base * TGRAD_STRIDE + q] = (&gacc[0][0])[q];
+    // each entry's gradient goes to its pre-sort slot: the record's first
+    // entry plus this tile's row-major index inside the record's tile rectangle
+    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) {
+      const int e = q / TGRAD_STRIDE, k = q - e * TGRAD_STRIDE;
+      const ViewRec& R = recs[e];
+      int i0, i1, j0, j1;
+      unpack_rect(R, i0, i1, j0, j1);
+      const int tx0 = i0 / TW, ty0 = j0 / TH, nx = i1 / TW - tx0 + 1;
+      const size_t d = (size_t)R.entry0 + (size_t)((c.ty - ty0) * nx + (c.tx - tx0));
+      tgrad[d * TGRAD_STRIDE + k] = gacc[e][k];
+      if (k == 0) eflag[d] = 1;
+    }
     __syncthreads();
   }
 }

@@ -34,6 +34,7 @@ __device__ __forceinline__ bool has_pixel(const ViewRec& R, int i, int j) {
 
 struct Tile8 {
   int view, tile;
+  int tx, ty;     // tile coordinates inside the view
   int i, j;
   bool inside;
 };
@@ -45,8 +46,10 @@ __device__ __forceinline__ Tile8 tile8(const DevView* vw, int nv, const uint32_t
   const DevView& V = vw[c.view];
   const int lt = c.tile - V.tile_base;
   const int lane = threadIdx.x & 63;
-  c.i = (lt % V.tiles_x) * 8 + (lane & 7);
-  c.j = (lt / V.tiles_x) * 8 + (lane >> 3);
+  c.tx = lt % V.tiles_x;
+  c.ty = lt / V.tiles_x;
+  c.i = c.tx * 8 + (lane & 7);
+  c.j = c.ty * 8 + (lane >> 3);
   c.inside = c.i < V.W && c.j < V.H;
   return c;
 }
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
-  const uint32_t* srec = at<const uint32_t>(ws, L.o_srec);
+  const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   int32_t* last_out = at<int32_t>(ws, L.o_last);
   float* tlast_out = at<float>(ws, L.o_tlast);
@@ -205,12 +208,12 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
-  const uint32_t* srec = at<const uint32_t>(ws, L.o_srec);
+  const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const int32_t* last_in = at<const int32_t>(ws, L.o_last);
   const float* tlast_in = at<const float>(ws, L.o_tlast);
-  uint32_t* proc_end = at<uint32_t>(ws, L.o_proc_end);
   float* tgrad = at<float>(ws, L.o_tgrad);
+  uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
   __shared__ ViewRec recs[CHB];
   __shared__ float abuf[CHB][64];    // raw alpha (-1: no hit / not reached)
   __shared__ float e2buf[CHB][64];   // exp(s f_next)
@@ -268,7 +271,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
   const int tmax = smax;
   const uint32_t pend = (tmax >= (int)start) ? (uint32_t)tmax + 1u : start;
-  if (threadIdx.x == 0) proc_end[c.tile] = pend;
 
   bool first = true;
   float Tnext = 1.0f;
@@ -381,7 +383,18 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) tgrad[(size_t)base * TGRAD_STRIDE + q] = (&gacc[0][0])[q];
+    // each entry's gradient goes to its pre-sort slot: the record's first
+    // entry plus this tile's row-major index inside the record's tile rectangle
+    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) {
+      const int e = q / TGRAD_STRIDE, k = q - e * TGRAD_STRIDE;
+      const ViewRec& R = recs[e];
+      int i0, i1, j0, j1;
+      unpack_rect(R, i0, i1, j0, j1);
+      const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
+      const size_t d = (size_t)R.entry0 + (size_t)((c.ty - ty0) * nx + (c.tx - tx0));
+      tgrad[d * TGRAD_STRIDE + k] = gacc[e][k];
+      if (k == 0) eflag[d] = 1;
+    }
   }
 }
 

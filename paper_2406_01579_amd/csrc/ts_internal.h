@@ -84,7 +84,8 @@ struct ViewRec {
   uint32_t rx;      // i0 | i1 << 16 (inclusive pixel columns)
   uint32_t ry;      // j0 | j1 << 16
   int32_t kept;     // global kept slot
-  int32_t pad[2];
+  int32_t view;
+  uint32_t entry0;  // first tile-duplicated entry of this record (set by the emit step)
 };
 static_assert(sizeof(ViewRec) == 128, "view record is 128 bytes");
 
@@ -111,13 +112,22 @@ struct Layout {
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_rec_off, o_off_sorted, o_scan_part;
   size_t o_hist;
-  size_t o_key2a, o_key2b, o_val2a, o_val2b, o_erec, o_srec, o_inv;
-  size_t o_ranges, o_tile_hist, o_tile_order, o_proc_end, o_tgrad, o_last, o_tlast;
+  size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
+  size_t o_ranges, o_tile_hist, o_tile_order, o_tgrad, o_last, o_tlast;
   size_t bytes;
 };
 
 bool plan_layout(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
                  int64_t kept_cap, int64_t entry_cap, Layout& L, const char** why);
+
+// after the tile sort (ceil(key2_bits / 8) passes, ping-pong a -> b -> a ...)
+// the sorted tile keys and their records live in one of the two buffers
+inline __host__ __device__ size_t sorted_tile_keys(const Layout& L) {
+  return (((L.key2_bits + SORT_BITS - 1) / SORT_BITS) & 1) ? L.o_key2b : L.o_key2a;
+}
+inline __host__ __device__ size_t sorted_entry_records(const Layout& L) {
+  return (((L.key2_bits + SORT_BITS - 1) / SORT_BITS) & 1) ? L.o_val2b : L.o_val2a;
+}
 
 template <class T>
 __host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }

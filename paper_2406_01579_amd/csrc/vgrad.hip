@@ -10,7 +10,7 @@
 
 namespace ts {
 
-__global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L, int tw_log2, int th_log2) {
+__global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
@@ -20,9 +20,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L, int tw_l
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const TetRec* trec = at<const TetRec>(ws, L.o_trec);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
-  const uint32_t* rec_off = at<const uint32_t>(ws, L.o_rec_off);
-  const uint32_t* inv = at<const uint32_t>(ws, L.o_inv);
-  const uint32_t* proc_end = at<const uint32_t>(ws, L.o_proc_end);
+  const uint8_t* eflag = at<const uint8_t>(ws, L.o_eflag);
   const float* tgrad = at<const float>(ws, L.o_tgrad);
   const uint32_t nk = min(hdr->kept_total, (uint32_t)L.kept_cap);
   const uint32_t nrec = hdr->records_total;
@@ -42,21 +40,17 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L, int tw_l
       if (cnt == 0) continue;
       const ViewRec& R = vrec[r];
       const DevView& V = vw[v];
-      int i0, i1, j0, j1;
-      unpack_rect(R, i0, i1, j0, j1);
-      const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
-      const int nx = tx1 - tx0 + 1;
-      const uint32_t o = rec_off[r];
+      const uint32_t o = R.entry0;
       float g[23];
       for (int z = 0; z < 23; ++z) g[z] = 0.0f;
       bool hit = false;
+      // the record's entries, one per tile it was binned to; the compositing
+      // backward flags the ones it reached
       for (uint32_t j = 0; j < cnt; ++j) {
         const uint64_t d = (uint64_t)o + j;
         if (d >= cap) break;
-        const uint32_t p = inv[d];
-        const int tile = V.tile_base + (ty0 + (int)(j / nx)) * V.tiles_x + tx0 + (int)(j % nx);
-        if (p >= proc_end[tile]) continue;
-        const float4* src = reinterpret_cast<const float4*>(tgrad + (size_t)p * TGRAD_STRIDE);
+        if (!eflag[d]) continue;
+        const float4* src = reinterpret_cast<const float4*>(tgrad + (size_t)d * TGRAD_STRIDE);
 #pragma unroll
         for (int z = 0; z < 6; ++z) {
           const float4 x = src[z];
@@ -145,8 +139,8 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L, int tw_l
 }
 
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  int twl = __builtin_ctz((unsigned)p.tile_w), thl = __builtin_ctz((unsigned)p.tile_h);
-  k_vertex_bwd<<<1024, 256, 0, st>>>(ws, L, twl, thl);
+  (void)p;
+  k_vertex_bwd<<<1024, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 
