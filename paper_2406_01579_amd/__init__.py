@@ -7,4 +7,5 @@ include/tetsplat.h (libtetsplat.so, built in-tree by
 side: argument marshalling, workspace sizing and ownership, and a
 torch.autograd.Function.
 """
-from .frontend import Params, Plan, Renderer, SceneT, TetSplatFunction, render  # noqa: F401
+from .frontend import CapacityError, Params, Plan, Renderer, SceneT, TetSplatFunction, render  # noqa: F401
+from .graph import CapturedStep  # noqa: F401

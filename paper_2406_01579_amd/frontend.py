@@ -113,6 +113,7 @@ class Plan:
     header_copy: torch.Tensor | None = None    # pinned copy of the status header (lazy check)
     header_event: object = None
     sig: tuple = ()
+    stacked: torch.Tensor | None = None          # [nv, 8, H, W] when all views share a size
 
 
 class Renderer:
@@ -124,7 +125,9 @@ class Renderer:
     copied to pinned memory without waiting and verified before the backward
     and at the next forward of the same shape; an overflow there raises
     CapacityError (never a silent wrong result), and the capacities are
-    enlarged for later calls."""
+    enlarged for later calls.  check="none": no host-side status traffic at
+    all (for stream capture); the caller reads the status itself
+    (read_status / CapturedStep.check)."""
 
     def __init__(self, params: Params | None = None, device="cuda", check: str = "sync"):
         self.params = params or Params()
@@ -146,12 +149,33 @@ class Renderer:
         return int(n.value)
 
     # -- forward ----------------------------------------------------------------
+    def set_capacity(self, scenes, cams, view_scene, kept_cap: int, entry_cap: int):
+        """Fix the capacities used for this shape of call (e.g. before capture)."""
+        cams = np.asarray(cams, np.float32)
+        if view_scene is None:
+            view_scene = np.zeros(cams.shape[0], np.int32)
+        self._caps[self._signature(scenes, cams, view_scene)] = (int(kept_cap), int(entry_cap))
+
+    def capacity(self, scenes, cams, view_scene=None):
+        cams = np.asarray(cams, np.float32)
+        if view_scene is None:
+            view_scene = np.zeros(cams.shape[0], np.int32)
+        return self._caps.get(self._signature(scenes, cams, view_scene))
+
     def forward(self, scenes, cams, view_scene=None, stream=None) -> Plan:
         cams = np.asarray(cams, np.float32)
         nv = cams.shape[0]
         if view_scene is None:
             view_scene = np.zeros(nv, np.int32)
-        outs = [torch.empty((8, int(c[1]), int(c[0])), device=self.device, dtype=torch.float32) for c in cams]
+        sizes = {(int(c[0]), int(c[1])) for c in cams}
+        if len(sizes) == 1:
+            # one [nv, 8, H, W] tensor; the views are its slices
+            W0, H0 = sizes.pop()
+            stacked = torch.empty((nv, 8, H0, W0), device=self.device, dtype=torch.float32)
+            outs = list(stacked.unbind(0))
+        else:
+            stacked = None
+            outs = [torch.empty((8, int(c[1]), int(c[0])), device=self.device, dtype=torch.float32) for c in cams]
         scene_c = (_lib.render_scene * len(scenes))(*[s.c() for s in scenes])
         view_c = make_views(cams, view_scene, outs)
         params_c = self.params.c()
@@ -168,6 +192,10 @@ class Renderer:
             check(_lib.lib().render_forward(C.byref(scene_c), len(scenes), C.byref(view_c), nv, C.byref(params_c),
                                             kept_cap, entry_cap, ws.data_ptr(), nbytes, st))
             plan = Plan(scenes, scene_c, view_c, params_c, kept_cap, entry_cap, ws, outs)
+            plan.stacked = stacked
+            self.last_plan = plan
+            if self.check == "none":
+                return plan
             if self.check != "sync" and sig in self._caps:
                 self._verify_pending()
                 plan.header_copy = torch.empty(_lib.STATUS_BYTES, dtype=torch.uint8, pin_memory=True)
@@ -292,7 +320,9 @@ class TetSplatFunction(torch.autograd.Function):
         plan = renderer.forward([scene], cams)
         ctx.plan = plan
         ctx.renderer = renderer
-        return torch.stack(plan.outs, 0) if len(plan.outs) > 1 else plan.outs[0].unsqueeze(0)
+        if plan.stacked is None:
+            raise ValueError("TetSplatFunction renders views of one size; use Renderer for mixed sizes")
+        return plan.stacked
 
     @staticmethod
     def backward(ctx, dout):

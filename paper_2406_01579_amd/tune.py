@@ -1,0 +1,126 @@
+"""Autotuner for the compositing launch shape.
+
+The knobs are the screen tile (8x8, 16x8, 8x16, 16x16, 32x8) and, for 8x8
+tiles, the number of 64-lane waves that share a tile (1, 2, 4, 8).  Every
+candidate produces the same images (the per-pixel arithmetic and blend order
+do not depend on the tiling), so the choice is purely a speed decision.
+
+The tuner times forward + backward of each candidate on the caller's actual
+scenes and views (median of a few repetitions, HIP events on the rendering
+stream) and caches the winner under a signature of the workload: the bit
+lengths of the tet count and of the kept count, the image sizes, the number
+of views and the steepness bucket.  The cache is a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import asdict
+
+import numpy as np
+
+from .frontend import Params
+
+TILES = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8)]
+WAVES = [1, 2, 4, 8]
+
+
+def candidates():
+    out = []
+    for tw, th in TILES:
+        if (tw, th) == (8, 8):
+            out += [(tw, th, w) for w in WAVES]
+        else:
+            out.append((tw, th, 1))
+    return out
+
+
+def _bits(x: int) -> int:
+    return int(x).bit_length()
+
+
+def signature(n_tets: int, n_kept: int, sizes, n_views: int, s: float) -> str:
+    """Workload bucket: tet and kept counts by bit length, distinct image
+    sizes, view count, steepness by bit length."""
+    sz = sorted({(int(w), int(h)) for w, h in sizes})
+    return json.dumps({"tets": _bits(n_tets), "kept": _bits(n_kept), "sizes": sz, "views": n_views,
+                       "s": _bits(int(round(s)))}, sort_keys=True)
+
+
+class Autotuner:
+    def __init__(self, cache_path: str | None = None, reps: int = 3, base: Params | None = None,
+                 timer=None):
+        self.cache_path = cache_path
+        self.reps = reps
+        self.base = base or Params()
+        self.cache = {}
+        self._timer = timer
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+
+    def _save(self):
+        if self.cache_path:
+            tmp = self.cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.cache_path)
+
+    def params_for(self, cand) -> Params:
+        d = asdict(self.base)
+        d.update(tile_w=cand[0], tile_h=cand[1], waves=cand[2])
+        return Params(**d)
+
+    def tune(self, key: str, measure) -> Params:
+        """measure(params) -> seconds.  Returns (and caches) the fastest."""
+        if key in self.cache:
+            return self.params_for(tuple(self.cache[key]["best"]))
+        times = {}
+        for cand in candidates():
+            t = measure(self.params_for(cand))
+            times[cand] = t
+        best = min(times, key=times.get)
+        self.cache[key] = {"best": list(best), "ms": {f"{c[0]}x{c[1]}w{c[2]}": round(1e3 * t, 4)
+                                                      for c, t in times.items()}}
+        self._save()
+        return self.params_for(best)
+
+    # ------------------------------------------------------------------
+    def best(self, scenes, cams, view_scene=None, dout=None, device="cuda") -> Params:
+        """Tune forward + backward for these device scenes and cameras."""
+        import torch
+
+        from .frontend import Renderer
+        cams = np.asarray(cams, np.float32)
+        nv = cams.shape[0]
+        if view_scene is None:
+            view_scene = np.zeros(nv, np.int32)
+        probe = Renderer(self.base, device=device, check="sync")
+        plan = probe.forward(scenes, cams, view_scene)
+        kept = int(plan.status.kept)
+        del plan
+        key = signature(sum(int(s.tets.shape[0]) for s in scenes), kept, [(c[0], c[1]) for c in cams], nv,
+                        max(float(s.s) for s in scenes))
+        douts = None
+
+        def measure(params):
+            nonlocal douts
+            r = Renderer(params, device=device, check="sync")
+            if douts is None:
+                p0 = r.forward(scenes, cams, view_scene)
+                douts = [torch.randn_like(o) for o in p0.outs] if dout is None else dout
+                del p0
+            ts = []
+            for k in range(self.reps + 1):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                p = r.forward(scenes, cams, view_scene)
+                r.backward(p, douts)
+                b.record()
+                torch.cuda.synchronize()
+                if k > 0:
+                    ts.append(a.elapsed_time(b) * 1e-3)
+            return float(np.median(ts))
+
+        return self.tune(key, self._timer or measure)
