@@ -47,6 +47,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-view path")
     ap.add_argument("--cpu-pixels", type=int, default=400000)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: 16 resident scenes, open-loop Poisson arrivals, "
+                         "continuous batching vs the plain one-launch-per-view path")
+    ap.add_argument("--serve-rates", default="50,200,500,1000,2000")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="trace length per rate")
+    ap.add_argument("--serve-max-requests", type=int, default=4000)
+    ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a device buffer of this many MiB three times (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
@@ -63,6 +70,9 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
               "build", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        return serve_bench(args)
 
     import torch
 
@@ -242,6 +252,57 @@ def main():
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items()},
         "workload_stats": {"entries": E, "entries_walked_bwd": e_proc, "kept_tets": int(stt.kept),
                            "records": int(stt.records), "tiles": tiles},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def serve_bench(args):
+    """Forward-only serving: 16 resident blob scenes (32^3..128^3 cube grids,
+    band-pruned), requests of 1-4 views at 256/512/1024 square, open-loop
+    Poisson arrivals; continuous batching over several streams vs the plain
+    path (FIFO, one launch sequence per view) on the same trace."""
+    import torch
+
+    import synth
+    from paper_2406_01579_amd import Params
+    from paper_2406_01579_amd.serve import SceneRegistry, Server
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    scenes = synth.serving_scenes(s=args.s)
+    reg = SceneRegistry(Params(waves=args.waves))
+    rng = np.random.default_rng(9)
+    for sc in scenes:
+        reg.add(sc, np.concatenate([synth.random_orbit_cameras(rng, 2, z) for z in (256, 512, 1024)], 0))
+    print(f"[serve] {len(scenes)} scenes resident ({reg.bytes / 2**20:.0f} MiB) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    # warm-up trace (allocator pools, first launches of each shape)
+    for batching in (True, False):
+        Server(reg, streams=args.serve_streams if batching else 1, batching=batching, keep_outputs=False).run(
+            synth.serving_requests(200, 1000.0, len(scenes), seed=99))
+    rows = []
+    for rate in (float(x) for x in args.serve_rates.split(",")):
+        n = int(min(args.serve_max_requests, max(50, rate * args.serve_seconds)))
+        trace = synth.serving_requests(n, rate, len(scenes))
+        row = {"rate_per_s": rate, "requests": n}
+        for name, batching in (("batched", True), ("plain", False)):
+            srv = Server(reg, streams=args.serve_streams if batching else 1, batching=batching, keep_outputs=False)
+            st = srv.run(trace)
+            row[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()
+                         if k in ("p50_ms", "p99_ms", "mean_ms", "mpix_per_s", "launches", "reruns", "batches",
+                                  "mean_views_per_batch", "max_queue", "served", "rejected")}
+            print(f"[serve] rate {rate:g}/s {name}: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms "
+                  f"{st['mpix_per_s']:.0f} Mpx/s", file=sys.stderr, flush=True)
+        rows.append(row)
+    top = rows[-1]
+    line = {
+        "metric": "serving forward Mpixels/s + p50/p99 latency vs plain path (16 resident scenes, Poisson arrivals)",
+        "value": top["batched"]["mpix_per_s"], "unit": "Mpixels/s", "n_gpus": 1, "steps": None, "warmup": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 blob scenes (32^3..128^3 cube grids, |f|<0.05 band), requests of 1-4 views at "
+                               "256/512/1024 square, open-loop Poisson arrivals, forward only, s=320",
+                   "streams": args.serve_streams, "rates": args.serve_rates, "tile": "8x8", "waves": args.waves},
+        "rates": rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -117,7 +117,8 @@ typedef struct {
  * views.  kept_capacity bounds the total number of tets kept by the
  * pre-filter (0: the sum of K over scenes, always sufficient);
  * entry_capacity bounds the number of (tet, tile) entries over all views
- * (0: 8 per (view, kept tet) record).  Pure host computation.
+ * (0: 8 per (view, kept tet) record).  Pure host computation; the views'
+ * output pointers are not read and may be NULL.
  */
 int render_workspace_size(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
                           const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
@@ -217,6 +218,45 @@ enum {
 };
 int render_profile(int enable);
 int render_profile_read(double* ms /* [RENDER_NSTAGES] */, int64_t* counts /* [RENDER_NSTAGES] */);
+
+/*
+ * Geometry regularisers (Sec. 4.2).
+ *
+ * render_mesh_edges: the unique undirected edges of a tet mesh, each once as
+ * (a, b) with a < b, in ascending (a, b) order -- the edge set of the
+ * normal-consistency term.  tets: device int32 [K][4], 16-byte aligned;
+ * a tet with an index outside [0, V) contributes no edge.  edges: device
+ * int32 [6K][2] (6K pairs always suffice); n_edges: device int32, receives
+ * the count.  Workspace from render_mesh_edges_workspace_size (device,
+ * caller-owned).  Asynchronous on stream.  Built once per topology.
+ */
+int render_mesh_edges_workspace_size(int32_t K, size_t* bytes);
+int render_mesh_edges(const int32_t* tets, int32_t K, int32_t V, int32_t* edges, int32_t* n_edges,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * render_regularizers: the eikonal term L_eik = sum over tets of
+ * (|g_k| - 1)^2, g_k the SDF gradient inside tet k (App. A.3), and the
+ * normal-consistency term L_nc = sum over edges of 1 - cos(m_a, m_b), m_v the
+ * sum of the unit normals g_k/|g_k| of the tets that contain vertex v.  Tets
+ * with a zero determinant, or an index outside [0, V), are left out of both;
+ * an edge with a zero vertex normal at either end is left out.
+ *   verts [V][3], sdf [V], tets [K][4] (16-byte aligned): device inputs;
+ *   edges / n_edges: as written by render_mesh_edges (edge_capacity bounds
+ *     the count that is read);
+ *   losses: device double[2] <- (L_eik, L_nc), unweighted; may be NULL;
+ *   dverts [V][3], dsdf [V]: device; the gradient of
+ *     weights[0] * L_eik + weights[1] * L_nc is ADDED to them (so it can
+ *     follow render_backward); both NULL for the losses alone;
+ *   weights: device float[2], read only when gradients are requested.
+ * Gradients use float atomics (reproducible to rounding, not bitwise).
+ * Asynchronous on stream; no host synchronisation, so it can be captured.
+ */
+int render_regularizers_workspace_size(int32_t V, int32_t K, size_t* bytes);
+int render_regularizers(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                        const int32_t* edges, const int32_t* n_edges, int64_t edge_capacity, const float* weights,
+                        double* losses, float* dverts, float* dsdf, void* workspace, size_t workspace_bytes,
+                        void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* render_last_error(void);

@@ -57,7 +57,8 @@ bool tile_ok(int tw, int th) {
   return k == 8008 || k == 16008 || k == 8016 || k == 16016 || k == 32008;
 }
 
-int check_args(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p) {
+int check_args(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
+               bool need_out = true) {
   if (!scenes || !views || !p) return fail(RENDER_EINVAL, "null scenes, views or params");
   if (ns <= 0 || nv <= 0) return fail(RENDER_EINVAL, "need at least one scene and one view (got %d, %d)", ns, nv);
   if (!tile_ok(p->tile_w, p->tile_h))
@@ -79,7 +80,7 @@ int check_args(const render_scene* scenes, int ns, const render_view* views, int
     if (V.scene < 0 || V.scene >= ns) return fail(RENDER_EINVAL, "view %d: scene index %d out of range", v, V.scene);
     if (V.width <= 0 || V.height <= 0 || V.width > 16384 || V.height > 16384)
       return fail(RENDER_EINVAL, "view %d: image size %dx%d out of range", v, V.width, V.height);
-    if (!V.out) return fail(RENDER_EINVAL, "view %d: null output", v);
+    if (need_out && !V.out) return fail(RENDER_EINVAL, "view %d: null output", v);
   }
   return RENDER_OK;
 }
@@ -266,10 +267,57 @@ extern "C" {
 
 const char* render_last_error(void) { return g_err.c_str(); }
 
+int render_mesh_edges_workspace_size(int32_t K, size_t* bytes) {
+  if (!bytes) return fail(RENDER_EINVAL, "null bytes");
+  if (K < 0 || K > 700000000) return fail(RENDER_EINVAL, "K out of range (%d)", K);
+  *bytes = ts::edge_layout(K).bytes;
+  return RENDER_OK;
+}
+
+int render_mesh_edges(const int32_t* tets, int32_t K, int32_t V, int32_t* edges, int32_t* n_edges, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  if (K < 0 || K > 700000000 || V < 0 || V > (1 << 30)) return fail(RENDER_EINVAL, "K or V out of range");
+  if (!n_edges || !workspace || (K > 0 && (!tets || !edges))) return fail(RENDER_EINVAL, "null pointer");
+  if (((uintptr_t)tets & 15u) != 0) return fail(RENDER_EINVAL, "tets must be 16-byte aligned");
+  if (((uintptr_t)edges & 7u) != 0) return fail(RENDER_EINVAL, "edges must be 8-byte aligned");
+  const ts::EdgeLayout E = ts::edge_layout(K);
+  if (workspace_bytes < E.bytes) return fail(RENDER_ENOSPC, "workspace %zu < %zu bytes", workspace_bytes, E.bytes);
+  hipError_t e = ts::launch_mesh_edges(tets, K, V, edges, n_edges, workspace, E, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RENDER_EHIP, "mesh edges: %s", hipGetErrorString(e));
+  return RENDER_OK;
+}
+
+int render_regularizers_workspace_size(int32_t V, int32_t K, size_t* bytes) {
+  if (!bytes) return fail(RENDER_EINVAL, "null bytes");
+  if (K < 0 || V < 0 || V > (1 << 30) || K > (1 << 30)) return fail(RENDER_EINVAL, "K or V out of range");
+  *bytes = ts::reg_layout(V).bytes;
+  return RENDER_OK;
+}
+
+int render_regularizers(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                        const int32_t* edges, const int32_t* n_edges, int64_t edge_capacity, const float* weights,
+                        double* losses, float* dverts, float* dsdf, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  if (K < 0 || V < 0 || V > (1 << 30) || K > (1 << 30)) return fail(RENDER_EINVAL, "K or V out of range");
+  if (edge_capacity < 0 || edge_capacity > 0xffffffffll) return fail(RENDER_EINVAL, "edge_capacity out of range");
+  if (!workspace || !n_edges || (K > 0 && (!verts || !tets || !sdf)) || (edge_capacity > 0 && !edges))
+    return fail(RENDER_EINVAL, "null pointer");
+  if ((dverts == nullptr) != (dsdf == nullptr)) return fail(RENDER_EINVAL, "dverts and dsdf: both or neither");
+  if (dverts && !weights) return fail(RENDER_EINVAL, "gradients need weights");
+  if (((uintptr_t)tets & 15u) != 0) return fail(RENDER_EINVAL, "tets must be 16-byte aligned");
+  if (((uintptr_t)edges & 7u) != 0) return fail(RENDER_EINVAL, "edges must be 8-byte aligned");
+  const ts::RegLayout R = ts::reg_layout(V);
+  if (workspace_bytes < R.bytes) return fail(RENDER_ENOSPC, "workspace %zu < %zu bytes", workspace_bytes, R.bytes);
+  hipError_t e = ts::launch_regularizers(verts, tets, sdf, V, K, edges, n_edges, edge_capacity, weights, losses,
+                                         dverts, dsdf, workspace, R, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RENDER_EHIP, "regularizers: %s", hipGetErrorString(e));
+  return RENDER_OK;
+}
+
 int render_workspace_size(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
                           const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
                           size_t* bytes) {
-  int rc = check_args(scenes, n_scenes, views, n_views, params);
+  int rc = check_args(scenes, n_scenes, views, n_views, params, false);
   if (rc) return rc;
   if (!bytes) return fail(RENDER_EINVAL, "null bytes");
   Layout L;

@@ -162,4 +162,23 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
                             const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
                             hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
 
+// unique-edge build and the Sec. 4.2 regularisers (reg.hip)
+struct EdgeLayout {
+  uint64_t n;            // 6 K candidate pairs
+  uint64_t sort_blocks, edge_blocks;
+  size_t o_n, o_ka, o_va, o_kb, o_vb, o_hist, o_bsum, bytes;
+};
+struct RegLayout {
+  size_t o_m, o_dm, o_part, bytes;
+  int blocks;
+};
+EdgeLayout edge_layout(int32_t K);
+hipError_t launch_mesh_edges(const int32_t* tets, int32_t K, int32_t V, int32_t* edges, int32_t* n_edges, void* ws,
+                             const EdgeLayout& E, hipStream_t st);
+RegLayout reg_layout(int32_t V);
+hipError_t launch_regularizers(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                               const int32_t* edges, const int32_t* n_edges, int64_t edge_cap, const float* weights,
+                               double* losses, float* dverts, float* dsdf, void* ws, const RegLayout& R,
+                               hipStream_t st);
+
 }  // namespace ts

@@ -162,7 +162,8 @@ class Renderer:
             view_scene = np.zeros(cams.shape[0], np.int32)
         return self._caps.get(self._signature(scenes, cams, view_scene))
 
-    def forward(self, scenes, cams, view_scene=None, stream=None) -> Plan:
+    def forward(self, scenes, cams, view_scene=None, stream=None, caps=None) -> Plan:
+        """caps=(kept_cap, entry_cap) overrides the remembered capacities."""
         cams = np.asarray(cams, np.float32)
         nv = cams.shape[0]
         if view_scene is None:
@@ -181,7 +182,7 @@ class Renderer:
         params_c = self.params.c()
         st = torch.cuda.current_stream(self.device).cuda_stream if stream is None else stream
         sig = self._signature(scenes, cams, view_scene)
-        kept_cap, entry_cap = self._caps.get(sig, (0, 0))
+        kept_cap, entry_cap = self._caps.get(sig, (0, 0)) if caps is None else (int(caps[0]), int(caps[1]))
         if entry_cap == 0:
             # first sight of this shape: generous bound, refined after the call
             rec = sum(int(scenes[int(view_scene[v])].tets.shape[0]) for v in range(nv))

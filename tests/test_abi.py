@@ -190,3 +190,25 @@ def test_product_path_has_no_cpu_fallback():
             _lib.lib()
     finally:
         _lib.LIB_PATH, _lib._lib = saved
+
+
+def test_regularizer_entry_points_validate_on_the_host(L):
+    lib = L.lib()
+    n = C.c_size_t(0)
+    assert lib.render_mesh_edges_workspace_size(1000, C.byref(n)) == L.RENDER_OK and n.value > 4 * 4 * 6000
+    assert lib.render_mesh_edges_workspace_size(-1, C.byref(n)) == L.RENDER_EINVAL
+    assert lib.render_regularizers_workspace_size(100, 300, C.byref(n)) == L.RENDER_OK
+    need = n.value
+    assert need >= 2 * 4 * 3 * 100
+    ws = 1 << 20
+    # unaligned tets, null count, too small a workspace
+    assert lib.render_mesh_edges(4100, 10, 20, 8192, 4096, ws, 1 << 20, None) == L.RENDER_EINVAL
+    assert lib.render_mesh_edges(4096, 10, 20, 8192, None, ws, 1 << 20, None) == L.RENDER_EINVAL
+    assert lib.render_mesh_edges(4096, 10, 20, 8192, 4096, ws, 16, None) == L.RENDER_ENOSPC
+    # gradients: both buffers or neither, and weights with them
+    args = [4096, 8192, 12288, 100, 300, 16384, 20480, 1800]
+    assert lib.render_regularizers(*args, None, None, 24576, None, ws, need, None) == L.RENDER_EINVAL
+    assert lib.render_regularizers(*args, None, None, 24576, 28672, ws, need, None) == L.RENDER_EINVAL
+    assert lib.render_regularizers(*args, 32768, None, 24576, 28672, ws, need - 256, None) == L.RENDER_ENOSPC
+    assert lib.render_regularizers(*args[:5], 16388, 20480, 1800, None, None, None, None, ws, need,
+                                   None) == L.RENDER_EINVAL
