@@ -258,6 +258,30 @@ int render_regularizers(const float* verts, const int32_t* tets, const float* sd
                         double* losses, float* dverts, float* dsdf, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/*
+ * render_marching_tets: triangle mesh of the zero level set (Marching
+ * Tetrahedra, the mesh extraction of Sec. 4.1).  A vertex is inside when
+ * f < 0.  Every edge of `edges` (as written by render_mesh_edges for the
+ * same tets) whose ends differ in that test carries one surface vertex at
+ * the zero of the linear interpolant, p = x_a + t (x_b - x_a),
+ * t = f_a / (f_a - f_b); vertices are numbered in edge order.  A tet with
+ * one or three inside vertices gives one triangle, with two inside a quad
+ * split into two triangles; triangles are in tet order and wind outward
+ * (normal from the inside vertices to the outside ones).
+ *   out_verts: device float [vert_capacity][3]; out_tris: device int32
+ *   [tri_capacity][3] (indices into out_verts); counts: device int32[2] <-
+ *   (vertices, triangles) -- the full counts, also when they exceed the
+ *   capacities (then only the first `capacity` items are written);
+ *   vert_capacity <= edge count and tri_capacity <= 2 K always suffice.
+ * Tets with an index outside [0, V) give no triangle.  Asynchronous on
+ * stream; workspace from render_marching_tets_workspace_size.
+ */
+int render_marching_tets_workspace_size(int32_t K, int64_t edge_capacity, size_t* bytes);
+int render_marching_tets(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                         const int32_t* edges, const int32_t* n_edges, int64_t edge_capacity, float* out_verts,
+                         int64_t vert_capacity, int32_t* out_tris, int64_t tri_capacity, int32_t* counts,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* render_last_error(void);
 

@@ -287,6 +287,35 @@ int render_mesh_edges(const int32_t* tets, int32_t K, int32_t V, int32_t* edges,
   return RENDER_OK;
 }
 
+int render_marching_tets_workspace_size(int32_t K, int64_t edge_capacity, size_t* bytes) {
+  if (!bytes) return fail(RENDER_EINVAL, "null bytes");
+  if (K < 0 || K > (1 << 30) || edge_capacity < 0 || edge_capacity > 0x7fffffffll)
+    return fail(RENDER_EINVAL, "K or edge_capacity out of range");
+  *bytes = ts::mt_layout(K, edge_capacity).bytes;
+  return RENDER_OK;
+}
+
+int render_marching_tets(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                         const int32_t* edges, const int32_t* n_edges, int64_t edge_capacity, float* out_verts,
+                         int64_t vert_capacity, int32_t* out_tris, int64_t tri_capacity, int32_t* counts,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+  if (K < 0 || V < 0 || V > (1 << 30) || K > (1 << 30)) return fail(RENDER_EINVAL, "K or V out of range");
+  if (edge_capacity < 0 || edge_capacity > 0x7fffffffll || vert_capacity < 0 || tri_capacity < 0)
+    return fail(RENDER_EINVAL, "capacity out of range");
+  if (!counts || !n_edges || !workspace || (K > 0 && (!verts || !tets || !sdf)) || (edge_capacity > 0 && !edges) ||
+      (vert_capacity > 0 && !out_verts) || (tri_capacity > 0 && !out_tris))
+    return fail(RENDER_EINVAL, "null pointer");
+  if (((uintptr_t)tets & 15u) != 0) return fail(RENDER_EINVAL, "tets must be 16-byte aligned");
+  if (((uintptr_t)edges & 7u) != 0) return fail(RENDER_EINVAL, "edges must be 8-byte aligned");
+  const ts::MTLayout M = ts::mt_layout(K, edge_capacity);
+  if (workspace_bytes < M.bytes) return fail(RENDER_ENOSPC, "workspace %zu < %zu bytes", workspace_bytes, M.bytes);
+  hipError_t e = ts::launch_marching_tets(verts, tets, sdf, V, K, edges, n_edges, edge_capacity, out_verts,
+                                          vert_capacity, out_tris, tri_capacity, counts, workspace, M,
+                                          (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RENDER_EHIP, "marching tets: %s", hipGetErrorString(e));
+  return RENDER_OK;
+}
+
 int render_regularizers_workspace_size(int32_t V, int32_t K, size_t* bytes) {
   if (!bytes) return fail(RENDER_EINVAL, "null bytes");
   if (K < 0 || V < 0 || V > (1 << 30) || K > (1 << 30)) return fail(RENDER_EINVAL, "K or V out of range");

@@ -18,6 +18,14 @@
 // The unique-edge list is built once per topology: the six (a < b) pairs of
 // every tet are sorted by b and then stably by a with the LSD radix sort, and
 // a flag/scan/scatter pass keeps the first of each run.
+//
+// Marching Tetrahedra (the mesh extraction of Sec. 4.1): a flag/scan/scatter
+// pass over the edges places one surface vertex on every edge whose ends
+// differ in the inside test (f < 0), numbered in edge order; a second one
+// over the tets writes one triangle (one or three inside vertices) or two
+// (two inside) in tet order, looking the crossed edges up in the sorted edge
+// list by binary search.  The winding is fixed by a 16-entry case table built
+// at compile time (outward normals, flipped for negatively oriented tets).
 #include <algorithm>
 
 #include "ts_device.h"
@@ -339,6 +347,193 @@ __global__ __launch_bounds__(RT) void k_reg_tet_bwd(const float* verts, const in
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Marching Tetrahedra
+// ---------------------------------------------------------------------------
+struct MTCase {
+  uint8_t ntri;   // 0, 1 or 2
+  uint8_t o[4];   // local vertex order (i, j, k, l), an even permutation
+  uint8_t rev;    // reverse the winding (lone outside vertex)
+};
+struct MTTable {
+  MTCase c[16];
+};
+
+constexpr MTTable make_mt_table() {
+  MTTable T{};
+  for (int m = 0; m < 16; ++m) {
+    const int cnt = (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1);
+    MTCase c{};
+    int o[4] = {0, 1, 2, 3};
+    int n = 0;
+    if (cnt == 1 || cnt == 3) {
+      const int want = cnt == 1 ? 1 : 0;
+      for (int q = 0; q < 4; ++q)
+        if (((m >> q) & 1) == want) o[n++] = q;
+      for (int q = 0; q < 4; ++q)
+        if (((m >> q) & 1) != want) o[n++] = q;
+      c.ntri = 1;
+      c.rev = cnt == 3;
+    } else if (cnt == 2) {
+      for (int q = 0; q < 4; ++q)
+        if ((m >> q) & 1) o[n++] = q;
+      for (int q = 0; q < 4; ++q)
+        if (!((m >> q) & 1)) o[n++] = q;
+      c.ntri = 2;
+    }
+    int inv = 0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) inv += o[a] > o[b];
+    if (inv & 1) {
+      const int t = o[2];
+      o[2] = o[3];
+      o[3] = t;
+    }
+    for (int q = 0; q < 4; ++q) c.o[q] = (uint8_t)o[q];
+    T.c[m] = c;
+  }
+  return T;
+}
+__constant__ MTTable c_mt = make_mt_table();
+
+__global__ __launch_bounds__(RT) void k_mt_edge_pass(const float* verts, const float* sdf, int32_t V,
+                                                     const int32_t* edges, const int32_t* n_edges, uint32_t cap,
+                                                     uint32_t* bsum, int32_t* vid, float* out, uint32_t vcap,
+                                                     int write) {
+  __shared__ uint32_t lds[RT / 64];
+  const uint32_t ne = min((uint32_t)max(n_edges[0], 0), cap);
+  const uint32_t j0 = blockIdx.x * EDGE_TILE + threadIdx.x * EDGE_ITEMS;
+  uint32_t bits = 0;
+  int2 ab[EDGE_ITEMS];
+#pragma unroll
+  for (int t = 0; t < EDGE_ITEMS; ++t) {
+    const uint32_t j = j0 + t;
+    ab[t] = make_int2(-1, -1);
+    if (j < ne) {
+      const int2 e = reinterpret_cast<const int2*>(edges)[j];
+      if ((uint32_t)e.x < (uint32_t)V && (uint32_t)e.y < (uint32_t)V) {
+        ab[t] = e;
+        if ((sdf[e.x] < 0.0f) != (sdf[e.y] < 0.0f)) bits |= 1u << t;
+      }
+    }
+  }
+  uint32_t tot;
+  const uint32_t base = block_scan_excl(__popc(bits), lds, &tot);
+  if (!write) {
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    return;
+  }
+  uint32_t o = bsum[blockIdx.x] + base;
+#pragma unroll
+  for (int t = 0; t < EDGE_ITEMS; ++t) {
+    const uint32_t j = j0 + t;
+    if (j >= ne) continue;
+    if (!(bits & (1u << t))) {
+      vid[j] = -1;
+      continue;
+    }
+    vid[j] = (int32_t)o;
+    if (o < vcap) {
+      const float fa = sdf[ab[t].x], fb = sdf[ab[t].y];
+      const float tt = fa / (fa - fb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float xa = verts[3 * (size_t)ab[t].x + c], xb = verts[3 * (size_t)ab[t].y + c];
+        out[3 * (size_t)o + c] = xa + tt * (xb - xa);
+      }
+    }
+    ++o;
+  }
+}
+
+// index of edge (a, b) in the sorted list, -1 if absent
+__device__ __forceinline__ int32_t find_edge(const int32_t* edges, uint32_t ne, int32_t a, int32_t b) {
+  const int2* E = reinterpret_cast<const int2*>(edges);
+  uint32_t lo = 0, hi = ne;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    const int2 e = E[mid];
+    if (e.x < a || (e.x == a && e.y < b))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < ne && E[lo].x == a && E[lo].y == b) ? (int32_t)lo : -1;
+}
+
+__device__ __forceinline__ int32_t surf_vertex(const int32_t* edges, uint32_t ne, const int32_t* vid, int32_t u,
+                                               int32_t w) {
+  const int32_t e = find_edge(edges, ne, min(u, w), max(u, w));
+  return e < 0 ? -1 : vid[e];
+}
+
+__global__ __launch_bounds__(RT) void k_mt_tet_pass(const float* verts, const int32_t* tets, const float* sdf,
+                                                    int32_t V, uint32_t K, const int32_t* edges,
+                                                    const int32_t* n_edges, uint32_t cap, const int32_t* vid,
+                                                    uint32_t* bsum, int32_t* tris, uint32_t tcap, int write) {
+  __shared__ uint32_t lds[RT / 64];
+  const uint32_t k0 = blockIdx.x * EDGE_TILE + threadIdx.x * EDGE_ITEMS;
+  uint32_t mask[EDGE_ITEMS];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int t = 0; t < EDGE_ITEMS; ++t) {
+    const uint32_t k = k0 + t;
+    mask[t] = 0;
+    if (k < K) {
+      int32_t v[4];
+      if (load_tet(tets, k, V, v))
+        mask[t] = (sdf[v[0]] < 0.0f ? 1u : 0u) | (sdf[v[1]] < 0.0f ? 2u : 0u) | (sdf[v[2]] < 0.0f ? 4u : 0u) |
+                  (sdf[v[3]] < 0.0f ? 8u : 0u);
+    }
+    cnt += c_mt.c[mask[t]].ntri;
+  }
+  uint32_t tot;
+  const uint32_t base = block_scan_excl(cnt, lds, &tot);
+  if (!write) {
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    return;
+  }
+  const uint32_t ne = min((uint32_t)max(n_edges[0], 0), cap);
+  uint32_t o = bsum[blockIdx.x] + base;
+#pragma unroll 1
+  for (int t = 0; t < EDGE_ITEMS; ++t) {
+    const MTCase c = c_mt.c[mask[t]];
+    if (c.ntri == 0) continue;
+    int32_t v[4];
+    load_tet(tets, k0 + t, V, v);
+    // orientation of the tet: sign of det[x1 - x0, x2 - x0, x3 - x0]
+    float e[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) e[a][m] = verts[3 * (size_t)v[a + 1] + m] - verts[3 * (size_t)v[0] + m];
+    const float det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) +
+                      e[0][1] * (e[1][2] * e[2][0] - e[1][0] * e[2][2]) +
+                      e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    const bool flip = det < 0.0f;
+    const int32_t i = v[c.o[0]], j = v[c.o[1]], kk = v[c.o[2]], l = v[c.o[3]];
+    int32_t tri[2][3];
+    if (c.ntri == 1) {
+      tri[0][0] = surf_vertex(edges, ne, vid, i, j);
+      tri[0][1] = surf_vertex(edges, ne, vid, i, kk);
+      tri[0][2] = surf_vertex(edges, ne, vid, i, l);
+    } else {
+      const int32_t ik = surf_vertex(edges, ne, vid, i, kk), il = surf_vertex(edges, ne, vid, i, l);
+      const int32_t jl = surf_vertex(edges, ne, vid, j, l), jk = surf_vertex(edges, ne, vid, j, kk);
+      tri[0][0] = ik; tri[0][1] = il; tri[0][2] = jl;
+      tri[1][0] = ik; tri[1][1] = jl; tri[1][2] = jk;
+    }
+    const bool rev = flip != (c.rev != 0);
+    for (int q = 0; q < c.ntri; ++q, ++o) {
+      if (o >= tcap) continue;
+      tris[3 * (size_t)o + 0] = tri[q][0];
+      tris[3 * (size_t)o + 1] = rev ? tri[q][2] : tri[q][1];
+      tris[3 * (size_t)o + 2] = rev ? tri[q][1] : tri[q][2];
+    }
+  }
+}
+
 __global__ __launch_bounds__(RT) void k_reg_losses(const float* part, int nb, double* losses) {
   __shared__ double lds[2][RT / 64];
   double s0 = 0.0, s1 = 0.0;
@@ -451,6 +646,44 @@ hipError_t launch_regularizers(const float* verts, const int32_t* tets, const fl
                                       part + R.blocks);
   if (bwd) k_reg_tet_bwd<<<R.blocks, RT, 0, st>>>(verts, tets, sdf, V, (uint32_t)K, dm, weights, dverts, dsdf);
   if (losses) k_reg_losses<<<1, RT, 0, st>>>(part, R.blocks, losses);
+  return hipGetLastError();
+}
+
+MTLayout mt_layout(int32_t K, int64_t edge_cap) {
+  MTLayout M{};
+  M.edge_blocks = ((uint64_t)edge_cap + EDGE_TILE - 1) / EDGE_TILE;
+  M.tet_blocks = ((uint64_t)K + EDGE_TILE - 1) / EDGE_TILE;
+  size_t o = 0;
+  M.o_vid = o; o += al(4 * (size_t)edge_cap);
+  M.o_bsum_e = o; o += al(4 * ((size_t)M.edge_blocks + 1));
+  M.o_bsum_t = o; o += al(4 * ((size_t)M.tet_blocks + 1));
+  M.bytes = o;
+  return M;
+}
+
+hipError_t launch_marching_tets(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                                const int32_t* edges, const int32_t* n_edges, int64_t edge_cap, float* out_verts,
+                                int64_t vert_cap, int32_t* out_tris, int64_t tri_cap, int32_t* counts, void* ws,
+                                const MTLayout& M, hipStream_t st) {
+  char* w = static_cast<char*>(ws);
+  int32_t* vid = reinterpret_cast<int32_t*>(w + M.o_vid);
+  uint32_t* be = reinterpret_cast<uint32_t*>(w + M.o_bsum_e);
+  uint32_t* bt = reinterpret_cast<uint32_t*>(w + M.o_bsum_t);
+  const unsigned ne = (unsigned)M.edge_blocks, nt = (unsigned)M.tet_blocks;
+  const uint32_t vc = (uint32_t)std::min<int64_t>(vert_cap, 0xffffffffll);
+  const uint32_t tc = (uint32_t)std::min<int64_t>(tri_cap, 0xffffffffll);
+  if (ne > 0)
+    k_mt_edge_pass<<<ne, RT, 0, st>>>(verts, sdf, V, edges, n_edges, (uint32_t)edge_cap, be, vid, out_verts, vc, 0);
+  k_edge_spine<<<1, 1024, 0, st>>>(be, ne, counts);
+  if (ne > 0)
+    k_mt_edge_pass<<<ne, RT, 0, st>>>(verts, sdf, V, edges, n_edges, (uint32_t)edge_cap, be, vid, out_verts, vc, 1);
+  if (nt > 0)
+    k_mt_tet_pass<<<nt, RT, 0, st>>>(verts, tets, sdf, V, (uint32_t)K, edges, n_edges, (uint32_t)edge_cap, vid, bt,
+                                     out_tris, tc, 0);
+  k_edge_spine<<<1, 1024, 0, st>>>(bt, nt, counts + 1);
+  if (nt > 0)
+    k_mt_tet_pass<<<nt, RT, 0, st>>>(verts, tets, sdf, V, (uint32_t)K, edges, n_edges, (uint32_t)edge_cap, vid, bt,
+                                     out_tris, tc, 1);
   return hipGetLastError();
 }
 

@@ -162,7 +162,7 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
                             const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
                             hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
 
-// unique-edge build and the Sec. 4.2 regularisers (reg.hip)
+// unique-edge build, the Sec. 4.2 regularisers and Marching Tetrahedra (geom.hip)
 struct EdgeLayout {
   uint64_t n;            // 6 K candidate pairs
   uint64_t sort_blocks, edge_blocks;
@@ -180,5 +180,14 @@ hipError_t launch_regularizers(const float* verts, const int32_t* tets, const fl
                                const int32_t* edges, const int32_t* n_edges, int64_t edge_cap, const float* weights,
                                double* losses, float* dverts, float* dsdf, void* ws, const RegLayout& R,
                                hipStream_t st);
+struct MTLayout {
+  uint64_t edge_blocks, tet_blocks;
+  size_t o_vid, o_bsum_e, o_bsum_t, bytes;
+};
+MTLayout mt_layout(int32_t K, int64_t edge_cap);
+hipError_t launch_marching_tets(const float* verts, const int32_t* tets, const float* sdf, int32_t V, int32_t K,
+                                const int32_t* edges, const int32_t* n_edges, int64_t edge_cap, float* out_verts,
+                                int64_t vert_cap, int32_t* out_tris, int64_t tri_cap, int32_t* counts, void* ws,
+                                const MTLayout& M, hipStream_t st);
 
 }  // namespace ts
