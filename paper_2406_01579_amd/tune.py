@@ -14,7 +14,6 @@ of views and the steepness bucket.  The cache is a JSON file.
 from __future__ import annotations
 
 import json
-import math
 import os
 from dataclasses import asdict
 
@@ -106,7 +105,9 @@ class Autotuner:
 
         def measure(params):
             nonlocal douts
-            r = Renderer(params, device=device, check="sync")
+            # the first call sizes the workspace synchronously, the timed ones
+            # check their status without waiting
+            r = Renderer(params, device=device, check="lazy")
             if douts is None:
                 p0 = r.forward(scenes, cams, view_scene)
                 douts = [torch.randn_like(o) for o in p0.outs] if dout is None else dout

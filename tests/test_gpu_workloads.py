@@ -1,0 +1,142 @@
+"""Parity at the full sizes of the batched and multi-scene workloads, in the
+launch the benchmark times (every view of every scene in one launch
+sequence): sampled pixels against the float32 oracle (1e-5 max-abs, with the
+float64 error printed) and gradients of a sparse upstream gradient (the
+oracle computes that backward exactly at full size).
+
+  batched:     128^3 blob grid pruned to the |f| < 0.05 band (662,683 tets),
+               8 views at 1024^2;
+  multi-scene: 32 blob scenes of 32^3..128^3 cube grids (5.55 M tets), 124
+               views at 256..1024 square, 1-8 per scene.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import IMG_TOL, check_gradient, compare_images, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def batched():
+    return synth.batched()
+
+
+@pytest.fixture(scope="module")
+def multiscene():
+    return synth.multiscene()
+
+
+def _render(w, P):
+    import torch
+    from paper_2406_01579_amd import Renderer, SceneT
+    r = Renderer(P)
+    scenes = [SceneT.from_numpy(s) for s in w.scenes]
+    plan = r.forward(scenes, w.cams, w.view_scene)
+    torch.cuda.synchronize()
+    return r, plan, [o.cpu().numpy() for o in plan.outs]
+
+
+def _pick(imgs, views, n_cov, n_any, seed):
+    """(view, i, j) samples: n_any uniform over the views, n_cov on covered pixels."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_any):
+        v = int(rng.choice(views))
+        H, W = imgs[v].shape[1:]
+        out.append((v, int(rng.integers(0, W)), int(rng.integers(0, H))))
+    cov = [(v, i, j) for v in views for (j, i) in np.argwhere(imgs[v][3] > 0.01)[::7]]
+    for k in rng.choice(len(cov), min(n_cov, len(cov)), replace=False):
+        out.append(cov[k])
+    return np.ascontiguousarray(np.array(out, np.int32).reshape(-1, 3))
+
+
+def _check_scene_pixels(w, s_idx, imgs, P, n_cov, n_any, seed, label):
+    views = np.nonzero(w.view_scene == s_idx)[0]
+    cams = w.cams[views]
+    pix = _pick(imgs, views, n_cov, n_any, seed)
+    local = pix.copy()
+    local[:, 0] = np.searchsorted(views, pix[:, 0])
+    g = oracle.Geometry.of(w.scenes[s_idx])
+    op = oracle_params(P, w.scenes[s_idx].s)
+    sub = [imgs[v] for v in views]
+    err, n_ex, n = compare_images(sub, g, cams, op, w.scenes[s_idx].s, pix=local)
+    got = np.stack([sub[v][:, j, i] for (v, i, j) in local], 0)
+    e64 = np.abs(got - oracle.render(g, cams, op, local, prec=64)).max()
+    print(f"{label}: {n} pixels, max-abs vs f32 {err:.2e} (excluded {n_ex}), vs f64 {e64:.2e}")
+    assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n))
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_batched_sampled_pixels(batched, tile):
+    from paper_2406_01579_amd import Params
+    P = Params(tile_w=tile[0], tile_h=tile[1])
+    _, _, imgs = _render(batched, P)
+    _check_scene_pixels(batched, 0, imgs, P, 1500, 1500, 5, f"batched {tile}")
+
+
+def _sparse_backward(w, r, plan, imgs, scenes, P, seed, label):
+    import torch
+    rng = np.random.default_rng(seed)
+    douts = [np.zeros_like(im) for im in imgs]
+    per_scene = {}
+    for s_idx in scenes:
+        views = np.nonzero(w.view_scene == s_idx)[0]
+        pix = _pick(imgs, views, 600, 0, seed + s_idx)
+        key = pix[:, 0].astype(np.int64) * (1 << 40) + pix[:, 2].astype(np.int64) * (1 << 20) + pix[:, 1]
+        _, first = np.unique(key, return_index=True)
+        pix = pix[np.sort(first)]
+        vals = rng.normal(size=(len(pix), 8)).astype(np.float32)
+        for (v, i, j), x in zip(pix, vals):
+            douts[v][:, j, i] = x
+        local = pix.copy()
+        local[:, 0] = np.searchsorted(views, pix[:, 0])
+        per_scene[s_idx] = (views, local, vals.astype(np.float64))
+    grads = r.backward(plan, [torch.from_numpy(d).cuda() for d in douts])
+    torch.cuda.synchronize()
+    for s_idx in range(len(w.scenes)):
+        got = [t.cpu().numpy() for t in grads[s_idx]]
+        if s_idx not in per_scene:
+            assert all(not np.any(x) for x in got), s_idx       # no upstream gradient, no gradient
+            continue
+        views, local, vals = per_scene[s_idx]
+        g = oracle.Geometry.of(w.scenes[s_idx])
+        op = oracle_params(P, w.scenes[s_idx].s)
+        ref32 = oracle.backward(g, w.cams[views], op, local, vals, prec=32)
+        ref64 = oracle.backward(g, w.cams[views], op, local, vals, prec=64)
+        for name, a, r32, r64 in zip(("dverts", "dsdf", "dcolors"), got, ref32, ref64):
+            check_gradient(name, a, r32, r64, f"{label} scene {s_idx}")
+
+
+def test_batched_gradients_of_sparse_upstream(batched):
+    from paper_2406_01579_amd import Params
+    P = Params()
+    r, plan, imgs = _render(batched, P)
+    _sparse_backward(batched, r, plan, imgs, [0], P, 21, "batched")
+
+
+def test_multiscene_sampled_pixels_all_scenes_in_one_launch(multiscene):
+    from paper_2406_01579_amd import Params
+    P = Params()
+    _, _, imgs = _render(multiscene, P)
+    for s_idx in range(len(multiscene.scenes)):
+        _check_scene_pixels(multiscene, s_idx, imgs, P, 60, 40, 100 + s_idx, f"multiscene scene {s_idx}")
+
+
+def test_multiscene_gradients_of_sparse_upstream(multiscene):
+    from paper_2406_01579_amd import Params
+    P = Params()
+    r, plan, imgs = _render(multiscene, P)
+    # smallest, largest and two in between, by tet count
+    order = np.argsort([s.tets.shape[0] for s in multiscene.scenes])
+    pick = [int(order[0]), int(order[len(order) // 3]), int(order[2 * len(order) // 3]), int(order[-1])]
+    _sparse_backward(multiscene, r, plan, imgs, pick, P, 31, "multiscene")
