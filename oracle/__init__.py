@@ -22,7 +22,7 @@ _lib = None
 
 # (tile_w, tile_h, alpha_min, alpha_clamp, t_min, prefilter_tf)
 DEFAULT = dict(tile_w=16, tile_h=16, alpha_min=1.0 / 255.0, alpha_clamp=0.99, t_min=1e-4,
-               prefilter_tf=1.0 / 255.0)
+               prefilter_tf=1.0 / 255.0, window=0)
 # thresholds off: the rendered function is piecewise smooth
 EXACT = dict(DEFAULT, alpha_min=0.0, alpha_clamp=1.0, t_min=0.0)
 
@@ -51,7 +51,7 @@ def lib():
         L.oracle_binning.argtypes = [P, P, P, C.c_int, C.c_int, P, C.c_int, P, C.c_long, P, P, P, P, P]
         L.oracle_binning.restype = C.c_long
         L.oracle_pixel_trace.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, C.c_int,
-                                         C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]
+                                         C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P]
         L.oracle_tet_pixel.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P]
         L.oracle_alpha.argtypes = [C.c_double, C.c_double, C.c_double]
         L.oracle_alpha.restype = C.c_double
@@ -77,7 +77,7 @@ def params_array(s: float, **kw) -> np.ndarray:
     d = dict(DEFAULT)
     d.update(kw)
     return np.array([d["tile_w"], d["tile_h"], d["alpha_min"], d["alpha_clamp"], d["t_min"],
-                     d["prefilter_tf"], s], dtype=np.float32)
+                     d["prefilter_tf"], s, d["window"]], dtype=np.float32)
 
 
 class Geometry:
@@ -202,12 +202,12 @@ def binning(g: Geometry, cams, params, want_rect: bool = False):
 def pixel_trace(g: Geometry, cams, params, view, i, j, prec: int = 64, cap: int = 4096):
     cams = np.ascontiguousarray(cams, dtype=np.float32)
     tid = np.zeros(cap, np.int32)
-    a, T, ar, fp, fn = (np.zeros(cap, np.float64) for _ in range(5))
+    a, T, ar, fp, fn, zi = (np.zeros(cap, np.float64) for _ in range(6))
     n = lib().oracle_pixel_trace(prec, _p(g.verts), _p(g.tets), _p(g.sdf), _p(g.colors), g.V, g.K, _p(cams),
                                  cams.shape[0], _p(params), view, i, j, cap, _p(tid), _p(a), _p(T), _p(ar),
-                                 _p(fp), _p(fn))
+                                 _p(fp), _p(fn), _p(zi))
     n = min(n, cap)
-    return dict(tet=tid[:n], alpha=a[:n], T=T[:n], alpha_raw=ar[:n], fprev=fp[:n], fnext=fn[:n])
+    return dict(tet=tid[:n], alpha=a[:n], T=T[:n], alpha_raw=ar[:n], fprev=fp[:n], fnext=fn[:n], zin=zi[:n])
 
 
 def tet_pixel(px, py, Z, f, qx, qy, s):

@@ -119,9 +119,10 @@ Cam load_cam(const float* r) {
 struct Params {
   int tile_w, tile_h;
   float alpha_min, alpha_clamp, t_min, prefilter_tf, s;
+  int window;  // per-pixel resort window N_w (Sec. 3.3); 0: off
 };
 Params load_params(const float* p) {
-  return Params{(int)p[0], (int)p[1], p[2], p[3], p[4], p[5], p[6]};
+  return Params{(int)p[0], (int)p[1], p[2], p[3], p[4], p[5], p[6], (int)p[7]};
 }
 
 template <class R>
@@ -387,6 +388,30 @@ struct PixelResult {
   std::vector<Contrib<R>> list;  // in blend order
 };
 
+// Sec. 3.3 resort window.  The pixel's candidates, in the per-tile order
+// (mean depth, tet id), pass through a buffer of at most N_w entries kept
+// sorted by the pixel's own entry depth (ties keep arrival order); when the
+// buffer overflows, its nearest entry leaves and is blended next.  At the end
+// of the list the rest leaves nearest first.  Only candidates that can blend
+// (alpha >= alpha_min) enter the buffer.
+template <class R>
+void resort_window(std::vector<Contrib<R>>& list, int nw, float alpha_min) {
+  std::vector<Contrib<R>> out, buf;
+  for (const auto& ct : list) {
+    if (ct.hit.alpha < R(alpha_min)) continue;
+    auto at = std::upper_bound(buf.begin(), buf.end(), ct, [](const Contrib<R>& a, const Contrib<R>& b) {
+      return a.hit.in.z < b.hit.in.z;
+    });
+    buf.insert(at, ct);
+    if ((int)buf.size() > nw) {
+      out.push_back(buf.front());
+      buf.erase(buf.begin());
+    }
+  }
+  out.insert(out.end(), buf.begin(), buf.end());
+  list.swap(out);
+}
+
 template <class R>
 void shade_pixel(const std::vector<KTet<R>>& kt, const std::vector<VTet<R>>& vt, const Cam& c,
                  const Params& P, int i, int j, PixelResult<R>& pr, bool keep_list) {
@@ -406,6 +431,7 @@ void shade_pixel(const std::vector<KTet<R>>& kt, const std::vector<VTet<R>>& vt,
   std::sort(list.begin(), list.end(), [](const Contrib<R>& a, const Contrib<R>& b) {
     return a.zbits != b.zbits ? a.zbits < b.zbits : a.tet_id < b.tet_id;
   });
+  if (P.window > 0) resort_window(list, P.window, P.alpha_min);
   for (int q = 0; q < 8; ++q) pr.out[q] = R(0);
   R T = R(1);
   int nb = 0;
@@ -877,11 +903,12 @@ long oracle_binning(const double* verts, const int* tets, const double* sdf, int
 }
 
 // Trace of one pixel: the tets blended, in order, with their alpha (after the
-// clamp), transmittance before them, raw alpha, and the pre-filter bound.
+// clamp), transmittance before them, raw alpha, entry/exit SDF values and
+// entry depth.
 int oracle_pixel_trace(int prec, const double* verts, const int* tets, const double* sdf, const double* colors,
                        int V, int K, const float* cams, int nv, const float* params, int view, int i, int j,
                        int cap, int* tet_id, double* alpha, double* T, double* alpha_raw, double* fprev,
-                       double* fnext) {
+                       double* fnext, double* zin) {
   Params P = load_params(params);
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
@@ -899,6 +926,7 @@ int oracle_pixel_trace(int prec, const double* verts, const int* tets, const dou
       alpha_raw[q] = val(pr.list[q].hit.alpha);
       fprev[q] = val(pr.list[q].hit.in.f);
       fnext[q] = val(pr.list[q].hit.out.f);
+      zin[q] = val(pr.list[q].hit.in.z);
     }
     return n;
   };
