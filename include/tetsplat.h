@@ -259,6 +259,22 @@ int render_regularizers(const float* verts, const int32_t* tets, const float* sd
                         void* stream);
 
 /*
+ * render_prefilter_bounds: coarse-to-fine pre-filtering (App. B).  The
+ * bounding box of the vertices of the tets the pre-filter keeps (alpha_max of
+ * Eq. 1 at the tet's largest and smallest SDF value >= params->prefilter_tf,
+ * the rule render_forward applies), and their count.  A caller rebuilds its
+ * grid over that box, samples the SDF there and pre-filters again.
+ *   scene: one scene (device pointers; colors are not read and may be NULL);
+ *   bounds: device float[6] <- (min x, min y, min z, max x, max y, max z),
+ *     all NaN when no tet is kept;
+ *   kept: device int64 <- the number of kept tets (may be NULL).
+ * Exact and deterministic (min/max and integer counts).  Tets with an index
+ * outside [0, V) are not kept.  Asynchronous on stream; no workspace.
+ */
+int render_prefilter_bounds(const render_scene* scene, const render_params* params, float* bounds, int64_t* kept,
+                            void* stream);
+
+/*
  * render_marching_tets: triangle mesh of the zero level set (Marching
  * Tetrahedra, the mesh extraction of Sec. 4.1).  A vertex is inside when
  * f < 0.  Every edge of `edges` (as written by render_mesh_edges for the

@@ -287,6 +287,27 @@ int render_mesh_edges(const int32_t* tets, int32_t K, int32_t V, int32_t* edges,
   return RENDER_OK;
 }
 
+int render_prefilter_bounds(const render_scene* scene, const render_params* params, float* bounds, int64_t* kept,
+                            void* stream) {
+  if (!scene || !params || !bounds) return fail(RENDER_EINVAL, "null scene, params or bounds");
+  const render_scene& S = *scene;
+  if (S.V < 0 || S.K < 0 || S.K > (1 << 30) || S.V > (1 << 30)) return fail(RENDER_EINVAL, "V or K out of range");
+  if (S.K > 0 && (!S.verts || !S.tets || !S.sdf)) return fail(RENDER_EINVAL, "null device pointer");
+  if (((uintptr_t)S.tets & 15u) != 0) return fail(RENDER_EINVAL, "tets must be 16-byte aligned");
+  if (((uintptr_t)bounds & 3u) != 0 || ((uintptr_t)kept & 7u) != 0) return fail(RENDER_EINVAL, "misaligned output");
+  ts::DevScene d{};
+  d.verts = S.verts;
+  d.tets = S.tets;
+  d.sdf = S.sdf;
+  d.colors = S.colors;
+  d.V = S.V;
+  d.K = S.K;
+  d.s = S.s;
+  hipError_t e = ts::launch_prefilter_bounds(d, params->prefilter_tf, bounds, kept, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RENDER_EHIP, "prefilter bounds: %s", hipGetErrorString(e));
+  return RENDER_OK;
+}
+
 int render_marching_tets_workspace_size(int32_t K, int64_t edge_capacity, size_t* bytes) {
   if (!bytes) return fail(RENDER_EINVAL, "null bytes");
   if (K < 0 || K > (1 << 30) || edge_capacity < 0 || edge_capacity > 0x7fffffffll)

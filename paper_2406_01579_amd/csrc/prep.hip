@@ -3,6 +3,8 @@
 // preserving compaction and per-tet normal/colour (Sec. 3.2, App. A.3),
 // projection and tile counting (Sec. 3.3), the device-wide scan of tile
 // counts, tile-duplicated key emission, and tile ranges.
+#include <algorithm>
+
 #include "ts_device.h"
 
 namespace ts {
@@ -614,6 +616,82 @@ hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene*, hipStre
   dim3 grid(256, (unsigned)L.ns);
   k_zero_grads<<<grid, 256, 0, st>>>(ws, L);
   k_zero_eflags<<<512, 256, 0, st>>>(ws, L);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-to-fine pre-filtering (App. B): bounding box of the vertices of the
+// kept tets.  Coordinates are reduced as order-preserving integer images of
+// their float bits (min/max are exact and order-independent).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ord_bits(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord_float(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ void k_bounds_init(uint32_t* box, unsigned long long* kept) {
+  const int t = threadIdx.x;
+  if (t < 3) box[t] = 0xffffffffu;
+  if (t >= 3 && t < 6) box[t] = 0u;
+  if (t == 0 && kept) *kept = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_pf_bounds(DevScene S, float tf, uint32_t* box, unsigned long long* kept) {
+  uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
+  uint32_t cnt = 0;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < S.K; k += gridDim.x * 256) {
+    int4 vi;
+    if (!keep_tet(S, k, tf, nullptr, &vi)) continue;
+    ++cnt;
+    const int idx[4] = {vi.x, vi.y, vi.z, vi.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const uint32_t u = ord_bits(S.verts[3 * (size_t)idx[a] + c]);
+        mn[c] = min(mn[c], u);
+        mx[c] = max(mx[c], u);
+      }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      mn[c] = min(mn[c], (uint32_t)__shfl_xor((int)mn[c], o, 64));
+      mx[c] = max(mx[c], (uint32_t)__shfl_xor((int)mx[c], o, 64));
+    }
+    cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && cnt > 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      atomicMin(&box[c], mn[c]);
+      atomicMax(&box[3 + c], mx[c]);
+    }
+    if (kept) atomicAdd(kept, (unsigned long long)cnt);
+  }
+}
+
+// in place: integer images back to floats; NaN where nothing was kept
+__global__ void k_bounds_final(uint32_t* box) {
+  const int t = threadIdx.x;
+  if (t < 6) {
+    const uint32_t u = box[t];
+    const bool empty = (t < 3) ? (u == 0xffffffffu) : (u == 0u);
+    reinterpret_cast<float*>(box)[t] = empty ? __uint_as_float(0x7fc00000u) : ord_float(u);
+  }
+}
+
+hipError_t launch_prefilter_bounds(const DevScene& S, float tf, float* bounds, int64_t* kept, hipStream_t st) {
+  uint32_t* box = reinterpret_cast<uint32_t*>(bounds);
+  unsigned long long* kp = reinterpret_cast<unsigned long long*>(kept);
+  k_bounds_init<<<1, 64, 0, st>>>(box, kp);
+  const unsigned g = (unsigned)std::max(1, std::min((S.K + 255) / 256, 2048));
+  if (S.K > 0) k_pf_bounds<<<g, 256, 0, st>>>(S, tf, box, kp);
+  k_bounds_final<<<1, 64, 0, st>>>(box);
   return hipGetLastError();
 }
 

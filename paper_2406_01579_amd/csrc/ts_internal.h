@@ -180,6 +180,8 @@ hipError_t launch_regularizers(const float* verts, const int32_t* tets, const fl
                                const int32_t* edges, const int32_t* n_edges, int64_t edge_cap, const float* weights,
                                double* losses, float* dverts, float* dsdf, void* ws, const RegLayout& R,
                                hipStream_t st);
+hipError_t launch_prefilter_bounds(const DevScene& S, float tf, float* bounds, int64_t* kept, hipStream_t st);
+
 struct MTLayout {
   uint64_t edge_blocks, tet_blocks;
   size_t o_vid, o_bsum_e, o_bsum_t, bytes;
