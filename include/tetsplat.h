@@ -94,7 +94,17 @@ typedef struct {
   float alpha_clamp;      /* clamp alpha to at most this (3DGS: 0.99) */
   float t_min;            /* stop before a tet that takes T below this (3DGS: 1e-4) */
   float prefilter_tf;     /* pre-filter threshold T_f on alpha_max (paper: 1/255) */
+  int32_t window;         /* per-pixel resort window N_w (Sec. 3.3), 0..RENDER_WINDOW_MAX; 0: off,
+                             the blend order is the per-tile order.  With N_w > 0 each pixel passes
+                             its candidates, in the per-tile order, through a buffer of N_w entries
+                             ordered by the depth where its ray enters the tet; on overflow the
+                             nearest leaves and is blended, at the end of the list the rest leave
+                             nearest first (equal depths: arrival order); only candidates with
+                             alpha >= alpha_min enter.  Needs 8x8 tiles; the workspace then holds
+                             16 B per (entry, pixel of its tile) for the backward. */
 } render_params;
+
+#define RENDER_WINDOW_MAX 8
 
 typedef struct {
   float* dverts;        /* [V,3] dL/dverts, overwritten */

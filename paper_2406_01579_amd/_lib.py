@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libtetsplat.so")
 
 RENDER_OK, RENDER_EINVAL, RENDER_ENOSPC, RENDER_EHIP, RENDER_EOVERFLOW = 0, -1, -2, -3, -4
 RENDER_RECOMPUTE_STATE, RENDER_VALIDATE = 1, 2
+RENDER_WINDOW_MAX = 8
 
 
 class render_scene(C.Structure):
@@ -26,7 +27,8 @@ class render_view(C.Structure):
 class render_params(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("flags", C.c_int32), ("waves", C.c_int32),
                 ("alpha_min", C.c_float),
-                ("alpha_clamp", C.c_float), ("t_min", C.c_float), ("prefilter_tf", C.c_float)]
+                ("alpha_clamp", C.c_float), ("t_min", C.c_float), ("prefilter_tf", C.c_float),
+                ("window", C.c_int32)]
 
 
 class render_grads(C.Structure):

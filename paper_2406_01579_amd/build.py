@@ -17,7 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtetsplat.so")
-SOURCES = ["api.cpp", "prep.hip", "sort.hip", "raster.hip", "raster_mw.hip", "vgrad.hip", "geom.hip"]
+SOURCES = ["api.cpp", "prep.hip", "sort.hip", "raster.hip", "raster_mw.hip", "raster_win.hip", "vgrad.hip", "geom.hip"]
 ARCH = "gfx950"
 
 

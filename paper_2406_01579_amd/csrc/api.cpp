@@ -67,6 +67,10 @@ int check_args(const render_scene* scenes, int ns, const render_view* views, int
   if (!(p->alpha_clamp > 0.0f && p->alpha_clamp <= 1.0f)) return fail(RENDER_EINVAL, "alpha_clamp must be in (0, 1]");
   if (!(p->waves == 0 || p->waves == 1 || p->waves == 2 || p->waves == 4 || p->waves == 8))
     return fail(RENDER_EINVAL, "waves must be 0, 1, 2, 4 or 8 (got %d)", p->waves);
+  if (p->window < 0 || p->window > RENDER_WINDOW_MAX)
+    return fail(RENDER_EINVAL, "window must be in [0, %d] (got %d)", RENDER_WINDOW_MAX, p->window);
+  if (p->window > 0 && (p->tile_w != 8 || p->tile_h != 8))
+    return fail(RENDER_EINVAL, "the resort window needs 8x8 tiles (got %dx%d)", p->tile_w, p->tile_h);
   for (int s = 0; s < ns; ++s) {
     const render_scene& S = scenes[s];
     if (S.V < 0 || S.K < 0) return fail(RENDER_EINVAL, "scene %d: negative V or K", s);
@@ -209,6 +213,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE * (size_t)entry_cap);
   L.o_last = take(4 * (size_t)pixels);
   L.o_tlast = take(4 * (size_t)pixels);
+  L.o_wpair = p->window > 0 ? take(16 * 64 * (size_t)entry_cap) : 0;
   L.bytes = o;
   return true;
 }
@@ -401,8 +406,9 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
   TS_STAGE(RENDER_STAGE_RANGES, launch_finalize(workspace, L, st), "tile ranges");
   TS_STAGE(RENDER_STAGE_RANGES, launch_tile_order(workspace, L, st), "tile order");
   TS_STAGE(RENDER_STAGE_COMPOSITE,
-           multiwave(*params) ? launch_composite_mw(workspace, L, with_waves(*params), st)
-                              : launch_composite(workspace, L, *params, st),
+           params->window > 0 ? launch_composite_win(workspace, L, with_waves(*params), st)
+           : multiwave(*params) ? launch_composite_mw(workspace, L, with_waves(*params), st)
+                                : launch_composite(workspace, L, *params, st),
            "composite");
   return RENDER_OK;
 }
@@ -435,8 +441,9 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
   TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,
-           multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)
-                              : launch_composite_backward(workspace, L, *params, st),
+           params->window > 0 ? launch_composite_backward_win(workspace, L, with_waves(*params), st)
+           : multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)
+                                : launch_composite_backward(workspace, L, *params, st),
            "composite backward");
   TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
   return RENDER_OK;

@@ -11,48 +11,11 @@
 // runs the recurrence over the chunk, and (backward) the waves then build and
 // reduce the per-entry gradients in parallel.  Results are bit-identical to
 // the one-wave kernels: the same per-pair arithmetic in the same order.
-#include "ts_device.h"
+#include "tile8.h"
 
 namespace ts {
 
 namespace {
-
-__device__ __forceinline__ void load_recs(ViewRec* recs, const ViewRec* __restrict__ vrec,
-                                          const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads) {
-  for (int q = threadIdx.x; q < n * 8; q += nthreads) {
-    const int e = q >> 3, part = q & 7;
-    const uint32_t r = srec[base + e];
-    reinterpret_cast<float4*>(&recs[e])[part] = reinterpret_cast<const float4*>(&vrec[r])[part];
-  }
-}
-
-__device__ __forceinline__ bool has_pixel(const ViewRec& R, int i, int j) {
-  int i0, i1, j0, j1;
-  unpack_rect(R, i0, i1, j0, j1);
-  return i >= i0 && i <= i1 && j >= j0 && j <= j1;
-}
-
-struct Tile8 {
-  int view, tile;
-  int tx, ty;     // tile coordinates inside the view
-  int i, j;
-  bool inside;
-};
-
-__device__ __forceinline__ Tile8 tile8(const DevView* vw, int nv, const uint32_t* order) {
-  Tile8 c;
-  c.tile = (int)order[blockIdx.x];
-  c.view = find_view_by_tile(vw, nv, c.tile);
-  const DevView& V = vw[c.view];
-  const int lt = c.tile - V.tile_base;
-  const int lane = threadIdx.x & 63;
-  c.tx = lt % V.tiles_x;
-  c.ty = lt / V.tiles_x;
-  c.i = c.tx * 8 + (lane & 7);
-  c.j = c.ty * 8 + (lane >> 3);
-  c.inside = c.i < V.W && c.j < V.H;
-  return c;
-}
 
 // Forward sweep over [start, end) with NWV waves; wave 0 ends with the
 // pixel's blend state.  Used by the forward kernel and by the backward's
@@ -164,40 +127,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
     last_out[g] = last;
     tlast_out[g] = Tb;
   }
-}
-
-// d f(face F) / d(record parameters) times df, added to g.  F is a
-// compile-time constant, so every index is static; the face's values (S, f)
-// are recomputed from its cross products N.
-// f = sum N_k w_k f_k / S, S = sum N_k w_k.
-template <int F>
-__device__ __forceinline__ void face_geom_grad(const ViewRec& R, const float (&ax)[4], const float (&ay)[4],
-                                               float N0, float N1, float N2, float df, float (&g)[32]) {
-  constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
-  constexpr int I[3] = {A, B, C};
-  const float N[3] = {N0, N1, N2};
-  const float qa = N0 * R.iz[A], qb = N1 * R.iz[B], qc = N2 * R.iz[C];
-  const float S = (qa + qb) + qc;
-  const float invS = rcp(S);
-  const float fF = fmaf(qa, R.f[A], fmaf(qb, R.f[B], qc * R.f[C])) * invS;
-  float a[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int v = I[k];
-    const float wk = R.iz[v];
-    const float diff = (R.f[v] - fF) * invS * df;
-    g[G_F + v] = fmaf(N[k] * wk * invS, df, g[G_F + v]);   // d/df_k
-    g[G_IZ + v] = fmaf(N[k], diff, g[G_IZ + v]);            // d/dw_k
-    a[k] = wk * diff;                                       // d/dN_k
-  }
-  const float Ax = ax[A], Ay = ay[A], Bx = ax[B], By = ay[B], Cx = ax[C], Cy = ay[C];
-  // N0 = cross(B', C'), N1 = cross(C', A'), N2 = cross(A', B')
-  g[G_PX + A] += a[2] * By - a[1] * Cy;
-  g[G_PY + A] += a[1] * Cx - a[2] * Bx;
-  g[G_PX + B] += a[0] * Cy - a[2] * Ay;
-  g[G_PY + B] += a[2] * Ax - a[0] * Cx;
-  g[G_PX + C] += a[1] * Ay - a[0] * By;
-  g[G_PY + C] += a[0] * Bx - a[1] * Ax;
 }
 
 template <int NWV>
@@ -335,66 +264,15 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
 #pragma unroll
       for (int q = 0; q < 32; ++q) g[q] = 0.0f;
       if (contrib) {
-        g[G_C + 0] = w * gr[0];
-        g[G_C + 1] = w * gr[1];
-        g[G_C + 2] = w * gr[2];
-        g[G_ZT] = w * gr[4];
-        g[G_N + 0] = w * gr[5];
-        g[G_N + 1] = w * gr[6];
-        g[G_N + 2] = w * gr[7];
         const float alpha = abuf[e][lane];
-        if (da != 0.0f && alpha > 0.0f) {
-          const ViewRec& R = recs[e];
-          // alpha = A / B, A = -expm1(-s d), B = 1 + exp(s f_next)
-          const float e2 = e2buf[e][lane];
-          const float B = 1.0f + e2;
-          const float invB = rcp(B);
-          const float e1p1 = 1.0f - alpha * B;                 // exp(-s d) = 1 + expm1(-s d)
-          const float dA = da * invB;
-          const float dB = -da * alpha * invB;
-          const float dd = dA * s * e1p1;                      // d/df_prev
-          const float dfn = dB * s * e2 - dd;                  // d/df_next
-          const int fs = sel[e][lane];
-          const int fe = fs & 3, fx = fs >> 2;
-          float ax[4], ay[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            ax[k] = R.px[k] - qx;
-            ay[k] = R.py[k] - qy;
-          }
-          const float e01 = ax[0] * ay[1] - ay[0] * ax[1];
-          const float e02 = ax[0] * ay[2] - ay[0] * ax[2];
-          const float e03 = ax[0] * ay[3] - ay[0] * ax[3];
-          const float e12 = ax[1] * ay[2] - ay[1] * ax[2];
-          const float e13 = ax[1] * ay[3] - ay[1] * ax[3];
-          const float e23 = ax[2] * ay[3] - ay[2] * ax[3];
-          const float w0 = (fe == 0 ? dd : 0.0f) + (fx == 0 ? dfn : 0.0f);
-          const float w1 = (fe == 1 ? dd : 0.0f) + (fx == 1 ? dfn : 0.0f);
-          const float w2 = (fe == 2 ? dd : 0.0f) + (fx == 2 ? dfn : 0.0f);
-          const float w3 = (fe == 3 ? dd : 0.0f) + (fx == 3 ? dfn : 0.0f);
-          if (w0 != 0.0f) face_geom_grad<0>(R, ax, ay, e12, -e02, e01, w0, g);
-          if (w1 != 0.0f) face_geom_grad<1>(R, ax, ay, e13, -e03, e01, w1, g);
-          if (w2 != 0.0f) face_geom_grad<2>(R, ax, ay, e23, -e03, e02, w2, g);
-          if (w3 != 0.0f) face_geom_grad<3>(R, ax, ay, e23, -e13, e12, w3, g);
-        }
+        pair_grad(recs[e], qx, qy, s, gr, da, w, alpha, e2buf[e][lane], sel[e][lane], g);
       }
       const float tot = wave_transpose_sum32(g);
       const unsigned q = lane >> 1;
       if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
     }
     __syncthreads();
-    // each entry's gradient goes to its pre-sort slot: the record's first
-    // entry plus this tile's row-major index inside the record's tile rectangle
-    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) {
-      const int e = q / TGRAD_STRIDE, k = q - e * TGRAD_STRIDE;
-      const ViewRec& R = recs[e];
-      int i0, i1, j0, j1;
-      unpack_rect(R, i0, i1, j0, j1);
-      const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
-      const size_t d = (size_t)R.entry0 + (size_t)((c.ty - ty0) * nx + (c.tx - tx0));
-      tgrad[d * TGRAD_STRIDE + k] = gacc[e][k];
-      if (k == 0) eflag[d] = 1;
-    }
+    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT);
   }
 }
 

@@ -59,6 +59,7 @@ struct PixEval {
   float N[4][3];
   float S[4], f[4];
   int fe, fx;      // entry / exit face
+  float zin_inv;   // 1 / depth where the ray enters (entry face); larger is nearer
   float alpha;     // Eq. 1 (unclamped)
   float e1, e2;    // expm1(-s d), exp(s f_next) (for the derivative)
 };
@@ -121,6 +122,7 @@ __device__ __forceinline__ bool pixel_eval(const ViewRec& r, float qx, float qy,
     fout = bo ? f : fout;
     h.fx = bo ? F : h.fx;
   }
+  h.zin_inv = best_in;
   // Eq. 1, stable form, with the hardware exponential
   const float d = fin - fout;
   const bool pos = d > 0.0f;
@@ -136,6 +138,90 @@ __device__ __forceinline__ void unpack_rect(const ViewRec& r, int& i0, int& i1, 
   i1 = (int)(r.rx >> 16);
   j0 = (int)(r.ry & 0xffffu);
   j1 = (int)(r.ry >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode of one (pixel, record) pair: the pixel's blend weight w and
+// dL/dalpha are chained to the record's 23 screen-space parameters.
+// ---------------------------------------------------------------------------
+// d f(face F) / d(record parameters) times df, added to g.  F is a
+// compile-time constant, so every index is static; the face's values (S, f)
+// are recomputed from its cross products N.
+// f = sum N_k w_k f_k / S, S = sum N_k w_k.
+template <int F>
+__device__ __forceinline__ void face_geom_grad(const ViewRec& R, const float (&ax)[4], const float (&ay)[4],
+                                               float N0, float N1, float N2, float df, float (&g)[32]) {
+  constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
+  constexpr int I[3] = {A, B, C};
+  const float N[3] = {N0, N1, N2};
+  const float qa = N0 * R.iz[A], qb = N1 * R.iz[B], qc = N2 * R.iz[C];
+  const float S = (qa + qb) + qc;
+  const float invS = rcp(S);
+  const float fF = fmaf(qa, R.f[A], fmaf(qb, R.f[B], qc * R.f[C])) * invS;
+  float a[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int v = I[k];
+    const float wk = R.iz[v];
+    const float diff = (R.f[v] - fF) * invS * df;
+    g[G_F + v] = fmaf(N[k] * wk * invS, df, g[G_F + v]);   // d/df_k
+    g[G_IZ + v] = fmaf(N[k], diff, g[G_IZ + v]);            // d/dw_k
+    a[k] = wk * diff;                                       // d/dN_k
+  }
+  const float Ax = ax[A], Ay = ay[A], Bx = ax[B], By = ay[B], Cx = ax[C], Cy = ay[C];
+  // N0 = cross(B', C'), N1 = cross(C', A'), N2 = cross(A', B')
+  g[G_PX + A] += a[2] * By - a[1] * Cy;
+  g[G_PY + A] += a[1] * Cx - a[2] * Bx;
+  g[G_PX + B] += a[0] * Cy - a[2] * Ay;
+  g[G_PY + B] += a[2] * Ax - a[0] * Cx;
+  g[G_PX + C] += a[1] * Ay - a[0] * By;
+  g[G_PY + C] += a[0] * Bx - a[1] * Ax;
+}
+
+// g (zeroed by the caller) <- the pair's gradient.  w = T alpha is the blend
+// weight (colour, depth and normal enter linearly); da = dL/dalpha (zero when
+// alpha was clamped); alpha, e2 = exp(s f_next) and the entry/exit faces
+// fs = fe | fx << 2 are the values of the pair's forward evaluation.
+__device__ __forceinline__ void pair_grad(const ViewRec& R, float qx, float qy, float s, const float (&gr)[8],
+                                          float da, float w, float alpha, float e2, int fs, float (&g)[32]) {
+  g[G_C + 0] = w * gr[0];
+  g[G_C + 1] = w * gr[1];
+  g[G_C + 2] = w * gr[2];
+  g[G_ZT] = w * gr[4];
+  g[G_N + 0] = w * gr[5];
+  g[G_N + 1] = w * gr[6];
+  g[G_N + 2] = w * gr[7];
+  if (da != 0.0f && alpha > 0.0f) {
+    // alpha = A / B, A = -expm1(-s d), B = 1 + exp(s f_next)
+    const float B = 1.0f + e2;
+    const float invB = rcp(B);
+    const float e1p1 = 1.0f - alpha * B;                 // exp(-s d) = 1 + expm1(-s d)
+    const float dA = da * invB;
+    const float dB = -da * alpha * invB;
+    const float dd = dA * s * e1p1;                      // d/df_prev
+    const float dfn = dB * s * e2 - dd;                  // d/df_next
+    const int fe = fs & 3, fx = fs >> 2;
+    float ax[4], ay[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ax[k] = R.px[k] - qx;
+      ay[k] = R.py[k] - qy;
+    }
+    const float e01 = ax[0] * ay[1] - ay[0] * ax[1];
+    const float e02 = ax[0] * ay[2] - ay[0] * ax[2];
+    const float e03 = ax[0] * ay[3] - ay[0] * ax[3];
+    const float e12 = ax[1] * ay[2] - ay[1] * ax[2];
+    const float e13 = ax[1] * ay[3] - ay[1] * ax[3];
+    const float e23 = ax[2] * ay[3] - ay[2] * ax[3];
+    const float w0 = (fe == 0 ? dd : 0.0f) + (fx == 0 ? dfn : 0.0f);
+    const float w1 = (fe == 1 ? dd : 0.0f) + (fx == 1 ? dfn : 0.0f);
+    const float w2 = (fe == 2 ? dd : 0.0f) + (fx == 2 ? dfn : 0.0f);
+    const float w3 = (fe == 3 ? dd : 0.0f) + (fx == 3 ? dfn : 0.0f);
+    if (w0 != 0.0f) face_geom_grad<0>(R, ax, ay, e12, -e02, e01, w0, g);
+    if (w1 != 0.0f) face_geom_grad<1>(R, ax, ay, e13, -e03, e01, w1, g);
+    if (w2 != 0.0f) face_geom_grad<2>(R, ax, ay, e23, -e03, e02, w2, g);
+    if (w3 != 0.0f) face_geom_grad<3>(R, ax, ay, e23, -e13, e12, w3, g);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -114,6 +114,7 @@ struct Layout {
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
   size_t o_ranges, o_tile_hist, o_tile_order, o_tgrad, o_last, o_tlast;
+  size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
   size_t bytes;
 };
 
@@ -150,6 +151,8 @@ hipError_t launch_composite(void* ws, const Layout& L, const render_params& p, h
 hipError_t launch_composite_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_backward_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_composite_win(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_composite_backward_win(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene* hs, hipStream_t st);
 

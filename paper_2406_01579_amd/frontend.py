@@ -32,11 +32,12 @@ class Params:
     prefilter_tf: float = 1.0 / 255.0
     recompute_state: bool = False
     waves: int = 4   # waves sharing one 8x8 tile
+    window: int = 0  # per-pixel resort window N_w (Sec. 3.3); 0: per-tile order
 
     def c(self) -> _lib.render_params:
         return _lib.render_params(self.tile_w, self.tile_h,
                                   _lib.RENDER_RECOMPUTE_STATE if self.recompute_state else 0, self.waves,
-                                  self.alpha_min, self.alpha_clamp, self.t_min, self.prefilter_tf)
+                                  self.alpha_min, self.alpha_clamp, self.t_min, self.prefilter_tf, self.window)
 
     @classmethod
     def exact(cls, **kw):

@@ -18,7 +18,8 @@ GRAD_TOL = 1e-4
 
 def oracle_params(P, s):
     return oracle.params_array(s, tile_w=P.tile_w, tile_h=P.tile_h, alpha_min=P.alpha_min,
-                               alpha_clamp=P.alpha_clamp, t_min=P.t_min, prefilter_tf=P.prefilter_tf)
+                               alpha_clamp=P.alpha_clamp, t_min=P.t_min, prefilter_tf=P.prefilter_tf,
+                               window=getattr(P, "window", 0))
 
 
 def gpu_forward(scene, cams, P, renderer=None, device="cuda"):

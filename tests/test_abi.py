@@ -212,3 +212,23 @@ def test_regularizer_entry_points_validate_on_the_host(L):
     assert lib.render_regularizers(*args, 32768, None, 24576, 28672, ws, need - 256, None) == L.RENDER_ENOSPC
     assert lib.render_regularizers(*args[:5], 16388, 20480, 1800, None, None, None, None, ws, need,
                                    None) == L.RENDER_EINVAL
+
+
+def test_resort_window_arguments(L):
+    """The resort window is 0..RENDER_WINDOW_MAX on 8x8 tiles; with it on, the
+    workspace holds 16 bytes per (entry, tile pixel) more."""
+    w = synth.tiny()
+    scenes, views, p = _args(L, w, (8, 8))
+    rc, base = _size(L, scenes, views, p, ent=10000)
+    assert rc == 0
+    p.window = 5
+    rc, with_win = _size(L, scenes, views, p, ent=10000)
+    assert rc == 0 and with_win >= base + 16 * 64 * 10000
+    for bad in (-1, L.RENDER_WINDOW_MAX + 1):
+        p.window = bad
+        assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL
+        assert b"window" in L.lib().render_last_error()
+    s2, v2, p2 = _args(L, w, (16, 16))
+    p2.window = 3
+    assert _size(L, s2, v2, p2)[0] == L.RENDER_EINVAL
+    assert b"8x8" in L.lib().render_last_error()
