@@ -24,11 +24,11 @@ template <int NWV, int CHN>
 __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, const uint32_t* __restrict__ srec,
                                               uint32_t start, uint32_t end, const Tile8& c, float s, float alpha_min,
                                               float alpha_clamp, float t_min, ViewRec* recs, float (*alds)[64],
-                                              unsigned long long* done_mask, float& T, float& Tb, float& O,
-                                              float (&acc)[7], int& last, bool want_acc) {
+                                              uint64_t* pmask, uint32_t* poff, unsigned long long* done_mask,
+                                              float& T, float& Tb, float& O, float (&acc)[7], int& last,
+                                              bool want_acc) {
   constexpr int NT = 64 * NWV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   bool done = !c.inside;
   if (threadIdx.x == 0) *done_mask = 0ull;
   __syncthreads();
@@ -42,16 +42,16 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
     const int n = (int)min((uint32_t)CHN, end - base);
     load_recs(recs, vrec, srec, base, n, NT);
     __syncthreads();
-    const bool mydone = (*done_mask >> lane) & 1ull;
-    for (int e = wave; e < n; e += NWV) {
-      float a = -1.0f;
-      const ViewRec& R = recs[e];
-      if (!mydone && has_pixel(R, c.i, c.j)) {
-        PixEval h;
-        if (pixel_eval(R, qx, qy, s, h)) a = h.alpha;
-      }
-      alds[e][lane] = a;
-    }
+    // phase A: coverage and Eq. 1 of the live (entry, pixel) pairs, packed
+    for (int q = threadIdx.x; q < n * 16; q += NT)
+      reinterpret_cast<float4*>(&alds[0][0])[q] = make_float4(-1.0f, -1.0f, -1.0f, -1.0f);
+    if (wave == 0) chunk_pairs<CHN>(recs, n, c, ~*done_mask, pmask, poff);
+    __syncthreads();
+    for_each_pair<CHN>(n, pmask, poff, NT, [&](int e, int pix) {
+      const float qx = (float)(c.tx * 8 + (pix & 7)) + 0.5f, qy = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
+      PixEval h;
+      alds[e][pix] = pixel_eval(recs[e], qx, qy, s, h) ? h.alpha : -1.0f;
+    });
     __syncthreads();
     if (wave == 0) {
       for (int e = 0; e < n; ++e) {
@@ -100,6 +100,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   float* tlast_out = at<float>(ws, L.o_tlast);
   __shared__ ViewRec recs[CHN];
   __shared__ float alds[CHN][64];
+  __shared__ uint64_t pmask[CHN];
+  __shared__ uint32_t poff[CHN + 1];
   __shared__ unsigned long long done_mask;
 
   const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
@@ -109,8 +111,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int last = -1;
-  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, &done_mask, T,
-                          Tb, O, acc, last, true);
+  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff,
+                          &done_mask, T, Tb, O, acc, last, true);
   if ((threadIdx.x >> 6) == 0 && c.inside) {
     const size_t plane = (size_t)V.W * V.H;
     const size_t px = (size_t)c.j * V.W + c.i;
@@ -152,6 +154,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   __shared__ float gacc[CHB][TGRAD_STRIDE];
   __shared__ float grs[8][64];       // upstream gradient of each pixel
   __shared__ int lasts[64];
+  __shared__ uint64_t pmask[CHB];
+  __shared__ uint32_t poff[CHB + 1];
   __shared__ unsigned long long done_mask;
   __shared__ int smax;
 
@@ -171,8 +175,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   if (recompute) {
     float T = 1.0f, O = 0.0f;
     float acc[7];
-    forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, &done_mask, T,
-                            Tb, O, acc, last, false);
+    forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, pmask, poff,
+                            &done_mask, T, Tb, O, acc, last, false);
   } else if (wave == 0 && c.inside) {
     const size_t gi = (size_t)V.pix_base + px;
     last = last_in[gi];
@@ -210,23 +214,28 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     __syncthreads();
     load_recs(recs, vrec, srec, base, n, NT);
     __syncthreads();
-    // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's walk reached
-    for (int e = wave; e < n; e += NWV) {
-      float a = -1.0f, e2 = 0.0f;
-      uint8_t fs = 0;
-      const ViewRec& R = recs[e];
-      if (c.inside && (int)(base + e) <= last && has_pixel(R, c.i, c.j)) {
-        PixEval h;
-        if (pixel_eval(R, qx, qy, s, h)) {
-          a = h.alpha;
-          e2 = h.e2;
-          fs = (uint8_t)(h.fe | (h.fx << 2));
-        }
+    // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's
+    // walk reached (entry at or before its last blend), packed
+    for (int q = threadIdx.x; q < n * 16; q += NT)
+      reinterpret_cast<float4*>(&abuf[0][0])[q] = make_float4(-1.0f, -1.0f, -1.0f, -1.0f);
+    if (wave == 0) {
+      uint64_t live_e = 0ull;
+      for (int e = 0; e < n; ++e) {
+        const uint64_t b = __ballot(c.inside && (int)(base + e) <= last);
+        live_e = ((int)lane == e) ? b : live_e;
       }
-      abuf[e][lane] = a;
-      e2buf[e][lane] = e2;
-      sel[e][lane] = fs;
+      chunk_pairs<CHB>(recs, n, c, live_e, pmask, poff);
     }
+    __syncthreads();
+    for_each_pair<CHB>(n, pmask, poff, NT, [&](int e, int pix) {
+      const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
+      PixEval h;
+      if (pixel_eval(recs[e], px_, py_, s, h)) {
+        abuf[e][pix] = h.alpha;
+        e2buf[e][pix] = h.e2;
+        sel[e][pix] = (uint8_t)(h.fe | (h.fx << 2));
+      }
+    });
     __syncthreads();
     // phase B: reverse recurrence (one wave)
     if (wave == 0) {

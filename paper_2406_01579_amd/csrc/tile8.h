@@ -65,5 +65,80 @@ __device__ __forceinline__ void store_entry_grads(const ViewRec* recs, const flo
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pair packing.  Of the 64 pixels of a tile, a record's pixel rectangle
+// usually holds a handful; evaluating one record per wave would leave most
+// lanes idle.  Instead each chunk lists the (entry, pixel) pairs whose pixel
+// lies in the entry's rectangle and is still live, entry-major, and the
+// workgroup's lanes take consecutive pairs.
+// ---------------------------------------------------------------------------
+// Pixels of the tile (bit = row-major local index) inside R's rectangle.
+__device__ __forceinline__ uint64_t rect_mask(const ViewRec& R, const Tile8& c) {
+  int i0, i1, j0, j1;
+  unpack_rect(R, i0, i1, j0, j1);
+  const int x0 = max(i0 - c.tx * 8, 0), x1 = min(i1 - c.tx * 8, 7);
+  const int y0 = max(j0 - c.ty * 8, 0), y1 = min(j1 - c.ty * 8, 7);
+  if (x0 > x1 || y0 > y1) return 0ull;
+  const uint64_t row = (uint64_t)(((2u << x1) - (1u << x0)) & 0xffu);
+  const uint64_t rows = (~0ull >> (8 * (7 - y1))) & (~0ull << (8 * y0));
+  return (row * 0x0101010101010101ull) & rows;
+}
+
+// Position of the k-th (from 0) set bit of m; m has more than k set bits.
+__device__ __forceinline__ int select_bit(uint64_t m, uint32_t k) {
+  int pos = 0;
+  uint32_t c = (uint32_t)__popc((uint32_t)m);
+  const bool hi = k >= c;
+  k = hi ? k - c : k;
+  uint32_t x = hi ? (uint32_t)(m >> 32) : (uint32_t)m;
+  pos = hi ? 32 : 0;
+#pragma unroll
+  for (int w = 16; w >= 1; w >>= 1) {
+    c = (uint32_t)__popc(x & ((1u << w) - 1u));
+    const bool up = k >= c;
+    k = up ? k - c : k;
+    x = up ? x >> w : x;
+    pos = up ? pos + w : pos;
+  }
+  return pos;
+}
+
+// Wave 0, lane e < n: entry e's pair mask is its rectangle & live_e (the
+// pixels that still take part for that entry).  Writes pmask[0..CH) and the
+// exclusive offsets poff[0..CH] (poff[n] = number of pairs).
+template <int CH>
+__device__ __forceinline__ void chunk_pairs(const ViewRec* recs, int n, const Tile8& c, uint64_t live_e,
+                                            uint64_t* pmask, uint32_t* poff) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t m = lane < n ? rect_mask(recs[lane], c) & live_e : 0ull;
+  uint32_t x = (uint32_t)__popcll(m);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    x += lane >= d ? y : 0u;
+  }
+  if (lane < CH) {
+    pmask[lane] = m;
+    poff[lane + 1] = x;
+  }
+  if (lane == 0) poff[0] = 0u;
+}
+
+// All threads: f(e, pix) for every listed pair (entry e, local pixel pix).
+template <int CH, class F>
+__device__ __forceinline__ void for_each_pair(int n, const uint64_t* pmask, const uint32_t* poff, int nthreads,
+                                              F&& f) {
+  const uint32_t total = poff[n];
+  for (uint32_t p = threadIdx.x; p < total; p += (uint32_t)nthreads) {
+    int e = 0;  // last entry whose first pair is at or before p
+#pragma unroll
+    for (int step = CH / 2; step > 0; step >>= 1) {
+      const int t = e + step;
+      e = (t < n && poff[t] <= p) ? t : e;
+    }
+    f(e, select_bit(pmask[e], p - poff[e]));
+  }
+}
+
 }  // namespace
 }  // namespace ts
