@@ -132,6 +132,7 @@ void fill_desc(const render_scene* scenes, int ns, const render_view* views, int
     d.tiles_y = (V.height + p->tile_h - 1) / p->tile_h;
     d.tile_base = (int32_t)tb;
     d.pix_base = (int32_t)pb;
+    d.s = scenes[V.scene].s;
     tb += (int64_t)d.tiles_x * d.tiles_y;
     pb += (int64_t)V.width * V.height;
   }
@@ -209,7 +210,11 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_eflag = take((size_t)entry_cap + 4);
   L.o_ranges = take(8 * (size_t)tiles);
   L.o_tile_hist = take(4 * 2 * (size_t)TILE_BUCKETS);  // right after the ranges: cleared together
-  L.o_tile_order = take(4 * (size_t)tiles);
+  L.o_tile_order = take(sizeof(TileSlot) * (size_t)tiles);
+  L.o_tile_pend = take(4 * (size_t)tiles);
+  L.o_bwd_hist = take(4 * 2 * (size_t)TILE_BUCKETS);
+  L.o_bwd_order = take(sizeof(TileSlot) * (size_t)tiles);
+  L.o_bwd_pend = take(4 * (size_t)tiles);
   L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE * (size_t)entry_cap);
   L.o_last = take(4 * (size_t)pixels);
   L.o_tlast = take(4 * (size_t)pixels);
@@ -440,6 +445,8 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
   TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, false, st),
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
+  if (params->window == 0 && multiwave(*params))
+    TS_STAGE(RENDER_STAGE_COMPOSITE_BWD, launch_bwd_order(workspace, L, st), "backward tile order");
   TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,
            params->window > 0 ? launch_composite_backward_win(workspace, L, with_waves(*params), st)
            : multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)

@@ -516,11 +516,18 @@ hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // dispatch order of the compositing workgroups: tiles with the longest lists
-// first (bucketed by the bit length of the list size), so the longest
-// sequential walks start in the first scheduling round.  The order inside a
-// bucket is whatever the atomics give; results do not depend on it.
+// first (bucketed by the list length: four buckets per power of two), so the
+// longest sequential walks start in the first scheduling round.  The forward
+// orders by list length; the backward by the length the forward actually
+// walked before every pixel of the tile stopped.  The order inside a bucket is
+// whatever the atomics give; results do not depend on it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0 ? 0 : 32 - __clz(len); }
+__device__ __forceinline__ int len_bucket(uint32_t len) {
+  if (len == 0) return 0;
+  const int b = 31 - __clz(len);  // floor(log2 len)
+  const int sub = b >= 2 ? (int)((len >> (b - 2)) & 3u) : (b == 1 ? (int)((len & 1u) << 1) : 0);
+  return 1 + 4 * b + sub;
+}
 
 __global__ __launch_bounds__(256) void k_tile_hist(void* ws, Layout L) {
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
@@ -534,8 +541,7 @@ __global__ __launch_bounds__(256) void k_tile_hist(void* ws, Layout L) {
   if (threadIdx.x < TILE_BUCKETS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_tile_scan(void* ws, Layout L) {
-  uint32_t* hist = at<uint32_t>(ws, L.o_tile_hist);
+__global__ void k_tile_scan(uint32_t* hist) {
   uint32_t* off = hist + TILE_BUCKETS;
   if (threadIdx.x == 0) {
     uint32_t run = 0;
@@ -549,7 +555,8 @@ __global__ void k_tile_scan(void* ws, Layout L) {
 __global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   uint32_t* off = at<uint32_t>(ws, L.o_tile_hist) + TILE_BUCKETS;
-  uint32_t* order = at<uint32_t>(ws, L.o_tile_order);
+  TileSlot* order = at<TileSlot>(ws, L.o_tile_order);
+  const DevView* vw = at<const DevView>(ws, L.o_view);
   __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS];
   if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -563,15 +570,75 @@ __global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
   __syncthreads();
   if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&off[threadIdx.x], cnt[threadIdx.x]);
   __syncthreads();
-  if (t < (uint32_t)L.total_tiles) order[base[b] + rank] = t;
+  if (t < (uint32_t)L.total_tiles) {
+    TileSlot sl;
+    sl.tile = t;
+    sl.view = (uint32_t)find_view_by_tile(vw, L.nv, (int)t);
+    sl.start = ranges[2 * t];
+    sl.end = ranges[2 * t + 1];
+    order[base[b] + rank] = sl;
+  }
 }
 
 hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
   k_tile_hist<<<nb, 256, 0, st>>>(ws, L);
-  k_tile_scan<<<1, 64, 0, st>>>(ws, L);
+  k_tile_scan<<<1, 64, 0, st>>>(at<uint32_t>(ws, L.o_tile_hist));
   k_tile_scatter<<<nb, 256, 0, st>>>(ws, L);
+  return hipGetLastError();
+}
+
+// backward order: forward slots re-bucketed by the walked length pend - start
+__global__ __launch_bounds__(256) void k_bwd_hist(void* ws, Layout L) {
+  const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
+  const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
+  uint32_t* hist = at<uint32_t>(ws, L.o_bwd_hist);
+  __shared__ uint32_t h[TILE_BUCKETS];
+  if (threadIdx.x < TILE_BUCKETS) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t < (uint32_t)L.total_tiles) atomicAdd(&h[len_bucket(pend[t] - slots[t].start)], 1u);
+  __syncthreads();
+  if (threadIdx.x < TILE_BUCKETS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
+  const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
+  const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
+  uint32_t* off = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
+  TileSlot* bslots = at<TileSlot>(ws, L.o_bwd_order);
+  uint32_t* bpend = at<uint32_t>(ws, L.o_bwd_pend);
+  __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS];
+  if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  int b = 0;
+  uint32_t rank = 0;
+  TileSlot sl{};
+  uint32_t pe = 0;
+  if (t < (uint32_t)L.total_tiles) {
+    sl = slots[t];
+    pe = pend[t];
+    b = len_bucket(pe - sl.start);
+    rank = atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&off[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (t < (uint32_t)L.total_tiles) {
+    bslots[base[b] + rank] = sl;
+    bpend[base[b] + rank] = pe;
+  }
+}
+
+hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
+  k_fill_u32<<<1, 256, 0, st>>>(at<uint32_t>(ws, L.o_bwd_hist), 2 * (uint64_t)TILE_BUCKETS, 0u);
+  k_bwd_hist<<<nb, 256, 0, st>>>(ws, L);
+  k_tile_scan<<<1, 64, 0, st>>>(at<uint32_t>(ws, L.o_bwd_hist));
+  k_bwd_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 

@@ -26,16 +26,20 @@ constexpr int CH = 64;  // records per LDS chunk
 
 struct TileCtx {
   int view, tile, lt, tx, ty;
+  uint32_t start, end;  // the tile's entry range
   int i, j;       // this lane's pixel
   bool inside;
   int wi0, wj0;   // this wave's 8x8 block origin
 };
 
 template <int TW, int TH>
-__device__ __forceinline__ TileCtx tile_ctx(const DevView* vw, int nv, const uint32_t* order) {
+__device__ __forceinline__ TileCtx tile_ctx(const DevView* vw, const TileSlot* slots) {
   TileCtx c;
-  c.tile = (int)order[blockIdx.x];
-  c.view = find_view_by_tile(vw, nv, c.tile);
+  const TileSlot sl = slots[blockIdx.x];
+  c.tile = (int)sl.tile;
+  c.view = (int)sl.view;
+  c.start = sl.start;
+  c.end = sl.end;
   const DevView& V = vw[c.view];
   c.lt = c.tile - V.tile_base;
   c.tx = c.lt % V.tiles_x;
@@ -81,18 +85,16 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
                                                       float t_min) {
   constexpr int NT = TW * TH;
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   int32_t* last_out = at<int32_t>(ws, L.o_last);
   float* tlast_out = at<float>(ws, L.o_tlast);
   __shared__ ViewRec recs[CH];
 
-  const TileCtx c = tile_ctx<TW, TH>(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const TileCtx c = tile_ctx<TW, TH>(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = sc[V.scene].s;
-  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float s = V.s;
+  const uint32_t start = c.start, end = c.end;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
 
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
@@ -190,8 +192,6 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const int32_t* last_in = at<const int32_t>(ws, L.o_last);
@@ -202,10 +202,10 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   __shared__ float gacc[CH][TGRAD_STRIDE];
   __shared__ int smax[NW];
 
-  const TileCtx c = tile_ctx<TW, TH>(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const TileCtx c = tile_ctx<TW, TH>(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = sc[V.scene].s;
-  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float s = V.s;
+  const uint32_t start = c.start, end = c.end;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   const size_t plane = (size_t)V.W * V.H;
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;

@@ -36,11 +36,19 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
     const unsigned long long m = __ballot(done);
     if (lane == 0) *done_mask = m;
   }
+  RecPipe<CHN, NT> rp;
+  if (start < end) {
+    rp.fetch_idx(srec, start, (int)min((uint32_t)CHN, end - start));
+    rp.fetch_rec(vrec);
+    if (end - start > (uint32_t)CHN) rp.fetch_idx(srec, start + CHN, (int)min((uint32_t)CHN, end - start - CHN));
+  }
   for (uint32_t base = start; base < end; base += CHN) {
     __syncthreads();
     if (*done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHN, end - base);
-    load_recs(recs, vrec, srec, base, n, NT);
+    rp.store(recs, n);
+    if (end - base > (uint32_t)CHN) rp.fetch_rec(vrec);
+    if (end - base > 2u * CHN) rp.fetch_idx(srec, base + 2 * CHN, (int)min((uint32_t)CHN, end - base - 2 * CHN));
     __syncthreads();
     // phase A: coverage and Eq. 1 of the live (entry, pixel) pairs, packed
     for (int q = threadIdx.x; q < n * 16; q += NT)
@@ -54,16 +62,18 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
     });
     __syncthreads();
     if (wave == 0) {
+      // branch-free so that the LDS reads of later entries issue early
+#pragma unroll 4
       for (int e = 0; e < n; ++e) {
-        float a = alds[e][lane];
-        if (done || a < 0.0f) continue;
-        if (a < alpha_min) continue;
-        a = fminf(a, alpha_clamp);
-        const float Tn = T * (1.0f - a);
-        if (Tn < t_min) { done = true; continue; }
-        const float w = T * a;
+        const float a = alds[e][lane];
+        const ViewRec& R = recs[e];
+        const bool live = !done && a >= 0.0f && a >= alpha_min;
+        const float ac = fminf(a, alpha_clamp);
+        const float Tn = T * (1.0f - ac);
+        const bool stop = live && Tn < t_min;
+        const bool blend = live && !stop;
+        const float w = blend ? T * ac : 0.0f;   // w = 0 leaves every sum unchanged
         if (want_acc) {
-          const ViewRec& R = recs[e];
           acc[0] = fmaf(w, R.c[0], acc[0]);
           acc[1] = fmaf(w, R.c[1], acc[1]);
           acc[2] = fmaf(w, R.c[2], acc[2]);
@@ -73,10 +83,10 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
           acc[6] = fmaf(w, R.n[2], acc[6]);
           O += w;
         }
-        Tb = T;
-        T = Tn;
-        last = (int)(base + e);
-        if (T == 0.0f) done = true;
+        Tb = blend ? T : Tb;
+        T = blend ? Tn : T;
+        last = blend ? (int)(base + e) : last;
+        done = done || stop || (blend && Tn == 0.0f);
       }
       const unsigned long long m = __ballot(done);
       if (lane == 0) *done_mask = m;
@@ -92,8 +102,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
                                                            float t_min) {
   constexpr int CHN = 64;
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   int32_t* last_out = at<int32_t>(ws, L.o_last);
@@ -104,15 +112,22 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   __shared__ uint32_t poff[CHN + 1];
   __shared__ unsigned long long done_mask;
 
-  const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = sc[V.scene].s;
-  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float s = V.s;
+  const uint32_t start = c.start, end = c.end;
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int last = -1;
   forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff,
                           &done_mask, T, Tb, O, acc, last, true);
+  if ((threadIdx.x >> 6) == 0) {
+    // end of the tile's blended prefix: where the backward starts its walk
+    int wmax = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+    if ((threadIdx.x & 63) == 0) at<uint32_t>(ws, L.o_tile_pend)[blockIdx.x] = wmax >= (int)start ? (uint32_t)wmax + 1u : start;
+  }
   if ((threadIdx.x >> 6) == 0 && c.inside) {
     const size_t plane = (size_t)V.W * V.H;
     const size_t px = (size_t)c.j * V.W + c.i;
@@ -137,8 +152,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   constexpr int NT = 64 * NWV;
   constexpr int CHB = 32;
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const int32_t* last_in = at<const int32_t>(ws, L.o_last);
@@ -146,41 +159,58 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   float* tgrad = at<float>(ws, L.o_tgrad);
   uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
   __shared__ ViewRec recs[CHB];
-  __shared__ float abuf[CHB][64];    // raw alpha (-1: no hit / not reached)
-  __shared__ float e2buf[CHB][64];   // exp(s f_next)
+  __shared__ float abuf[CHB][64];    // raw alpha (-1: no hit / not reached); phase B: dL/df_prev
+  __shared__ float e2buf[CHB][64];   // exp(s f_next); phase B: dL/df_next
   __shared__ uint8_t sel[CHB][64];   // entry face | exit face << 2
-  __shared__ float dabuf[CHB][64];   // dL/dalpha (0 when clamped)
   __shared__ float wbuf[CHB][64];    // blend weight T alpha
   __shared__ float gacc[CHB][TGRAD_STRIDE];
   __shared__ float grs[8][64];       // upstream gradient of each pixel
-  __shared__ int lasts[64];
   __shared__ uint64_t pmask[CHB];
   __shared__ uint32_t poff[CHB + 1];
+  __shared__ uint32_t hmask[64];     // per pixel: chunk entries it blended (bit e)
+  __shared__ float feat[7][CHB];     // per entry: c[3], zt, n[3] (conflict-free gathers)
   __shared__ unsigned long long done_mask;
   __shared__ int smax;
 
-  const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  // dispatch order by the length the forward walked (longest first); the
+  // tiles where nothing was blended come last and leave at once
+  const TileSlot* bslots = at<const TileSlot>(ws, L.o_bwd_order);
+  if (!recompute && at<const uint32_t>(ws, L.o_bwd_pend)[blockIdx.x] == bslots[blockIdx.x].start) return;
+  const Tile8 c = tile8(vw, bslots);
   const DevView& V = vw[c.view];
-  const float s = sc[V.scene].s;
-  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float s = V.s;
+  const uint32_t start = c.start, end = c.end;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   const size_t plane = (size_t)V.W * V.H;
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
   const unsigned lane = threadIdx.x & 63u;
   const int wave = threadIdx.x >> 6;
 
-  // per-pixel state (wave 0): last blended entry, T before it, upstream gradient
+  // per-pixel state (wave 0): last blended entry, T before it, upstream gradient;
+  // pend: end of the tile's blended prefix (from the forward, or the replay)
   int last = -1;
   float Tb = 1.0f;
+  uint32_t pend;
   if (recompute) {
     float T = 1.0f, O = 0.0f;
     float acc[7];
     forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, pmask, poff,
                             &done_mask, T, Tb, O, acc, last, false);
-  } else if (wave == 0 && c.inside) {
-    const size_t gi = (size_t)V.pix_base + px;
-    last = last_in[gi];
-    Tb = tlast_in[gi];
+    if (wave == 0) {
+      int wmax = last;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+      if (lane == 0) smax = wmax;
+    }
+    __syncthreads();
+    pend = smax >= (int)start ? (uint32_t)smax + 1u : start;
+  } else {
+    pend = at<const uint32_t>(ws, L.o_bwd_pend)[blockIdx.x];
+    if (wave == 0 && c.inside) {
+      const size_t gi = (size_t)V.pix_base + px;
+      last = last_in[gi];
+      Tb = tlast_in[gi];
+    }
   }
   float gr[8];
   if (wave == 0) {
@@ -189,35 +219,36 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
       grs[q][lane] = gr[q];
     }
-    lasts[lane] = last;
-    int wmax = last;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
-    if (lane == 0) smax = wmax;
-  }
-  __syncthreads();
-  if (wave != 0) {
-    last = lasts[lane];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) gr[q] = grs[q][lane];
   }
   float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
-  const int tmax = smax;
-  const uint32_t pend = (tmax >= (int)start) ? (uint32_t)tmax + 1u : start;
 
   bool first = true;
   float Tnext = 1.0f;
-  for (int64_t cb = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CHB) * CHB;
-       cb >= (int64_t)start && pend > start; cb -= CHB) {
+  // chunks from the one holding pend - 1 down to start; only the first is partial
+  const int64_t cb0 = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CHB) * CHB;
+  RecPipe<CHB, NT> rp;
+  if (pend > start) {
+    rp.fetch_idx(srec, (uint32_t)cb0, (int)(pend - (uint32_t)cb0));
+    rp.fetch_rec(vrec);
+    if (cb0 - CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb0 - CHB), CHB);
+  }
+  for (int64_t cb = cb0; cb >= (int64_t)start && pend > start; cb -= CHB) {
     const uint32_t base = (uint32_t)cb;
     const int n = (int)min((uint32_t)CHB, pend - base);
     __syncthreads();
-    load_recs(recs, vrec, srec, base, n, NT);
+    rp.store(recs, n);
+    if (cb - CHB >= (int64_t)start) rp.fetch_rec(vrec);
+    if (cb - 2 * CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb - 2 * CHB), CHB);
     __syncthreads();
     // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's
     // walk reached (entry at or before its last blend), packed
     for (int q = threadIdx.x; q < n * 16; q += NT)
       reinterpret_cast<float4*>(&abuf[0][0])[q] = make_float4(-1.0f, -1.0f, -1.0f, -1.0f);
+    if (threadIdx.x < 64) hmask[threadIdx.x] = 0u;
+    for (int q = threadIdx.x; q < n * 7; q += NT) {
+      const int e = q / 7, k = q - e * 7;
+      feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
+    }
     if (wave == 0) {
       uint64_t live_e = 0ull;
       for (int e = 0; e < n; ++e) {
@@ -234,51 +265,84 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         abuf[e][pix] = h.alpha;
         e2buf[e][pix] = h.e2;
         sel[e][pix] = (uint8_t)(h.fe | (h.fx << 2));
+        if (h.alpha >= alpha_min) atomicOr(&hmask[pix], 1u << e);
       }
     });
     __syncthreads();
-    // phase B: reverse recurrence (one wave)
+    // phase B: reverse recurrence (one wave); the others clear the chunk's sums
+    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) (&gacc[0][0])[q] = 0.0f;
     if (wave == 0) {
-      for (int e = n - 1; e >= 0; --e) {
-        const float araw = abuf[e][lane];
-        float da = 0.0f, w = 0.0f;
-        if (araw >= 0.0f && araw >= alpha_min) {
-          const ViewRec& R = recs[e];
+      // each pixel visits only the entries it blended, nearest-last first
+      const uint32_t m0 = hmask[lane];
+      uint32_t m = m0;
+      while (__ballot(m != 0u) != 0ull) {
+        if (m != 0u) {
+          const int e = 31 - __clz(m);
+          m ^= 1u << e;
+          const float araw = abuf[e][lane];
+          const float e2 = e2buf[e][lane];
           const float a = fminf(araw, alpha_clamp);
-          float T;
-          if (first) { T = Tb; first = false; }
-          else T = Tnext * rcp(1.0f - a);
+          const float T = first ? Tb : Tnext * rcp(1.0f - a);
+          first = false;
           Tnext = T;
-          w = T * a;
-          const float sdot = gr[0] * R.c[0] + gr[1] * R.c[1] + gr[2] * R.c[2] + gr[3] + gr[4] * R.zt +
-                             gr[5] * R.n[0] + gr[6] * R.n[1] + gr[7] * R.n[2];
-          da = T * (sdot - Rbehind);
+          const float sdot = gr[0] * feat[0][e] + gr[1] * feat[1][e] + gr[2] * feat[2][e] + gr[3] +
+                             gr[4] * feat[3][e] + gr[5] * feat[4][e] + gr[6] * feat[5][e] + gr[7] * feat[6][e];
+          const float da = araw > alpha_clamp ? 0.0f : T * (sdot - Rbehind);
           Rbehind = a * sdot + (1.0f - a) * Rbehind;
-          if (araw > alpha_clamp) da = 0.0f;
+          // chain dL/dalpha through Eq. 1 here, so phase C needs neither alpha nor e2
+          float dd, dfn;
+          eq1_chain(da, araw, e2, s, dd, dfn);
+          abuf[e][lane] = dd;
+          e2buf[e][lane] = dfn;
+          wbuf[e][lane] = T * a;
         }
-        dabuf[e][lane] = da;
-        wbuf[e][lane] = w;
       }
+      // lane e: the pixels that blended entry e (the pairs of phase C)
+      uint32_t any = m0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+      any = __builtin_amdgcn_readfirstlane(any);
+      uint64_t cmask_e = 0ull;
+      for (uint32_t t = any; t != 0u; t &= t - 1u) {
+        const int e = __ffs(t) - 1;
+        const uint64_t b = __ballot((m0 >> e) & 1u);
+        cmask_e = ((int)lane == e) ? b : cmask_e;
+      }
+      pair_offsets<CHB, 16>(n, cmask_e, pmask, poff);
     }
     __syncthreads();
-    // phase C: per-entry gradients, reduced over the tile
-    for (int e = wave; e < n; e += NWV) {
-      const float da = dabuf[e][lane], w = wbuf[e][lane];
-      const bool contrib = (da != 0.0f) || (w != 0.0f);
-      if (__ballot(contrib) == 0ull) {
-        if (lane < (unsigned)TGRAD_STRIDE) gacc[e][lane] = 0.0f;
-        continue;
-      }
-      float g[32];
+    // phase C: the gradient of every contributing (entry, pixel) pair.  Each
+    // entry's pairs fill 16-lane groups (four per wave); a group is summed
+    // with row DPP and added to the entry's sum (LDS float add: an entry with
+    // more than 16 contributing pixels spans several groups).
+    {
+      const uint32_t ngroups = poff[n];
+      const int l16 = (int)(lane & 15u);
+      for (uint32_t g0 = (uint32_t)wave * 4u; g0 < ngroups; g0 += 4u * NWV) {
+        const uint32_t grp = g0 + (lane >> 4);
+        float g[32];
 #pragma unroll
-      for (int q = 0; q < 32; ++q) g[q] = 0.0f;
-      if (contrib) {
-        const float alpha = abuf[e][lane];
-        pair_grad(recs[e], qx, qy, s, gr, da, w, alpha, e2buf[e][lane], sel[e][lane], g);
+        for (int q = 0; q < 32; ++q) g[q] = 0.0f;
+        int e = 0;
+        if (grp < ngroups) {
+          e = entry_of<CHB>(n, poff, grp);
+          const uint64_t m = pmask[e];
+          const uint32_t k = (grp - poff[e]) * 16u + (uint32_t)l16;
+          if (k < (uint32_t)__popcll(m)) {
+            const int pix = select_bit(m, k);
+            const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
+            float grp8[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) grp8[q] = grs[q][pix];
+            pair_grad_f(recs[e], px_, py_, grp8, abuf[e][pix], e2buf[e][pix], wbuf[e][pix], sel[e][pix], g);
+          }
+        }
+        const float2 r = row_transpose_sum32(g);
+        if (grp < ngroups && 2 * l16 < TGRAD_STRIDE - 1) {
+          atomicAdd(&gacc[e][2 * l16], r.x);
+          if (2 * l16 + 1 < TGRAD_STRIDE - 1) atomicAdd(&gacc[e][2 * l16 + 1], r.y);
+        }
       }
-      const float tot = wave_transpose_sum32(g);
-      const unsigned q = lane >> 1;
-      if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
     }
     __syncthreads();
     store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT);

@@ -115,8 +115,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
                                                             float t_min, int nw) {
   constexpr int NT = 64 * NWV;
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   int32_t* last_out = at<int32_t>(ws, L.o_last);
@@ -127,10 +125,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   __shared__ float pay[WSLOTS][8][64];  // per slot: alpha, c[3], zt, n[3]
   __shared__ unsigned long long done_mask;
 
-  const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = sc[V.scene].s;
-  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float s = V.s;
+  const uint32_t start = c.start, end = c.end;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
 
@@ -235,8 +233,6 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
                                                                 float alpha_clamp, float t_min, int nw) {
   constexpr int NT = 64 * NWV;
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   float* tgrad = at<float>(ws, L.o_tgrad);
@@ -251,10 +247,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   __shared__ float gacc[CHW][TGRAD_STRIDE];
   __shared__ unsigned long long done_mask;
 
-  const Tile8 c = tile8(vw, L.nv, at<const uint32_t>(ws, L.o_tile_order));
+  const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = sc[V.scene].s;
-  const uint32_t start = ranges[2 * (size_t)c.tile], end = ranges[2 * (size_t)c.tile + 1];
+  const float s = V.s;
+  const uint32_t start = c.start, end = c.end;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   const size_t plane = (size_t)V.W * V.H;

@@ -26,15 +26,19 @@ __device__ __forceinline__ bool has_pixel(const ViewRec& R, int i, int j) {
 
 struct Tile8 {
   int view, tile;
-  int tx, ty;     // tile coordinates inside the view
-  int i, j;
+  int tx, ty;            // tile coordinates inside the view
+  int i, j;              // this lane's pixel
   bool inside;
+  uint32_t start, end;   // the tile's entry range
 };
 
-__device__ __forceinline__ Tile8 tile8(const DevView* vw, int nv, const uint32_t* order) {
+__device__ __forceinline__ Tile8 tile8(const DevView* vw, const TileSlot* slots) {
   Tile8 c;
-  c.tile = (int)order[blockIdx.x];
-  c.view = find_view_by_tile(vw, nv, c.tile);
+  const TileSlot sl = slots[blockIdx.x];
+  c.tile = (int)sl.tile;
+  c.view = (int)sl.view;
+  c.start = sl.start;
+  c.end = sl.end;
   const DevView& V = vw[c.view];
   const int lt = c.tile - V.tile_base;
   const int lane = threadIdx.x & 63;
@@ -103,15 +107,14 @@ __device__ __forceinline__ int select_bit(uint64_t m, uint32_t k) {
   return pos;
 }
 
-// Wave 0, lane e < n: entry e's pair mask is its rectangle & live_e (the
-// pixels that still take part for that entry).  Writes pmask[0..CH) and the
-// exclusive offsets poff[0..CH] (poff[n] = number of pairs).
-template <int CH>
-__device__ __forceinline__ void chunk_pairs(const ViewRec* recs, int n, const Tile8& c, uint64_t live_e,
-                                            uint64_t* pmask, uint32_t* poff) {
+// Wave 0, lane e < n: m_e is entry e's pair mask.  Writes pmask[0..CH) and
+// the exclusive offsets poff[0..CH] of the entries' pairs counted in groups
+// of GROUP (poff[n] = number of groups).
+template <int CH, int GROUP = 1>
+__device__ __forceinline__ void pair_offsets(int n, uint64_t m_e, uint64_t* pmask, uint32_t* poff) {
   const int lane = threadIdx.x & 63;
-  const uint64_t m = lane < n ? rect_mask(recs[lane], c) & live_e : 0ull;
-  uint32_t x = (uint32_t)__popcll(m);
+  const uint64_t m = lane < n ? m_e : 0ull;
+  uint32_t x = ((uint32_t)__popcll(m) + (GROUP - 1)) / GROUP;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const uint32_t y = __shfl_up(x, d, 64);
@@ -124,21 +127,75 @@ __device__ __forceinline__ void chunk_pairs(const ViewRec* recs, int n, const Ti
   if (lane == 0) poff[0] = 0u;
 }
 
+// Wave 0, lane e < n: entry e's pairs are the pixels of its rectangle in
+// live_e (the pixels that still take part for that entry).
+template <int CH>
+__device__ __forceinline__ void chunk_pairs(const ViewRec* recs, int n, const Tile8& c, uint64_t live_e,
+                                            uint64_t* pmask, uint32_t* poff) {
+  const int lane = threadIdx.x & 63;
+  pair_offsets<CH>(n, lane < n ? rect_mask(recs[lane], c) & live_e : 0ull, pmask, poff);
+}
+
+// Last entry whose first pair (or group) is at or before p.
+template <int CH>
+__device__ __forceinline__ int entry_of(int n, const uint32_t* poff, uint32_t p) {
+  int e = 0;
+#pragma unroll
+  for (int step = CH / 2; step > 0; step >>= 1) {
+    const int t = e + step;
+    e = (t < n && poff[t] <= p) ? t : e;
+  }
+  return e;
+}
+
 // All threads: f(e, pix) for every listed pair (entry e, local pixel pix).
 template <int CH, class F>
 __device__ __forceinline__ void for_each_pair(int n, const uint64_t* pmask, const uint32_t* poff, int nthreads,
                                               F&& f) {
   const uint32_t total = poff[n];
   for (uint32_t p = threadIdx.x; p < total; p += (uint32_t)nthreads) {
-    int e = 0;  // last entry whose first pair is at or before p
-#pragma unroll
-    for (int step = CH / 2; step > 0; step >>= 1) {
-      const int t = e + step;
-      e = (t < n && poff[t] <= p) ? t : e;
-    }
+    const int e = entry_of<CH>(n, poff, p);
     f(e, select_bit(pmask[e], p - poff[e]));
   }
 }
+
+// Software pipeline of the chunk loads: while a chunk is processed, the next
+// chunk's records are in flight into registers and the record indices of the
+// one after it are in flight too, so a chunk's two dependent global loads
+// overlap the previous chunk's work.  Each thread owns PQ of the chunk's
+// 16-byte record parts.
+template <int CH, int NT>
+struct RecPipe {
+  static constexpr int PQ = (CH * 8 + NT - 1) / NT;
+  uint32_t idx[PQ];
+  float vx[PQ], vy[PQ], vz[PQ], vw[PQ];  // scalars, so the parts stay in registers
+  __device__ __forceinline__ void fetch_idx(const uint32_t* __restrict__ srec, uint32_t base, int n) {
+#pragma unroll
+    for (int j = 0; j < PQ; ++j) {
+      const int q = (int)threadIdx.x + j * NT;
+      idx[j] = q < n * 8 ? srec[base + (uint32_t)(q >> 3)] : 0u;
+    }
+  }
+  // unconditional: a part past the chunk reads record 0 (allocated) and is never stored
+  __device__ __forceinline__ void fetch_rec(const ViewRec* __restrict__ vrec) {
+#pragma unroll
+    for (int j = 0; j < PQ; ++j) {
+      const int q = (int)threadIdx.x + j * NT;
+      const float4 t = reinterpret_cast<const float4*>(vrec)[(size_t)idx[j] * 8 + (size_t)(q & 7)];
+      vx[j] = t.x;
+      vy[j] = t.y;
+      vz[j] = t.z;
+      vw[j] = t.w;
+    }
+  }
+  __device__ __forceinline__ void store(ViewRec* recs, int n) const {
+#pragma unroll
+    for (int j = 0; j < PQ; ++j) {
+      const int q = (int)threadIdx.x + j * NT;
+      if (q < n * 8) reinterpret_cast<float4*>(&recs[q >> 3])[q & 7] = make_float4(vx[j], vy[j], vz[j], vw[j]);
+    }
+  }
+};
 
 }  // namespace
 }  // namespace ts

@@ -178,12 +178,27 @@ __device__ __forceinline__ void face_geom_grad(const ViewRec& R, const float (&a
   g[G_PY + C] += a[0] * Bx - a[1] * Ax;
 }
 
-// g (zeroed by the caller) <- the pair's gradient.  w = T alpha is the blend
-// weight (colour, depth and normal enter linearly); da = dL/dalpha (zero when
-// alpha was clamped); alpha, e2 = exp(s f_next) and the entry/exit faces
-// fs = fe | fx << 2 are the values of the pair's forward evaluation.
-__device__ __forceinline__ void pair_grad(const ViewRec& R, float qx, float qy, float s, const float (&gr)[8],
-                                          float da, float w, float alpha, float e2, int fs, float (&g)[32]) {
+// dL/dalpha of a pair chained through Eq. 1 (stable form) to its entry and
+// exit SDF values: alpha = A / B, A = -expm1(-s d), B = 1 + exp(s f_next),
+// d = f_prev - f_next; e2 = exp(s f_next).  Zero when alpha is zero (the
+// max(., 0) of Eq. 1).
+__device__ __forceinline__ void eq1_chain(float da, float alpha, float e2, float s, float& dd, float& dfn) {
+  const bool on = da != 0.0f && alpha > 0.0f;
+  const float B = 1.0f + e2;
+  const float invB = rcp(B);
+  const float e1p1 = 1.0f - alpha * B;                   // exp(-s d) = 1 + expm1(-s d)
+  const float dA = da * invB;
+  const float dB = -da * alpha * invB;
+  const float ddv = dA * s * e1p1;                       // d/df_prev
+  dd = on ? ddv : 0.0f;
+  dfn = on ? dB * s * e2 - ddv : 0.0f;                   // d/df_next
+}
+
+// g (zeroed by the caller) <- the pair's gradient, given the blend weight
+// w = T alpha (colour, depth and normal enter linearly), dL/df_prev = dd and
+// dL/df_next = dfn, and the entry/exit faces fs = fe | fx << 2.
+__device__ __forceinline__ void pair_grad_f(const ViewRec& R, float qx, float qy, const float (&gr)[8], float dd,
+                                            float dfn, float w, int fs, float (&g)[32]) {
   g[G_C + 0] = w * gr[0];
   g[G_C + 1] = w * gr[1];
   g[G_C + 2] = w * gr[2];
@@ -191,15 +206,7 @@ __device__ __forceinline__ void pair_grad(const ViewRec& R, float qx, float qy, 
   g[G_N + 0] = w * gr[5];
   g[G_N + 1] = w * gr[6];
   g[G_N + 2] = w * gr[7];
-  if (da != 0.0f && alpha > 0.0f) {
-    // alpha = A / B, A = -expm1(-s d), B = 1 + exp(s f_next)
-    const float B = 1.0f + e2;
-    const float invB = rcp(B);
-    const float e1p1 = 1.0f - alpha * B;                 // exp(-s d) = 1 + expm1(-s d)
-    const float dA = da * invB;
-    const float dB = -da * alpha * invB;
-    const float dd = dA * s * e1p1;                      // d/df_prev
-    const float dfn = dB * s * e2 - dd;                  // d/df_next
+  if (dd != 0.0f || dfn != 0.0f) {
     const int fe = fs & 3, fx = fs >> 2;
     float ax[4], ay[4];
 #pragma unroll
@@ -222,6 +229,14 @@ __device__ __forceinline__ void pair_grad(const ViewRec& R, float qx, float qy, 
     if (w2 != 0.0f) face_geom_grad<2>(R, ax, ay, e23, -e03, e02, w2, g);
     if (w3 != 0.0f) face_geom_grad<3>(R, ax, ay, e23, -e13, e12, w3, g);
   }
+}
+
+// The same from dL/dalpha = da, the raw alpha and e2 = exp(s f_next).
+__device__ __forceinline__ void pair_grad(const ViewRec& R, float qx, float qy, float s, const float (&gr)[8],
+                                          float da, float w, float alpha, float e2, int fs, float (&g)[32]) {
+  float dd, dfn;
+  eq1_chain(da, alpha, e2, s, dd, dfn);
+  pair_grad_f(R, qx, qy, gr, dd, dfn, w, fs, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -269,6 +284,45 @@ __device__ __forceinline__ float wave_transpose_sum32(const float (&v)[32]) {
   float z = keep + dpp<0x4E>(send);   // quad_perm [2,3,0,1]
   z = z + dpp<0xB1>(z);               // quad_perm [1,0,3,2]
   return z;
+}
+
+
+// Per 16-lane row (gfx950 DPP row operations only): afterwards lane L of a
+// row holds, in .x and .y, the sums over the row's 16 lanes of v[2 (L & 15)]
+// and v[2 (L & 15) + 1].  Each step halves the values per lane while pairing
+// lanes 8, 4 (half-row mirror), 2 and 1 apart.  Every lane must be active.
+__device__ __forceinline__ float2 row_transpose_sum32(const float (&v)[32]) {
+  const unsigned lane = __lane_id();
+  const bool b3 = lane & 8u, b2 = lane & 4u, b1 = lane & 2u, b0 = lane & 1u;
+  float x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float send = b3 ? v[k] : v[k + 16];
+    const float keep = b3 ? v[k + 16] : v[k];
+    x[k] = keep + dpp<0x128>(send);   // row_ror:8   (j <-> j ^ 8)
+  }
+  float y[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float send = b2 ? x[k] : x[k + 8];
+    const float keep = b2 ? x[k + 8] : x[k];
+    y[k] = keep + dpp<0x141>(send);   // row_half_mirror (j <-> j ^ 7 in each half-row)
+  }
+  float z[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float send = b1 ? y[k] : y[k + 4];
+    const float keep = b1 ? y[k + 4] : y[k];
+    z[k] = keep + dpp<0x4E>(send);    // quad_perm [2,3,0,1] (j <-> j ^ 2)
+  }
+  float u[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float send = b0 ? z[k] : z[k + 2];
+    const float keep = b0 ? z[k + 2] : z[k];
+    u[k] = keep + dpp<0xB1>(send);    // quad_perm [1,0,3,2] (j <-> j ^ 1)
+  }
+  return make_float2(u[0], u[1]);
 }
 
 }  // namespace ts

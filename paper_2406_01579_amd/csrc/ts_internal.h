@@ -41,7 +41,15 @@ struct DevView {
   int32_t tiles_x, tiles_y;
   int32_t tile_base;    // first global tile id of this view
   int32_t pix_base;     // first global pixel id of this view
-  int32_t pad;
+  float s;              // steepness of Eq. 1 of the view's scene
+};
+
+// One compositing workgroup's tile, in dispatch order (longest list first),
+// so that a workgroup finds its tile, view and entry range in one load.
+struct TileSlot {
+  uint32_t tile;        // global tile id
+  uint32_t view;
+  uint32_t start, end;  // the tile's entry range
 };
 
 // device-written counters at the start of the workspace
@@ -114,6 +122,8 @@ struct Layout {
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
   size_t o_ranges, o_tile_hist, o_tile_order, o_tgrad, o_last, o_tlast;
+  size_t o_tile_pend;    // per dispatch slot: end of the entries the forward blended (backward walk)
+  size_t o_bwd_hist, o_bwd_order, o_bwd_pend;  // backward dispatch order (by walked length)
   size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
   size_t bytes;
 };
@@ -146,7 +156,8 @@ hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStr
 hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st);
-constexpr int TILE_BUCKETS = 33;  // tiles bucketed by bit length of their list size
+constexpr int TILE_BUCKETS = 129;  // tiles bucketed by list length, four buckets per power of two
+hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_composite(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st);
