@@ -24,7 +24,8 @@ template <int NWV, int CHN>
 __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, const uint32_t* __restrict__ srec,
                                               uint32_t start, uint32_t end, const Tile8& c, float s, float alpha_min,
                                               float alpha_clamp, float t_min, ViewRec* recs, float (*alds)[64],
-                                              uint64_t* pmask, uint32_t* poff, unsigned long long* done_mask,
+                                              uint64_t* pmask, uint32_t* poff, uint64_t* hm, float (*feat)[CHN],
+                                              unsigned long long* done_mask,
                                               float& T, float& Tb, float& O, float (&acc)[7], int& last,
                                               bool want_acc) {
   constexpr int NT = 64 * NWV;
@@ -50,43 +51,53 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
     if (end - base > (uint32_t)CHN) rp.fetch_rec(vrec);
     if (end - base > 2u * CHN) rp.fetch_idx(srec, base + 2 * CHN, (int)min((uint32_t)CHN, end - base - 2 * CHN));
     __syncthreads();
-    // phase A: coverage and Eq. 1 of the live (entry, pixel) pairs, packed
-    for (int q = threadIdx.x; q < n * 16; q += NT)
-      reinterpret_cast<float4*>(&alds[0][0])[q] = make_float4(-1.0f, -1.0f, -1.0f, -1.0f);
+    // phase A: coverage and Eq. 1 of the live (entry, pixel) pairs, packed;
+    // hm[pixel] collects the chunk entries the pixel may blend
+    if (threadIdx.x < 64) hm[threadIdx.x] = 0ull;
+    for (int q = threadIdx.x; q < n * 7; q += NT) {
+      const int e = q / 7, k = q - e * 7;
+      feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
+    }
     if (wave == 0) chunk_pairs<CHN>(recs, n, c, ~*done_mask, pmask, poff);
     __syncthreads();
     for_each_pair<CHN>(n, pmask, poff, NT, [&](int e, int pix) {
       const float qx = (float)(c.tx * 8 + (pix & 7)) + 0.5f, qy = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
       PixEval h;
-      alds[e][pix] = pixel_eval(recs[e], qx, qy, s, h) ? h.alpha : -1.0f;
+      if (pixel_eval(recs[e], qx, qy, s, h) && h.alpha >= alpha_min) {
+        alds[e][pix] = h.alpha;
+        atomicOr(&hm[pix], 1ull << e);
+      }
     });
     __syncthreads();
     if (wave == 0) {
-      // branch-free so that the LDS reads of later entries issue early
-#pragma unroll 4
-      for (int e = 0; e < n; ++e) {
-        const float a = alds[e][lane];
-        const ViewRec& R = recs[e];
-        const bool live = !done && a >= 0.0f && a >= alpha_min;
-        const float ac = fminf(a, alpha_clamp);
-        const float Tn = T * (1.0f - ac);
-        const bool stop = live && Tn < t_min;
-        const bool blend = live && !stop;
-        const float w = blend ? T * ac : 0.0f;   // w = 0 leaves every sum unchanged
-        if (want_acc) {
-          acc[0] = fmaf(w, R.c[0], acc[0]);
-          acc[1] = fmaf(w, R.c[1], acc[1]);
-          acc[2] = fmaf(w, R.c[2], acc[2]);
-          acc[3] = fmaf(w, R.zt, acc[3]);
-          acc[4] = fmaf(w, R.n[0], acc[4]);
-          acc[5] = fmaf(w, R.n[1], acc[5]);
-          acc[6] = fmaf(w, R.n[2], acc[6]);
-          O += w;
+      // each pixel visits only its candidate entries, front to back
+      uint64_t cand = hm[lane];
+      while (__ballot(cand != 0ull && !done) != 0ull) {
+        if (cand != 0ull && !done) {
+          const int e = __ffsll((unsigned long long)cand) - 1;
+          cand &= cand - 1ull;
+          const float a = fminf(alds[e][lane], alpha_clamp);
+          const float Tn = T * (1.0f - a);
+          if (Tn < t_min) {
+            done = true;
+          } else {
+            const float w = T * a;
+            if (want_acc) {
+              acc[0] = fmaf(w, feat[0][e], acc[0]);
+              acc[1] = fmaf(w, feat[1][e], acc[1]);
+              acc[2] = fmaf(w, feat[2][e], acc[2]);
+              acc[3] = fmaf(w, feat[3][e], acc[3]);
+              acc[4] = fmaf(w, feat[4][e], acc[4]);
+              acc[5] = fmaf(w, feat[5][e], acc[5]);
+              acc[6] = fmaf(w, feat[6][e], acc[6]);
+              O += w;
+            }
+            Tb = T;
+            T = Tn;
+            last = (int)(base + e);
+            if (T == 0.0f) done = true;
+          }
         }
-        Tb = blend ? T : Tb;
-        T = blend ? Tn : T;
-        last = blend ? (int)(base + e) : last;
-        done = done || stop || (blend && Tn == 0.0f);
       }
       const unsigned long long m = __ballot(done);
       if (lane == 0) *done_mask = m;
@@ -110,6 +121,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   __shared__ float alds[CHN][64];
   __shared__ uint64_t pmask[CHN];
   __shared__ uint32_t poff[CHN + 1];
+  __shared__ uint64_t hm[64];
+  __shared__ float feat[7][CHN];
   __shared__ unsigned long long done_mask;
 
   const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
@@ -119,8 +132,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int last = -1;
-  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff,
-                          &done_mask, T, Tb, O, acc, last, true);
+  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff, hm,
+                          feat, &done_mask, T, Tb, O, acc, last, true);
   if ((threadIdx.x >> 6) == 0) {
     // end of the tile's blended prefix: where the backward starts its walk
     int wmax = last;
@@ -167,7 +180,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   __shared__ float grs[8][64];       // upstream gradient of each pixel
   __shared__ uint64_t pmask[CHB];
   __shared__ uint32_t poff[CHB + 1];
-  __shared__ uint32_t hmask[64];     // per pixel: chunk entries it blended (bit e)
+  __shared__ uint64_t hmask[64];     // per pixel: chunk entries it blended (bit e)
   __shared__ float feat[7][CHB];     // per entry: c[3], zt, n[3] (conflict-free gathers)
   __shared__ unsigned long long done_mask;
   __shared__ int smax;
@@ -195,7 +208,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     float T = 1.0f, O = 0.0f;
     float acc[7];
     forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, pmask, poff,
-                            &done_mask, T, Tb, O, acc, last, false);
+                            hmask, feat, &done_mask, T, Tb, O, acc, last, false);
     if (wave == 0) {
       int wmax = last;
 #pragma unroll
@@ -242,9 +255,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     __syncthreads();
     // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's
     // walk reached (entry at or before its last blend), packed
-    for (int q = threadIdx.x; q < n * 16; q += NT)
-      reinterpret_cast<float4*>(&abuf[0][0])[q] = make_float4(-1.0f, -1.0f, -1.0f, -1.0f);
-    if (threadIdx.x < 64) hmask[threadIdx.x] = 0u;
+    if (threadIdx.x < 64) hmask[threadIdx.x] = 0ull;
     for (int q = threadIdx.x; q < n * 7; q += NT) {
       const int e = q / 7, k = q - e * 7;
       feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         abuf[e][pix] = h.alpha;
         e2buf[e][pix] = h.e2;
         sel[e][pix] = (uint8_t)(h.fe | (h.fx << 2));
-        if (h.alpha >= alpha_min) atomicOr(&hmask[pix], 1u << e);
+        if (h.alpha >= alpha_min) atomicOr(&hmask[pix], 1ull << e);
       }
     });
     __syncthreads();
@@ -273,7 +284,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) (&gacc[0][0])[q] = 0.0f;
     if (wave == 0) {
       // each pixel visits only the entries it blended, nearest-last first
-      const uint32_t m0 = hmask[lane];
+      const uint32_t m0 = (uint32_t)hmask[lane];   // CHB = 32 entries
       uint32_t m = m0;
       while (__ballot(m != 0u) != 0ull) {
         if (m != 0u) {
