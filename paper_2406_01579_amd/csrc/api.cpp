@@ -180,6 +180,12 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   int kb = 1;
   while (((int64_t)1 << kb) < tiles) ++kb;
   L.key2_bits = kb;
+  {
+    std::vector<int> vps(ns, 0);
+    for (int v = 0; v < nv; ++v) ++vps[views[v].scene];
+    L.max_scene_views = 0;
+    for (int s = 0; s < ns; ++s) L.max_scene_views = vps[s] > L.max_scene_views ? vps[s] : L.max_scene_views;
+  }
 
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at_ = o; o = align_up(o + bytes, 256); return at_; };
@@ -207,7 +213,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_key2b = take(4 * (size_t)entry_cap);
   L.o_val2a = take(4 * (size_t)entry_cap);
   L.o_val2b = take(4 * (size_t)entry_cap);
-  L.o_eflag = take((size_t)entry_cap + 4);
+  L.o_eflag = take((size_t)entry_cap + 16);  // padded: the vertex backward reads aligned 8-byte words
   L.o_ranges = take(8 * (size_t)tiles);
   L.o_tile_hist = take(4 * 2 * (size_t)TILE_BUCKETS);  // right after the ranges: cleared together
   L.o_tile_order = take(sizeof(TileSlot) * (size_t)tiles);

@@ -116,6 +116,7 @@ struct Layout {
   int64_t kept_cap, rec_cap, entry_cap;
   int64_t pf_blocks, scan_blocks_rec, sort_blocks_max, total_tiles, total_pixels;
   int key2_bits;
+  int max_scene_views;  // largest number of views of one scene
   size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_rec_off, o_off_sorted, o_scan_part;

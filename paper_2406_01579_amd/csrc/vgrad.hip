@@ -1,15 +1,29 @@
-// Per-tet backward of the gfx950 tetrahedron rasterizer.  One thread per
-// kept tet: for every view of the tet's scene it sums the per-entry
-// screen-space gradients of the (view, tet) record over the tiles the record
-// was binned to and chains them through the projection and the mean depth to
-// world-space vertex positions; the view-independent parts -- the SDF
-// values, the per-tet normal n = g/|g| (App. A.3, as the equivalent 3x3 edge
-// system g = E^-1 (f_k - f_0)) and the mean colour -- are chained once per
-// tet.  The result is added to the per-vertex gradients (float atomics).
+// Per-tet backward of the gfx950 tetrahedron rasterizer.  A group of P
+// adjacent lanes (P a power of two covering the largest view count of a
+// scene) owns one kept tet; lane q takes the tet's records in views q, q + P,
+// ...: it sums each record's per-entry screen-space gradients over the tiles
+// the record was binned to (the entries the compositing backward reached are
+// flagged) and chains them through the projection and the mean depth to the
+// vertex positions.  The group then sums over its lanes, and its first lane
+// chains the view-independent parts -- the SDF values, the tet normal
+// n = g/|g| (App. A.3, as the equivalent 3x3 edge system g = E^-1 (f_k - f_0))
+// and the mean colour -- and adds the result to the per-vertex gradients
+// (float atomics, one set per tet).  A record's loads form short dependent
+// rounds (the record, then its entry flags, then the flagged entries), and
+// the views of a tet are in flight together.
 #include "ts_device.h"
 
 namespace ts {
 
+// sum over aligned groups of P lanes (P a power of two <= 64)
+template <int P>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int P>
 __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
@@ -25,69 +39,113 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
   const uint32_t nk = min(hdr->kept_total, (uint32_t)L.kept_cap);
   const uint32_t nrec = hdr->records_total;
   const uint64_t cap = (uint64_t)L.entry_cap;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nk; k += gridDim.x * blockDim.x) {
-    const TetRec& T = trec[k];
-    const DevScene& S = sc[T.scene];
-    const uint32_t kl = k - (uint32_t)kbase[T.scene];
+  const int q0 = (int)(threadIdx.x % P);
+  const uint32_t stride = gridDim.x * (blockDim.x / P);
+  // the loop runs the same number of times in every lane of a group
+  for (uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) / P; k < nk + (stride - nk % stride) % stride;
+       k += stride) {
+    const bool tet_ok = k < nk;
+    const TetRec& T = trec[tet_ok ? k : 0u];
     float dv[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     float dfv[4] = {0, 0, 0, 0}, dn[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
     bool any = false;
-    for (int q = 0; q < S.view_count; ++q) {
-      const int v = scene_views[S.view_first + q];
-      const uint32_t r = (uint32_t)rbase[v] + kl;
-      if (r >= nrec) continue;
-      const uint32_t cnt = count1[r];
-      if (cnt == 0) continue;
-      const ViewRec& R = vrec[r];
-      const DevView& V = vw[v];
-      const uint32_t o = R.entry0;
-      float g[23];
-      for (int z = 0; z < 23; ++z) g[z] = 0.0f;
-      bool hit = false;
-      // the record's entries, one per tile it was binned to; the compositing
-      // backward flags the ones it reached
-      for (uint32_t j = 0; j < cnt; ++j) {
-        const uint64_t d = (uint64_t)o + j;
-        if (d >= cap) break;
-        if (!eflag[d]) continue;
-        const float4* src = reinterpret_cast<const float4*>(tgrad + (size_t)d * TGRAD_STRIDE);
+    if (tet_ok) {
+      const DevScene& S = sc[T.scene];
+      const uint32_t kl = k - (uint32_t)kbase[T.scene];
+      for (int q = q0; q < S.view_count; q += P) {
+        const int v = scene_views[S.view_first + q];
+        const uint32_t r = (uint32_t)rbase[v] + kl;
+        if (r >= nrec) continue;
+        const uint32_t cnt = count1[r];
+        if (cnt == 0) continue;
+        const ViewRec& R = vrec[r];
+        const uint32_t o = R.entry0;
+        const uint32_t n = (uint32_t)min((uint64_t)cnt, cap > o ? cap - o : 0ull);
+        if (n == 0u) continue;  // entries past the capacity (an overflowed forward)
+        // reached flags, bit j for entry o + j: the first eight from two
+        // aligned 8-byte words (the flag array is padded for this), the rest
+        // (records binned to more than eight tiles) byte by byte
+        uint32_t fl = 0u;
+        {
+          const uint64_t* w8 = reinterpret_cast<const uint64_t*>(eflag + ((size_t)o & ~(size_t)7));
+          const uint64_t a = w8[0], b = w8[1];
+          const int sh = (int)(o & 7u) * 8;
+          const uint64_t lo = sh ? (a >> sh) | (b << (64 - sh)) : a;
 #pragma unroll
-        for (int z = 0; z < 6; ++z) {
-          const float4 x = src[z];
-          if (4 * z + 0 < 23) g[4 * z + 0] += x.x;
-          if (4 * z + 1 < 23) g[4 * z + 1] += x.y;
-          if (4 * z + 2 < 23) g[4 * z + 2] += x.z;
-          if (4 * z + 3 < 23) g[4 * z + 3] += x.w;
+          for (int j = 0; j < 8; ++j) fl |= ((lo >> (8 * j)) & 0xffull) ? (1u << j) : 0u;
+          for (uint32_t j = 8; j < n && j < 32u; ++j) fl |= eflag[o + j] ? (1u << j) : 0u;
+          if (n < 32u) fl &= (1u << n) - 1u;
         }
-        hit = true;
+        float g[23];
+#pragma unroll
+        for (int z = 0; z < 23; ++z) g[z] = 0.0f;
+        bool hit = false;
+        for (uint32_t t = fl; t != 0u; t &= t - 1u) {
+          const uint64_t d = (uint64_t)o + (uint64_t)(__ffs(t) - 1);
+          const float4* src = reinterpret_cast<const float4*>(tgrad + (size_t)d * TGRAD_STRIDE);
+#pragma unroll
+          for (int z = 0; z < 6; ++z) {
+            const float4 x = src[z];
+            if (4 * z + 0 < 23) g[4 * z + 0] += x.x;
+            if (4 * z + 1 < 23) g[4 * z + 1] += x.y;
+            if (4 * z + 2 < 23) g[4 * z + 2] += x.z;
+            if (4 * z + 3 < 23) g[4 * z + 3] += x.w;
+          }
+          hit = true;
+        }
+        // a record binned to more than 32 tiles: the rest one by one
+        for (uint32_t j = 32; j < n; ++j) {
+          const uint64_t d = (uint64_t)o + j;
+          if (!eflag[d]) continue;
+          const float* src = tgrad + (size_t)d * TGRAD_STRIDE;
+          for (int z = 0; z < 23; ++z) g[z] += src[z];
+          hit = true;
+        }
+        if (!hit) continue;
+        any = true;
+        const DevView& V = vw[v];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float x = T.x[a][0], y = T.x[a][1], z = T.x[a][2];
+          const float X = fmaf(V.R[0], x, fmaf(V.R[1], y, fmaf(V.R[2], z, V.t[0])));
+          const float Y = fmaf(V.R[3], x, fmaf(V.R[4], y, fmaf(V.R[5], z, V.t[1])));
+          const float iz = R.iz[a];
+          // x' = fx X/Z + cx, y' = fy Y/Z + cy; w = 1/Z; z_t = mean Z
+          const float dpx = g[G_PX + a] * V.fx, dpy = g[G_PY + a] * V.fy;
+          const float dX = dpx * iz, dY = dpy * iz;
+          float dZ = -(dpx * X + dpy * Y) * iz * iz;
+          dZ += -g[G_IZ + a] * iz * iz;
+          dZ += 0.25f * g[G_ZT];
+#pragma unroll
+          for (int m = 0; m < 3; ++m) dv[a][m] += V.R[m] * dX + V.R[3 + m] * dY + V.R[6 + m] * dZ;
+          dfv[a] += g[G_F + a];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          dn[m] += g[G_N + m];
+          dc[m] += g[G_C + m];
+        }
       }
-      if (!hit) continue;
-      any = true;
+    }
+    // sum over the tet's lanes
+    if (P > 1) {
+      any = __ballot(any) & (((1ull << (P - 1)) << 1) - 1ull) << (threadIdx.x % 64 / P * P);
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const float x = T.x[a][0], y = T.x[a][1], z = T.x[a][2];
-        const float X = fmaf(V.R[0], x, fmaf(V.R[1], y, fmaf(V.R[2], z, V.t[0])));
-        const float Y = fmaf(V.R[3], x, fmaf(V.R[4], y, fmaf(V.R[5], z, V.t[1])));
-        const float iz = R.iz[a];
-        // x' = fx X/Z + cx, y' = fy Y/Z + cy; w = 1/Z; z_t = mean Z
-        const float dpx = g[G_PX + a] * V.fx, dpy = g[G_PY + a] * V.fy;
-        const float dX = dpx * iz, dY = dpy * iz;
-        float dZ = -(dpx * X + dpy * Y) * iz * iz;
-        dZ += -g[G_IZ + a] * iz * iz;
-        dZ += 0.25f * g[G_ZT];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) dv[a][m] += V.R[m] * dX + V.R[3 + m] * dY + V.R[6 + m] * dZ;
-        dfv[a] += g[G_F + a];
+        for (int m = 0; m < 3; ++m) dv[a][m] = group_sum<P>(dv[a][m]);
+        dfv[a] = group_sum<P>(dfv[a]);
       }
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        dn[m] += g[G_N + m];
-        dc[m] += g[G_C + m];
+        dn[m] = group_sum<P>(dn[m]);
+        dc[m] = group_sum<P>(dc[m]);
       }
     }
-    if (!any) continue;
+    if (!tet_ok || !any || q0 != 0) continue;
+    const DevScene& S = sc[T.scene];
     // normal: n = g/|g|, g = E^-1 df
-    {
+    if (dn[0] != 0.0f || dn[1] != 0.0f || dn[2] != 0.0f) {
       float e[3][3], df[3];
       for (int a = 0; a < 3; ++a) {
         for (int m = 0; m < 3; ++m) e[a][m] = T.x[a + 1][m] - T.x[0][m];
@@ -100,7 +158,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
                         {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
                          e[0][0] * e[1][1] - e[0][1] * e[1][0]}};
       const float det = e[0][0] * cr[0][0] + e[0][1] * cr[0][1] + e[0][2] * cr[0][2];
-      if (det != 0.0f && (dn[0] != 0.0f || dn[1] != 0.0f || dn[2] != 0.0f)) {
+      if (det != 0.0f) {
         float gg[3];
         for (int m = 0; m < 3; ++m) gg[m] = (cr[0][m] * df[0] + cr[1][m] * df[1] + cr[2][m] * df[2]) / det;
         const float gn = sqrtf(gg[0] * gg[0] + gg[1] * gg[1] + gg[2] * gg[2]);
@@ -140,7 +198,15 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
 
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
   (void)p;
-  k_vertex_bwd<<<1024, 256, 0, st>>>(ws, L);
+  // lanes per tet: the largest view count of a scene, rounded up to a power of two (at most 8)
+  const int nvs = L.max_scene_views;
+  const int64_t threads = L.kept_cap * (nvs <= 1 ? 1 : nvs <= 2 ? 2 : nvs <= 4 ? 4 : 8);
+  const int64_t b = (threads + 255) / 256;
+  const unsigned blocks = (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+  if (nvs <= 1) k_vertex_bwd<1><<<blocks, 256, 0, st>>>(ws, L);
+  else if (nvs <= 2) k_vertex_bwd<2><<<blocks, 256, 0, st>>>(ws, L);
+  else if (nvs <= 4) k_vertex_bwd<4><<<blocks, 256, 0, st>>>(ws, L);
+  else k_vertex_bwd<8><<<blocks, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 
