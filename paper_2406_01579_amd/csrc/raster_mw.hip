@@ -261,10 +261,24 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
     }
     if (wave == 0) {
-      uint64_t live_e = 0ull;
-      for (int e = 0; e < n; ++e) {
-        const uint64_t b = __ballot(c.inside && (int)(base + e) <= last);
-        live_e = ((int)lane == e) ? b : live_e;
+      // lane e: the pixels whose walk reached entry e (last >= base + e).  A
+      // pixel whose last blend lies past the chunk takes part in all of it;
+      // only the pixels whose last blend lies inside the chunk need a test
+      // per entry.
+      const int rel = c.inside ? last - (int)base : -1;
+      uint64_t live_e = __ballot(rel >= n - 1);
+      uint64_t part = __ballot(rel >= 0 && rel < n - 1);
+      if (__popcll(part) * 2 <= n) {
+        for (; part != 0ull; part &= part - 1ull) {
+          const int p = __ffsll((unsigned long long)part) - 1;
+          const int lp = __shfl(rel, p, 64);
+          live_e |= ((int)lane <= lp) ? (1ull << p) : 0ull;
+        }
+      } else {
+        for (int e = 0; e < n - 1; ++e) {
+          const uint64_t b = __ballot(rel >= e);
+          live_e = ((int)lane == e) ? b : live_e;
+        }
       }
       chunk_pairs<CHB>(recs, n, c, live_e, pmask, poff);
     }
