@@ -30,18 +30,21 @@ HBM_PEAK_GBS = 8000.0
 REC_BYTES = 128          # one ViewRec per tile entry
 ENTRY_LIST_BYTES = 4     # sorted record index per entry
 TGRAD_BYTES = 96         # per-entry screen-space gradient written by the backward
-# HBM bytes per launch of the backward compositing kernel at the default
-# workload and launch shape (8x8 tiles, 4 waves), from the rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes summarised under profiles/ (FETCH_SIZE scaled
-# by 2.0, WRITE_SIZE by 1.0 against a 256 MiB copy), and its VALU issue share
-# from SQ_INSTS_VALU.  Valid only for the kernel sources with these digests;
-# reported as null once they change.
+# HBM bytes per launch of the compositing kernels at the default workload and
+# launch shape (8x8 tiles, 4 waves), from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes summarised under profiles/ (FETCH_SIZE scaled by 2.0,
+# WRITE_SIZE by 1.0 against a 256 MiB copy), and their VALU issue share: wave
+# instructions (SQ_INSTS_VALU) x 4 cycles over 1024 SIMDs x 2.4 GHz x the
+# kernel's mean duration.  Valid only for the kernel sources with these
+# digests; reported as null once they change.
 MEASURED = {"sha256": {"paper_2406_01579_amd/csrc/raster_mw.hip":
-                       "8e74317dcf87a3562797626b0b85bbeda6c780cb4e0eba789e767a4230783673",
+                       "c72d631322147ce597215895913b0dd5f588f4a1e9f64842a62c307c1a074ae1",
                        "paper_2406_01579_amd/csrc/ts_device.h":
-                       "3887d3642a0ff29199dbc6df8a87bf9bc9b39b3ad285d8bf98cfb171a8239ba4"},
-            "composite_bwd": {"traffic": 257.2e6, "valu_issue_frac": 0.58},
-            "composite": {"traffic": 105.5e6, "valu_issue_frac": 0.61}}
+                       "dfb39772aab50edd49ce43f69084068be29722f18186b0fdbdcfac5a2f479819",
+                       "paper_2406_01579_amd/csrc/tile8.h":
+                       "34f49bd926e8c5c9da893ba5c2adbbdae2d31039d3f32a28034594845123158e"},
+            "composite_bwd": {"traffic": 117.2e6, "valu_issue_frac": 0.50},
+            "composite": {"traffic": 121.3e6, "valu_issue_frac": 0.59}}
 
 
 def measured_counters(kernel, args):
@@ -226,7 +229,9 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None if meas is None else int(meas["traffic"]),
                 "kernel": dom, "kernel_ms": round(kern[dom]["ms"], 4), "algorithmic_bytes": int(kern[dom]["bytes"]),
                 "valu_issue_frac": None if meas is None else meas["valu_issue_frac"],
-                "note": "the compositing kernels are bound by VALU issue, not HBM (valu_issue_frac from SQ_INSTS_VALU)"}
+                "note": "the compositing kernels move about their algorithmic bytes (traffic) but are bound by the "
+                        "per-tile sequential walk and its issue latency, not HBM: valu_issue_frac is the VALU issue "
+                        "share from SQ_INSTS_VALU"}
 
     # plain path: one launch sequence per view
     plain = None

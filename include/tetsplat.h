@@ -219,7 +219,7 @@ enum {
   RENDER_STAGE_SCAN = 4,        /* scan of tile counts */
   RENDER_STAGE_EMIT = 5,        /* tile-duplicated keys */
   RENDER_STAGE_TILE_SORT = 6,   /* radix sort of entries by tile */
-  RENDER_STAGE_RANGES = 7,      /* tile ranges and entry records */
+  RENDER_STAGE_RANGES = 7,      /* tile ranges, entry records, dispatch orders (forward and backward) */
   RENDER_STAGE_COMPOSITE = 8,   /* forward compositing */
   RENDER_STAGE_ZERO_GRADS = 9,  /* gradient buffer clear */
   RENDER_STAGE_COMPOSITE_BWD = 10, /* reverse-order compositing backward */

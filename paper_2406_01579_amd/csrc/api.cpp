@@ -452,7 +452,7 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
   if (params->window == 0 && multiwave(*params))
-    TS_STAGE(RENDER_STAGE_COMPOSITE_BWD, launch_bwd_order(workspace, L, st), "backward tile order");
+    TS_STAGE(RENDER_STAGE_RANGES, launch_bwd_order(workspace, L, st), "backward tile order");
   TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,
            params->window > 0 ? launch_composite_backward_win(workspace, L, with_waves(*params), st)
            : multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)
