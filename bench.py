@@ -72,6 +72,8 @@ def parse():
                          "eager launches through the autograd Function")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-view path")
+    ap.add_argument("--window-bench", type=int, default=5,
+                    help="also time the step with the per-pixel resort window of this size (0: skip)")
     ap.add_argument("--cpu-pixels", type=int, default=400000)
     ap.add_argument("--workload", default="training", choices=["training", "batched", "multiscene"],
                     help="batched: 128^3 band grid, 8 views at 1024^2; multiscene: 32 scenes, 124 mixed views "
@@ -186,6 +188,27 @@ def main():
         del cstep
     value = pixels / (ms_per_step * 1e-3) / 1e6
 
+    # the same step with the per-pixel resort window (Sec. 3.3), graph-captured
+    window = None
+    if args.window_bench > 0 and args.mode == "graph" and (tw, th) == (8, 8):
+        from paper_2406_01579_amd import CapturedStep
+        wparams = Params(tile_w=8, tile_h=8, waves=args.waves, window=args.window_bench)
+        wstep = CapturedStep(verts.detach(), sdf.detach(), colors.detach(), st.tets, cams, args.s, wparams, dout)
+        for _ in range(max(1, args.warmup)):
+            wstep.replay()
+        wstep.check()
+        n_w = max(5, args.steps // 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_w):
+            wstep.replay()
+        torch.cuda.synchronize()
+        wms = 1000.0 * (time.perf_counter() - t0) / n_w
+        wstep.check()
+        window = {"window": args.window_bench, "ms_per_step": round(wms, 4),
+                  "mpx_s": round(pixels / (wms * 1e-3) / 1e6, 2)}
+        del wstep
+
     # workload facts of the last forward (for the roofline)
     plan = renderer.forward([SceneT(verts.detach(), st.tets, sdf.detach(), colors.detach(), args.s)], cams)
     stt = renderer.read_status(plan)
@@ -283,6 +306,7 @@ def main():
         "eager_path": eager,
         "graph": graph,
         "plain_path": plain,
+        "window_path": window,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items()},

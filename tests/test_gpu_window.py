@@ -202,3 +202,29 @@ def test_training_window_gradients_of_sparse_upstream(training):
     ref64 = oracle.backward(g, w.cams, op, upix, dflat, prec=64)
     for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads, ref32, ref64):
         check_gradient(name, got.cpu().numpy(), r32, r64, "training window 5 sparse-upstream")
+
+
+# ---------------------------------------------------------------------------
+# sorting error (Sec. 3.3): images under the per-tile order and under windows
+# of several sizes, against the exact per-pixel order (the oracle's window
+# longer than any pixel's list), on the training-shaped grid at two
+# resolutions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("R", [64, 128])
+def test_window_sort_error_against_exact_per_pixel_order(R):
+    w = synth.training(s=320.0, R=R)
+    g = oracle.Geometry.of(w.scenes[0])
+    _, _, base = gpu_forward(w.scenes[0], w.cams, _params("default", 0))
+    cov = np.argwhere(np.stack(base)[:, 3] > 0.01)
+    pick = cov[np.random.default_rng(7).choice(len(cov), 3000, replace=False)]
+    pix = np.ascontiguousarray(pick[:, [0, 2, 1]], dtype=np.int32)
+    exact = oracle.render(g, w.cams, oracle.params_array(320.0, tile_w=8, tile_h=8, window=4096), pix, prec=32)
+    stats = {}
+    for nw in (0, 1, 3, 5, 8):
+        _, _, imgs = gpu_forward(w.scenes[0], w.cams, _params("default", nw))
+        got = np.stack([imgs[v][:, j, i] for (v, i, j) in pix], 0)
+        err = np.abs(got[:, :3] - exact[:, :3]).max(axis=1)
+        stats[nw] = (float((err > 1e-3).mean()), float(err.mean()), float(err.max()))
+        print(f"R={R} window {nw}: pixels off the exact order's colour by >1e-3: {100 * stats[nw][0]:.2f}%, "
+              f"mean {stats[nw][1]:.2e}, max {stats[nw][2]:.3f}")
+    assert stats[8][0] <= stats[0][0] and stats[5][1] <= stats[0][1]
