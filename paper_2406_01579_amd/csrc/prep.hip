@@ -452,7 +452,6 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   const uint32_t* off = at<const uint32_t>(ws, L.o_off_sorted);
   ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
-  uint32_t* rec_off = at<uint32_t>(ws, L.o_rec_off);
   uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
   uint32_t* val2 = at<uint32_t>(ws, L.o_val2a);
   const uint32_t n = hdr->records_total;
@@ -462,7 +461,6 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
     const uint32_t c = count1[r];
     if (c == 0) continue;
     const uint32_t o = off[q];
-    rec_off[r] = o;
     vrec[r].entry0 = o;
     const ViewRec& R = vrec[r];
     int i0, i1, j0, j1;

@@ -121,12 +121,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
   // ranking: wave w owns items [b*TILE + w*SUB, b*TILE + (w+1)*SUB)
   constexpr int SUB = SORT_ITEMS * 64;
   const uint32_t i0 = b * SORT_TILE + wave * SUB + lane;
-  uint32_t keys[SORT_ITEMS], rank[SORT_ITEMS];
+  uint32_t keys[SORT_ITEMS], vals[SORT_ITEMS], rank[SORT_ITEMS];
+  // keys and values in flight together, before any ranking
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const uint32_t i = i0 + it * 64;
+    keys[it] = i < n ? kin[i] : 0u;
+    vals[it] = i < n ? (vin ? vin[i] : i) : 0u;
+  }
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const uint32_t i = i0 + it * 64;
     const bool valid = i < n;
-    keys[it] = valid ? kin[i] : 0u;
     const uint32_t digit = (keys[it] >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int bit = 0; bit < digit_bits; ++bit) {
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
       const uint32_t digit = (keys[it] >> shift) & mask;
       const uint32_t pos = wrun[wave][digit] + rank[it];
       kout[pos] = keys[it];
-      vout[pos] = vin ? vin[i] : i;
+      vout[pos] = vals[it];
     }
   }
 }
