@@ -9,11 +9,13 @@
 // candidates with alpha >= alpha_min enter the buffer.  Equal depths leave in
 // arrival order.
 //
-// Forward: as in the multi-wave kernels, all waves evaluate the chunk's
-// (entry, pixel) pairs into LDS (alpha and the entry depth); wave 0 runs the
-// window and the blend.  A lane's window keys live in registers with static
-// slot indices; each slot's payload (alpha and the seven blended features)
-// lives in LDS, where a per-lane slot index is cheap.
+// Forward: as in the multi-wave kernels, all waves evaluate the chunk's packed
+// (entry, pixel) pairs -- pixel live and inside the entry's rectangle -- into
+// LDS (alpha and the entry depth) and mark each pixel's candidates; wave 0
+// runs the window over each pixel's candidates and the blend.  A lane's
+// window keys live in registers with static slot indices; each slot's payload
+// (alpha and the seven blended features) lives in LDS, where a per-lane slot
+// index is cheap.
 //
 // Backward: a pixel's blend order is no longer the tile order, so the
 // reverse-order walk of the plain backward does not apply.  Sweep 1 replays
@@ -25,7 +27,8 @@
 // from its last blend back (the reverse mode of Eq. 2) and leaves
 // (dL/dalpha, T alpha) in place.  Sweep 3 goes over the chunks again in tile
 // order and chains every pair to the record's parameters, reduced over the
-// tile into the per-entry gradient, exactly as the plain backward does.
+// tile into the per-entry gradient.  The backward keeps the dense per-entry
+// evaluation (every wave owns interleaved entries for all 64 pixels).
 #include "tile8.h"
 
 namespace ts {
@@ -108,6 +111,18 @@ __device__ __forceinline__ void eval_chunk(const ViewRec* recs, int n, const Til
   }
 }
 
+// Per chunk: the entries' blended features as a conflict-free table
+// (feat[k][e]: c[3], zt, n[3]) and a cleared per-pixel candidate mask.
+template <int CH>
+__device__ __forceinline__ void load_chunk_tables(const ViewRec* recs, int n, float (*feat)[CH], uint32_t* hm,
+                                                  int nthreads) {
+  if (threadIdx.x < 64) hm[threadIdx.x] = 0u;
+  for (int q = threadIdx.x; q < n * 7; q += nthreads) {
+    const int e = q / 7, k = q - e * 7;
+    feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
+  }
+}
+
 }  // namespace
 
 template <int NWV>
@@ -122,6 +137,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   __shared__ ViewRec recs[CHW];
   __shared__ float alds[CHW][64];
   __shared__ float zlds[CHW][64];
+  __shared__ float feat[7][CHW];        // per entry: c[3], zt, n[3]
+  __shared__ uint64_t pmask[CHW];
+  __shared__ uint32_t poff[CHW + 1];
+  __shared__ uint32_t hm[64];           // per pixel: the chunk's candidates (bit e)
   __shared__ float pay[WSLOTS][8][64];  // per slot: alpha, c[3], zt, n[3]
   __shared__ unsigned long long done_mask;
 
@@ -168,32 +187,50 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
     const unsigned long long m = __ballot(done);
     if (lane == 0) done_mask = m;
   }
+  RecPipe<CHW, NT> rp;
+  if (start < end) {
+    rp.fetch_idx(srec, start, (int)min((uint32_t)CHW, end - start));
+    rp.fetch_rec(vrec);
+    if (end - start > (uint32_t)CHW) rp.fetch_idx(srec, start + CHW, (int)min((uint32_t)CHW, end - start - CHW));
+  }
   for (uint32_t base = start; base < end; base += CHW) {
     __syncthreads();
     if (done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHW, end - base);
-    load_recs(recs, vrec, srec, base, n, NT);
+    rp.store(recs, n);
+    if (end - base > (uint32_t)CHW) rp.fetch_rec(vrec);
+    if (end - base > 2u * CHW) rp.fetch_idx(srec, base + 2 * CHW, (int)min((uint32_t)CHW, end - base - 2 * CHW));
     __syncthreads();
-    eval_chunk<NWV>(recs, n, c, qx, qy, s, (done_mask >> lane) & 1ull, alds, zlds);
+    load_chunk_tables(recs, n, feat, hm, NT);
+    if (wave == 0) chunk_pairs<CHW>(recs, n, c, ~done_mask, pmask, poff);
+    __syncthreads();
+    for_each_pair<CHW>(n, pmask, poff, NT, [&](int e, int pix) {
+      const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
+      PixEval h;
+      if (pixel_eval(recs[e], px_, py_, s, h) && h.alpha >= alpha_min) {
+        alds[e][pix] = h.alpha;
+        zlds[e][pix] = h.zin_inv;
+        atomicOr(&hm[pix], 1u << e);
+      }
+    });
     __syncthreads();
     if (wave == 0) {
-      for (int e = 0; e < n; ++e) {
-        const float a = alds[e][lane];
-        if (done || a < 0.0f || a < alpha_min) continue;
-        const int slot = win_insert(win, zlds[e][lane], (int)(base + e));
-        const ViewRec& R = recs[e];
-        pay[slot][0][lane] = a;
-        pay[slot][1][lane] = R.c[0];
-        pay[slot][2][lane] = R.c[1];
-        pay[slot][3][lane] = R.c[2];
-        pay[slot][4][lane] = R.zt;
-        pay[slot][5][lane] = R.n[0];
-        pay[slot][6][lane] = R.n[1];
-        pay[slot][7][lane] = R.n[2];
-        if (win.cnt > nw) {
-          int idx;
-          const int m = win_pop(win, &idx);
-          blend(m, idx);
+      // each pixel's candidates in arrival order
+      uint32_t cand = done ? 0u : hm[lane];
+      while (__ballot(cand != 0u) != 0ull) {
+        if (cand != 0u) {
+          const int e = __ffs(cand) - 1;
+          cand &= cand - 1u;
+          const int slot = win_insert(win, zlds[e][lane], (int)(base + e));
+          pay[slot][0][lane] = alds[e][lane];
+#pragma unroll
+          for (int k = 0; k < 7; ++k) pay[slot][1 + k][lane] = feat[k][e];
+          if (win.cnt > nw) {
+            int idx;
+            const int m = win_pop(win, &idx);
+            blend(m, idx);
+          }
+          if (done) cand = 0u;
         }
       }
       const unsigned long long m = __ballot(done);
