@@ -225,15 +225,16 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       Tb = tlast_in[gi];
     }
   }
-  float gr[8];
+  float Rbehind = 0.0f;
   if (wave == 0) {
+    float gr[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
       grs[q][lane] = gr[q];
     }
+    Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
   }
-  float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
 
   bool first = true;
   float Tnext = 1.0f;
@@ -300,6 +301,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       // each pixel visits only the entries it blended, nearest-last first
       const uint32_t m0 = (uint32_t)hmask[lane];   // CHB = 32 entries
       uint32_t m = m0;
+      float gr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) gr[q] = grs[q][lane];
       while (__ballot(m != 0u) != 0ull) {
         if (m != 0u) {
           const int e = 31 - __clz(m);
@@ -345,25 +349,24 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       const int l16 = (int)(lane & 15u);
       for (uint32_t g0 = (uint32_t)wave * 4u; g0 < ngroups; g0 += 4u * NWV) {
         const uint32_t grp = g0 + (lane >> 4);
+        // branch-free: a lane past the last group or the entry's last pair
+        // chains zero weights
+        const bool gv = grp < ngroups;
+        const int e = entry_of<CHB>(n, poff, gv ? grp : ngroups - 1u);
+        const uint64_t m = pmask[e];
+        const uint32_t k = (grp - poff[e]) * 16u + (uint32_t)l16;
+        const bool valid = gv && k < (uint32_t)__popcll(m);
+        const int pix = valid ? select_bit(m, k) : 0;
+        const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
+        float grp8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) grp8[q] = grs[q][pix];
+        const float dd = valid ? abuf[e][pix] : 0.0f, dfn = valid ? e2buf[e][pix] : 0.0f;
+        const float w = valid ? wbuf[e][pix] : 0.0f;
         float g[32];
-#pragma unroll
-        for (int q = 0; q < 32; ++q) g[q] = 0.0f;
-        int e = 0;
-        if (grp < ngroups) {
-          e = entry_of<CHB>(n, poff, grp);
-          const uint64_t m = pmask[e];
-          const uint32_t k = (grp - poff[e]) * 16u + (uint32_t)l16;
-          if (k < (uint32_t)__popcll(m)) {
-            const int pix = select_bit(m, k);
-            const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
-            float grp8[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) grp8[q] = grs[q][pix];
-            pair_grad_f(recs[e], px_, py_, grp8, abuf[e][pix], e2buf[e][pix], wbuf[e][pix], sel[e][pix], g);
-          }
-        }
+        pair_grad_all(recs[e], px_, py_, grp8, dd, dfn, w, sel[e][pix], g);
         const float2 r = row_transpose_sum32(g);
-        if (grp < ngroups && 2 * l16 < TGRAD_STRIDE - 1) {
+        if (gv && 2 * l16 < TGRAD_STRIDE - 1) {
           atomicAdd(&gacc[e][2 * l16], r.x);
           if (2 * l16 + 1 < TGRAD_STRIDE - 1) atomicAdd(&gacc[e][2 * l16 + 1], r.y);
         }

@@ -148,7 +148,7 @@ __device__ __forceinline__ void unpack_rect(const ViewRec& r, int& i0, int& i1, 
 // compile-time constant, so every index is static; the face's values (S, f)
 // are recomputed from its cross products N.
 // f = sum N_k w_k f_k / S, S = sum N_k w_k.
-template <int F>
+template <int F, bool ZERO_SAFE = false>
 __device__ __forceinline__ void face_geom_grad(const ViewRec& R, const float (&ax)[4], const float (&ay)[4],
                                                float N0, float N1, float N2, float df, float (&g)[32]) {
   constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
@@ -156,7 +156,7 @@ __device__ __forceinline__ void face_geom_grad(const ViewRec& R, const float (&a
   const float N[3] = {N0, N1, N2};
   const float qa = N0 * R.iz[A], qb = N1 * R.iz[B], qc = N2 * R.iz[C];
   const float S = (qa + qb) + qc;
-  const float invS = rcp(S);
+  const float invS = ZERO_SAFE ? (df != 0.0f ? rcp(S) : 0.0f) : rcp(S);
   const float fF = fmaf(qa, R.f[A], fmaf(qb, R.f[B], qc * R.f[C])) * invS;
   float a[3];
 #pragma unroll
@@ -229,6 +229,43 @@ __device__ __forceinline__ void pair_grad_f(const ViewRec& R, float qx, float qy
     if (w2 != 0.0f) face_geom_grad<2>(R, ax, ay, e23, -e03, e02, w2, g);
     if (w3 != 0.0f) face_geom_grad<3>(R, ax, ay, e23, -e13, e12, w3, g);
   }
+}
+
+// pair_grad_f without branches: all four faces are chained, a face whose
+// weight is zero contributes exactly zero (its 1/S is taken as 0), so g is
+// updated in place and a lane with w = dd = dfn = 0 returns zeros.
+__device__ __forceinline__ void pair_grad_all(const ViewRec& R, float qx, float qy, const float (&gr)[8], float dd,
+                                              float dfn, float w, int fs, float (&g)[32]) {
+#pragma unroll
+  for (int q = 0; q < 32; ++q) g[q] = 0.0f;
+  g[G_C + 0] = w * gr[0];
+  g[G_C + 1] = w * gr[1];
+  g[G_C + 2] = w * gr[2];
+  g[G_ZT] = w * gr[4];
+  g[G_N + 0] = w * gr[5];
+  g[G_N + 1] = w * gr[6];
+  g[G_N + 2] = w * gr[7];
+  const int fe = fs & 3, fx = fs >> 2;
+  float ax[4], ay[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ax[k] = R.px[k] - qx;
+    ay[k] = R.py[k] - qy;
+  }
+  const float e01 = ax[0] * ay[1] - ay[0] * ax[1];
+  const float e02 = ax[0] * ay[2] - ay[0] * ax[2];
+  const float e03 = ax[0] * ay[3] - ay[0] * ax[3];
+  const float e12 = ax[1] * ay[2] - ay[1] * ax[2];
+  const float e13 = ax[1] * ay[3] - ay[1] * ax[3];
+  const float e23 = ax[2] * ay[3] - ay[2] * ax[3];
+  const float w0 = (fe == 0 ? dd : 0.0f) + (fx == 0 ? dfn : 0.0f);
+  const float w1 = (fe == 1 ? dd : 0.0f) + (fx == 1 ? dfn : 0.0f);
+  const float w2 = (fe == 2 ? dd : 0.0f) + (fx == 2 ? dfn : 0.0f);
+  const float w3 = (fe == 3 ? dd : 0.0f) + (fx == 3 ? dfn : 0.0f);
+  face_geom_grad<0, true>(R, ax, ay, e12, -e02, e01, w0, g);
+  face_geom_grad<1, true>(R, ax, ay, e13, -e03, e01, w1, g);
+  face_geom_grad<2, true>(R, ax, ay, e23, -e03, e02, w2, g);
+  face_geom_grad<3, true>(R, ax, ay, e23, -e13, e12, w3, g);
 }
 
 // The same from dL/dalpha = da, the raw alpha and e2 = exp(s f_next).
