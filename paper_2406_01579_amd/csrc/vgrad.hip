@@ -23,8 +23,21 @@ __device__ __forceinline__ float group_sum(float x) {
   return x;
 }
 
+// Per-block combine of the vertex gradients: tets that share a vertex
+// (every vertex of a tetrahedral grid belongs to many tets, and neighbouring
+// kept slots are neighbouring tets) add into one LDS slot, keyed by vertex
+// id, and each slot is added to HBM once per block.  Open addressing with a
+// bounded probe; a vertex that finds no slot, or a tet of another scene than
+// the block's first, adds to HBM directly.
+constexpr int VB_HASH = 512;
+constexpr int VB_PROBES = 16;
+static_assert(VB_HASH == 1 << 9, "the slot hash keeps 9 bits");
+
 template <int P>
 __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
+  __shared__ uint32_t hkey[VB_HASH];   // vertex id + 1; 0: empty
+  __shared__ float hval[7][VB_HASH];   // dverts xyz, dsdf, dcolors xyz
+  __shared__ int bscene;
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
@@ -46,6 +59,13 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
        k += stride) {
     const bool tet_ok = k < nk;
     const TetRec& T = trec[tet_ok ? k : 0u];
+    for (int h = threadIdx.x; h < VB_HASH; h += blockDim.x) {
+      hkey[h] = 0u;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) hval[m][h] = 0.0f;
+    }
+    if (threadIdx.x == 0) bscene = tet_ok ? T.scene : -1;   // thread 0 holds the block's first tet
+    __syncthreads();
     float dv[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     float dfv[4] = {0, 0, 0, 0}, dn[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
     bool any = false;
@@ -142,7 +162,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
         dc[m] = group_sum<P>(dc[m]);
       }
     }
-    if (!tet_ok || !any || q0 != 0) continue;
+    if (tet_ok && any && q0 == 0) {
     const DevScene& S = sc[T.scene];
     // normal: n = g/|g|, g = E^-1 df
     if (dn[0] != 0.0f || dn[1] != 0.0f || dn[2] != 0.0f) {
@@ -185,14 +205,47 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
     const int4 vi = reinterpret_cast<const int4*>(S.tets)[T.tet];
     const int idx[4] = {vi.x, vi.y, vi.z, vi.w};
     for (int a = 0; a < 4; ++a) {
-      const size_t vv = (size_t)idx[a];
-      for (int m = 0; m < 3; ++m) {
-        if (dv[a][m] != 0.0f) unsafeAtomicAdd(&S.dverts[3 * vv + m], dv[a][m]);
-        const float dcm = 0.25f * dc[m];
-        if (dcm != 0.0f) unsafeAtomicAdd(&S.dcolors[3 * vv + m], dcm);
+      const uint32_t vv = (uint32_t)idx[a];
+      const float val[7] = {dv[a][0], dv[a][1], dv[a][2], dfv[a], 0.25f * dc[0], 0.25f * dc[1], 0.25f * dc[2]};
+      bool put = false;
+      if (T.scene == bscene) {
+        uint32_t h = (vv * 2654435761u) >> 23;   // 9 bits: VB_HASH slots
+        for (int probe = 0; probe < VB_PROBES; ++probe) {
+          const uint32_t old = atomicCAS(&hkey[h], 0u, vv + 1u);
+          if (old == 0u || old == vv + 1u) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+              if (val[m] != 0.0f) atomicAdd(&hval[m][h], val[m]);
+            put = true;
+            break;
+          }
+          h = (h + 1u) & (VB_HASH - 1u);
+        }
       }
-      if (dfv[a] != 0.0f) unsafeAtomicAdd(&S.dsdf[vv], dfv[a]);
+      if (!put) {
+        for (int m = 0; m < 3; ++m) {
+          if (val[m] != 0.0f) unsafeAtomicAdd(&S.dverts[3 * (size_t)vv + m], val[m]);
+          if (val[4 + m] != 0.0f) unsafeAtomicAdd(&S.dcolors[3 * (size_t)vv + m], val[4 + m]);
+        }
+        if (val[3] != 0.0f) unsafeAtomicAdd(&S.dsdf[vv], val[3]);
+      }
     }
+    }
+    __syncthreads();
+    if (bscene >= 0) {
+      const DevScene& S = sc[bscene];
+      for (int h = threadIdx.x; h < VB_HASH; h += blockDim.x) {
+        const uint32_t key = hkey[h];
+        if (key == 0u) continue;
+        const size_t vv = (size_t)(key - 1u);
+        for (int m = 0; m < 3; ++m) {
+          if (hval[m][h] != 0.0f) unsafeAtomicAdd(&S.dverts[3 * vv + m], hval[m][h]);
+          if (hval[4 + m][h] != 0.0f) unsafeAtomicAdd(&S.dcolors[3 * vv + m], hval[4 + m][h]);
+        }
+        if (hval[3][h] != 0.0f) unsafeAtomicAdd(&S.dsdf[vv], hval[3][h]);
+      }
+    }
+    __syncthreads();
   }
 }
 
