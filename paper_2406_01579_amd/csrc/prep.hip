@@ -4,6 +4,8 @@
 // projection and tile counting (Sec. 3.3), the device-wide scan of tile
 // counts, tile-duplicated key emission, and tile ranges.
 #include <algorithm>
+#include <cstring>
+#include <vector>
 
 #include "ts_device.h"
 
@@ -35,22 +37,28 @@ static hipError_t upload(const void* src, size_t bytes, void* dst, hipStream_t s
   return hipGetLastError();
 }
 
+// The header (forward only), scenes, views and scene-view lists occupy
+// consecutive workspace regions: they go up as one image (alignment gaps
+// zeroed), in as few launches as the argument size allows.
 hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
                              void* ws, const Layout& L, bool reset_header, hipStream_t st) {
-  hipError_t e;
+  static_assert(sizeof(DevHeader) % 4 == 0 && sizeof(DevScene) % 4 == 0 && sizeof(DevView) % 4 == 0,
+                "descriptors are whole words");
+  const size_t first = reset_header ? L.o_hdr : L.o_scene;
+  const size_t end = L.o_scene_views + 4 * (size_t)nv;
+  if (L.o_hdr > L.o_scene || L.o_scene > L.o_view || L.o_view > L.o_scene_views) return hipErrorInvalidValue;
+  std::vector<uint8_t> img(end - first, 0);
   if (reset_header) {
     // fresh counters for a forward pass (its kernels accumulate into them)
     DevHeader h{};
     h.entry_capacity = L.entry_cap;
     h.kept_capacity = L.kept_cap;
-    e = upload(&h, sizeof h, at<void>(ws, L.o_hdr), st);
-    if (e != hipSuccess) return e;
+    std::memcpy(img.data() + (L.o_hdr - first), &h, sizeof h);
   }
-  e = upload(hs, sizeof(DevScene) * ns, at<void>(ws, L.o_scene), st);
-  if (e != hipSuccess) return e;
-  e = upload(scene_views, sizeof(int32_t) * nv, at<void>(ws, L.o_scene_views), st);
-  if (e != hipSuccess) return e;
-  return upload(hv, sizeof(DevView) * nv, at<void>(ws, L.o_view), st);
+  std::memcpy(img.data() + (L.o_scene - first), hs, sizeof(DevScene) * ns);
+  std::memcpy(img.data() + (L.o_view - first), hv, sizeof(DevView) * nv);
+  std::memcpy(img.data() + (L.o_scene_views - first), scene_views, sizeof(int32_t) * nv);
+  return upload(img.data(), img.size(), at<void>(ws, first), st);
 }
 
 // ---------------------------------------------------------------------------
@@ -454,6 +462,14 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
   uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
   uint32_t* val2 = at<uint32_t>(ws, L.o_val2a);
+  // the tile ranges and the tile-length histogram (adjacent) start cleared
+  // for the range and dispatch-order kernels after the tile sort
+  {
+    uint32_t* clr = at<uint32_t>(ws, L.o_ranges);
+    const uint64_t nclr = (L.o_tile_hist - L.o_ranges) / 4 + 2 * (uint64_t)TILE_BUCKETS;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nclr; i += (uint64_t)gridDim.x * blockDim.x)
+      clr[i] = 0u;
+  }
   const uint32_t n = hdr->records_total;
   const uint64_t cap = (uint64_t)L.entry_cap;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
@@ -505,9 +521,7 @@ __global__ __launch_bounds__(256) void k_finalize(void* ws, Layout L) {
 }
 
 hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
-  // ranges and the tile-length histogram are adjacent: clear both
-  k_fill_u32<<<256, 256, 0, st>>>(at<uint32_t>(ws, L.o_ranges),
-                                  (L.o_tile_hist - L.o_ranges) / 4 + 2 * (uint64_t)TILE_BUCKETS, 0u);
+  // ranges and the tile-length histogram were cleared by the emit kernel
   k_finalize<<<2048, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
@@ -539,24 +553,27 @@ __global__ __launch_bounds__(256) void k_tile_hist(void* ws, Layout L) {
   if (threadIdx.x < TILE_BUCKETS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_tile_scan(uint32_t* hist) {
-  uint32_t* off = hist + TILE_BUCKETS;
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = TILE_BUCKETS - 1; b >= 0; --b) {
-      off[b] = run;
-      run += hist[b];
-    }
-  }
+// Every scatter block: first[b] = the number of tiles in buckets above b
+// (longest first), from the complete histogram; the block's tiles of bucket
+// b then take consecutive places from first[b] + an atomic cursor.
+static_assert(TILE_BUCKETS <= 256, "one thread per bucket");
+__device__ __forceinline__ void bucket_first(const uint32_t* hist, uint32_t* first, uint32_t* lds /*[8]*/) {
+  const int t = threadIdx.x;
+  const uint32_t v = t < TILE_BUCKETS ? hist[TILE_BUCKETS - 1 - t] : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_exclusive_scan_256(v, lds, &tot);
+  if (t < TILE_BUCKETS) first[TILE_BUCKETS - 1 - t] = ex;
 }
 
 __global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
-  uint32_t* off = at<uint32_t>(ws, L.o_tile_hist) + TILE_BUCKETS;
+  const uint32_t* hist = at<const uint32_t>(ws, L.o_tile_hist);
+  uint32_t* cursor = at<uint32_t>(ws, L.o_tile_hist) + TILE_BUCKETS;
   TileSlot* order = at<TileSlot>(ws, L.o_tile_order);
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS];
+  __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS], first[TILE_BUCKETS], lds[8];
   if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
+  bucket_first(hist, first, lds);
   __syncthreads();
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   int b = 0;
@@ -566,7 +583,8 @@ __global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
     rank = atomicAdd(&cnt[b], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&off[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x])
+    base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
   __syncthreads();
   if (t < (uint32_t)L.total_tiles) {
     TileSlot sl;
@@ -582,7 +600,6 @@ hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
   k_tile_hist<<<nb, 256, 0, st>>>(ws, L);
-  k_tile_scan<<<1, 64, 0, st>>>(at<uint32_t>(ws, L.o_tile_hist));
   k_tile_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
@@ -604,11 +621,13 @@ __global__ __launch_bounds__(256) void k_bwd_hist(void* ws, Layout L) {
 __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
   const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
-  uint32_t* off = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
+  const uint32_t* hist = at<const uint32_t>(ws, L.o_bwd_hist);
+  uint32_t* cursor = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
   TileSlot* bslots = at<TileSlot>(ws, L.o_bwd_order);
   uint32_t* bpend = at<uint32_t>(ws, L.o_bwd_pend);
-  __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS];
+  __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS], first[TILE_BUCKETS], lds[8];
   if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
+  bucket_first(hist, first, lds);
   __syncthreads();
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   int b = 0;
@@ -622,7 +641,8 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
     rank = atomicAdd(&cnt[b], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&off[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x])
+    base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
   __syncthreads();
   if (t < (uint32_t)L.total_tiles) {
     bslots[base[b] + rank] = sl;
@@ -633,9 +653,8 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
 hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
-  k_fill_u32<<<1, 256, 0, st>>>(at<uint32_t>(ws, L.o_bwd_hist), 2 * (uint64_t)TILE_BUCKETS, 0u);
+  // the histogram and its cursors were cleared with the gradients
   k_bwd_hist<<<nb, 256, 0, st>>>(ws, L);
-  k_tile_scan<<<1, 64, 0, st>>>(at<uint32_t>(ws, L.o_bwd_hist));
   k_bwd_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
@@ -659,28 +678,30 @@ hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // gradient buffers are overwritten: clear them first
 // ---------------------------------------------------------------------------
+// One launch: the scenes' gradients (row y: scene y); row 0 also clears the
+// entry flags of the last forward's entries (the backward sets the ones it
+// reaches) and the backward dispatch-order histogram with its cursors.
 __global__ void k_zero_grads(void* ws, Layout L) {
   const DevScene& S = at<const DevScene>(ws, L.o_scene)[blockIdx.y];
   const size_t n3 = 3 * (size_t)S.V;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n3; i += (size_t)gridDim.x * blockDim.x) {
+  const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = i0; i < n3; i += stride) {
     S.dverts[i] = 0.0f;
     S.dcolors[i] = 0.0f;
     if (i < (size_t)S.V) S.dsdf[i] = 0.0f;
   }
-}
-
-// entry flags of the last forward's entries (the backward sets the ones it reaches)
-__global__ void k_zero_eflags(void* ws, Layout L) {
+  if (blockIdx.y != 0) return;
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   uint32_t* f = at<uint32_t>(ws, L.o_eflag);
   const uint32_t words = (hdr->entries_total + 3u) / 4u;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) f[i] = 0u;
+  for (size_t i = i0; i < words; i += stride) f[i] = 0u;
+  uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
+  for (size_t i = i0; i < 2 * (size_t)TILE_BUCKETS; i += stride) bh[i] = 0u;
 }
 
 hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene*, hipStream_t st) {
   dim3 grid(256, (unsigned)L.ns);
   k_zero_grads<<<grid, 256, 0, st>>>(ws, L);
-  k_zero_eflags<<<512, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 
