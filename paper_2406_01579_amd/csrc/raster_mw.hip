@@ -337,24 +337,25 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         const uint64_t b = __ballot((m0 >> e) & 1u);
         cmask_e = ((int)lane == e) ? b : cmask_e;
       }
-      pair_offsets<CHB, 16>(n, cmask_e, pmask, poff);
+      pair_offsets<CHB, 8>(n, cmask_e, pmask, poff);
     }
     __syncthreads();
     // phase C: the gradient of every contributing (entry, pixel) pair.  Each
-    // entry's pairs fill 16-lane groups (four per wave); a group is summed
-    // with row DPP and added to the entry's sum (LDS float add: an entry with
-    // more than 16 contributing pixels spans several groups).
+    // entry's pairs fill 8-lane groups (eight per wave); a group is summed
+    // with DPP inside its half-row and added to the entry's sum (LDS float
+    // add: an entry with more than 8 contributing pixels spans several
+    // groups).
     {
       const uint32_t ngroups = poff[n];
-      const int l16 = (int)(lane & 15u);
-      for (uint32_t g0 = (uint32_t)wave * 4u; g0 < ngroups; g0 += 4u * NWV) {
-        const uint32_t grp = g0 + (lane >> 4);
+      const int l8 = (int)(lane & 7u);
+      for (uint32_t g0 = (uint32_t)wave * 8u; g0 < ngroups; g0 += 8u * NWV) {
+        const uint32_t grp = g0 + (lane >> 3);
         // branch-free: a lane past the last group or the entry's last pair
         // chains zero weights
         const bool gv = grp < ngroups;
         const int e = entry_of<CHB>(n, poff, gv ? grp : ngroups - 1u);
         const uint64_t m = pmask[e];
-        const uint32_t k = (grp - poff[e]) * 16u + (uint32_t)l16;
+        const uint32_t k = (grp - poff[e]) * 8u + (uint32_t)l8;
         const bool valid = gv && k < (uint32_t)__popcll(m);
         const int pix = valid ? select_bit(m, k) : 0;
         const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
@@ -365,10 +366,13 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         const float w = valid ? wbuf[e][pix] : 0.0f;
         float g[32];
         pair_grad_all(recs[e], px_, py_, grp8, dd, dfn, w, sel[e][pix], g);
-        const float2 r = row_transpose_sum32(g);
-        if (gv && 2 * l16 < TGRAD_STRIDE - 1) {
-          atomicAdd(&gacc[e][2 * l16], r.x);
-          if (2 * l16 + 1 < TGRAD_STRIDE - 1) atomicAdd(&gacc[e][2 * l16 + 1], r.y);
+        const float4 r = row8_transpose_sum32(g);
+        if (gv && 4 * l8 < TGRAD_STRIDE - 1) {
+          static_assert(TGRAD_STRIDE - 1 == 23, "23 gradient slots: lane 5 holds the last three");
+          atomicAdd(&gacc[e][4 * l8], r.x);
+          atomicAdd(&gacc[e][4 * l8 + 1], r.y);
+          atomicAdd(&gacc[e][4 * l8 + 2], r.z);
+          if (4 * l8 + 3 < TGRAD_STRIDE - 1) atomicAdd(&gacc[e][4 * l8 + 3], r.w);
         }
       }
     }

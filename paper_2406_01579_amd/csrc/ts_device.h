@@ -362,4 +362,36 @@ __device__ __forceinline__ float2 row_transpose_sum32(const float (&v)[32]) {
   return make_float2(u[0], u[1]);
 }
 
+// Per 8-lane group (half of a DPP row): afterwards lane L of a group holds,
+// in .x .. .w, the sums over the group's 8 lanes of v[4 (L & 7)] ..
+// v[4 (L & 7) + 3].  Each step halves the values per lane while pairing
+// lanes mirrored in the half-row, 2 apart and 1 apart.  Every lane must be
+// active.
+__device__ __forceinline__ float4 row8_transpose_sum32(const float (&v)[32]) {
+  const unsigned lane = __lane_id();
+  const bool b2 = lane & 4u, b1 = lane & 2u, b0 = lane & 1u;
+  float x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float send = b2 ? v[k] : v[k + 16];
+    const float keep = b2 ? v[k + 16] : v[k];
+    x[k] = keep + dpp<0x141>(send);   // row_half_mirror (j <-> 7 - j in each half-row)
+  }
+  float y[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float send = b1 ? x[k] : x[k + 8];
+    const float keep = b1 ? x[k + 8] : x[k];
+    y[k] = keep + dpp<0x4E>(send);    // quad_perm [2,3,0,1] (j <-> j ^ 2)
+  }
+  float z[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float send = b0 ? y[k] : y[k + 4];
+    const float keep = b0 ? y[k + 4] : y[k];
+    z[k] = keep + dpp<0xB1>(send);    // quad_perm [1,0,3,2] (j <-> j ^ 1)
+  }
+  return make_float4(z[0], z[1], z[2], z[3]);
+}
+
 }  // namespace ts
