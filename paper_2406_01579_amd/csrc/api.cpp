@@ -447,9 +447,9 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
     hs[s].dcolors = grads[s].dcolors;
   }
   for (int v = 0; v < n_views; ++v) hv[v].dout = dL_dout[v];
-  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, false, st),
-           "upload descriptors");
-  TS_STAGE(RENDER_STAGE_ZERO_GRADS, launch_zero_grads(workspace, L, hs.data(), st), "zero gradients");
+  TS_STAGE(RENDER_STAGE_ZERO_GRADS,
+           launch_desc_zero_grads(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, st),
+           "upload descriptors and zero gradients");
   if (params->window == 0 && multiwave(*params))
     TS_STAGE(RENDER_STAGE_RANGES, launch_bwd_order(workspace, L, st), "backward tile order");
   TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,

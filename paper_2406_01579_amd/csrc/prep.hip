@@ -16,7 +16,7 @@ namespace ts {
 // the whole call sequence can be captured in a graph)
 // ---------------------------------------------------------------------------
 constexpr int BLOB_WORDS = 960;
-struct Blob {
+struct alignas(16) Blob {
   uint32_t w[BLOB_WORDS];
 };
 
@@ -39,15 +39,15 @@ static hipError_t upload(const void* src, size_t bytes, void* dst, hipStream_t s
 
 // The header (forward only), scenes, views and scene-view lists occupy
 // consecutive workspace regions: they go up as one image (alignment gaps
-// zeroed), in as few launches as the argument size allows.
-hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
-                             void* ws, const Layout& L, bool reset_header, hipStream_t st) {
+// zeroed).
+static hipError_t desc_image(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                             const Layout& L, bool reset_header, std::vector<uint8_t>& img, size_t& first) {
   static_assert(sizeof(DevHeader) % 4 == 0 && sizeof(DevScene) % 4 == 0 && sizeof(DevView) % 4 == 0,
                 "descriptors are whole words");
-  const size_t first = reset_header ? L.o_hdr : L.o_scene;
+  first = reset_header ? L.o_hdr : L.o_scene;
   const size_t end = L.o_scene_views + 4 * (size_t)nv;
   if (L.o_hdr > L.o_scene || L.o_scene > L.o_view || L.o_view > L.o_scene_views) return hipErrorInvalidValue;
-  std::vector<uint8_t> img(end - first, 0);
+  img.assign(end - first, 0);
   if (reset_header) {
     // fresh counters for a forward pass (its kernels accumulate into them)
     DevHeader h{};
@@ -58,6 +58,16 @@ hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int 
   std::memcpy(img.data() + (L.o_scene - first), hs, sizeof(DevScene) * ns);
   std::memcpy(img.data() + (L.o_view - first), hv, sizeof(DevView) * nv);
   std::memcpy(img.data() + (L.o_scene_views - first), scene_views, sizeof(int32_t) * nv);
+  return hipSuccess;
+}
+
+// in as few launches as the argument size allows
+hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                             void* ws, const Layout& L, bool reset_header, hipStream_t st) {
+  std::vector<uint8_t> img;
+  size_t first;
+  const hipError_t e = desc_image(hs, ns, hv, nv, scene_views, L, reset_header, img, first);
+  if (e != hipSuccess) return e;
   return upload(img.data(), img.size(), at<void>(ws, first), st);
 }
 
@@ -469,6 +479,10 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
     const uint64_t nclr = (L.o_tile_hist - L.o_ranges) / 4 + 2 * (uint64_t)TILE_BUCKETS;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nclr; i += (uint64_t)gridDim.x * blockDim.x)
       clr[i] = 0u;
+    // and the backward-order histogram the forward compositing kernel fills
+    uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (uint32_t)TILE_BUCKETS; i += gridDim.x * blockDim.x)
+      bh[i] = 0u;
   }
   const uint32_t n = hdr->records_total;
   const uint64_t cap = (uint64_t)L.entry_cap;
@@ -534,12 +548,6 @@ hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
 // walked before every pixel of the tile stopped.  The order inside a bucket is
 // whatever the atomics give; results do not depend on it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int len_bucket(uint32_t len) {
-  if (len == 0) return 0;
-  const int b = 31 - __clz(len);  // floor(log2 len)
-  const int sub = b >= 2 ? (int)((len >> (b - 2)) & 3u) : (b == 1 ? (int)((len & 1u) << 1) : 0);
-  return 1 + 4 * b + sub;
-}
 
 __global__ __launch_bounds__(256) void k_tile_hist(void* ws, Layout L) {
   const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
@@ -605,19 +613,9 @@ hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
 }
 
 // backward order: forward slots re-bucketed by the walked length pend - start
-__global__ __launch_bounds__(256) void k_bwd_hist(void* ws, Layout L) {
-  const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
-  const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
-  uint32_t* hist = at<uint32_t>(ws, L.o_bwd_hist);
-  __shared__ uint32_t h[TILE_BUCKETS];
-  if (threadIdx.x < TILE_BUCKETS) h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  if (t < (uint32_t)L.total_tiles) atomicAdd(&h[len_bucket(pend[t] - slots[t].start)], 1u);
-  __syncthreads();
-  if (threadIdx.x < TILE_BUCKETS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
-}
-
+// (the forward compositing kernel counted every slot with pend > start; the
+// tiles with nothing walked form bucket 0, placed last, whose own count the
+// offsets never need)
 __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
   const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
@@ -653,8 +651,8 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
 hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
-  // the histogram and its cursors were cleared with the gradients
-  k_bwd_hist<<<nb, 256, 0, st>>>(ws, L);
+  // histogram: counted by the forward compositing kernel; cursors: cleared
+  // with the gradients
   k_bwd_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
@@ -678,11 +676,10 @@ hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // gradient buffers are overwritten: clear them first
 // ---------------------------------------------------------------------------
-// One launch: the scenes' gradients (row y: scene y); row 0 also clears the
-// entry flags of the last forward's entries (the backward sets the ones it
-// reaches) and the backward dispatch-order histogram with its cursors.
-__global__ void k_zero_grads(void* ws, Layout L) {
-  const DevScene& S = at<const DevScene>(ws, L.o_scene)[blockIdx.y];
+// The scenes' gradients (row y: scene y); row 0 also clears the entry flags
+// of the last forward's entries (the backward sets the ones it reaches) and
+// the cursors of the backward dispatch order.
+__device__ __forceinline__ void zero_grads_body(const DevScene& S, void* ws, const Layout& L) {
   const size_t n3 = 3 * (size_t)S.V;
   const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = i0; i < n3; i += stride) {
@@ -695,13 +692,46 @@ __global__ void k_zero_grads(void* ws, Layout L) {
   uint32_t* f = at<uint32_t>(ws, L.o_eflag);
   const uint32_t words = (hdr->entries_total + 3u) / 4u;
   for (size_t i = i0; i < words; i += stride) f[i] = 0u;
-  uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
-  for (size_t i = i0; i < 2 * (size_t)TILE_BUCKETS; i += stride) bh[i] = 0u;
+  uint32_t* bcur = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
+  for (size_t i = i0; i < (size_t)TILE_BUCKETS; i += stride) bcur[i] = 0u;
 }
 
-hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene*, hipStream_t st) {
+__global__ void k_zero_grads(void* ws, Layout L) {
+  zero_grads_body(at<const DevScene>(ws, L.o_scene)[blockIdx.y], ws, L);
+}
+
+// The same, taking the backward's descriptor image (scenes first) as the
+// kernel argument: row 0 also writes it to the workspace for the kernels
+// after this one, and every block reads its scene from the argument.
+__global__ void k_zero_grads_desc(Blob b, int nwords, void* ws, Layout L) {
+  if (blockIdx.y == 0) {
+    uint32_t* dst = at<uint32_t>(ws, L.o_scene);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) dst[i] = b.w[i];
+  }
+  zero_grads_body(reinterpret_cast<const DevScene*>(b.w)[blockIdx.y], ws, L);
+}
+
+// Descriptor upload and gradient clearing of a backward pass: one launch when
+// the descriptors fit in one kernel argument, else the upload launches and
+// then the clearing kernel.
+hipError_t launch_desc_zero_grads(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                                  void* ws, const Layout& L, hipStream_t st) {
+  std::vector<uint8_t> img;
+  size_t first;
+  hipError_t e = desc_image(hs, ns, hv, nv, scene_views, L, false, img, first);
+  if (e != hipSuccess) return e;
   dim3 grid(256, (unsigned)L.ns);
-  k_zero_grads<<<grid, 256, 0, st>>>(ws, L);
+  const size_t words = img.size() / 4;
+  if (words <= (size_t)BLOB_WORDS) {
+    static_assert(alignof(DevScene) <= 16, "scenes start the image, which starts the argument");
+    Blob b;
+    std::memcpy(b.w, img.data(), img.size());
+    k_zero_grads_desc<<<grid, 256, 0, st>>>(b, (int)words, ws, L);
+  } else {
+    e = upload(img.data(), img.size(), at<void>(ws, first), st);
+    if (e != hipSuccess) return e;
+    k_zero_grads<<<grid, 256, 0, st>>>(ws, L);
+  }
   return hipGetLastError();
 }
 

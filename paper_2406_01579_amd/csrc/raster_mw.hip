@@ -139,7 +139,13 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
     int wmax = last;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
-    if ((threadIdx.x & 63) == 0) at<uint32_t>(ws, L.o_tile_pend)[blockIdx.x] = wmax >= (int)start ? (uint32_t)wmax + 1u : start;
+    if ((threadIdx.x & 63) == 0) {
+      const uint32_t pend = wmax >= (int)start ? (uint32_t)wmax + 1u : start;
+      at<uint32_t>(ws, L.o_tile_pend)[blockIdx.x] = pend;
+      // the backward dispatch order's histogram of walked lengths (bucket 0,
+      // nothing walked, is not counted)
+      if (pend > start) atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + len_bucket(pend - start), 1u);
+    }
   }
   if ((threadIdx.x >> 6) == 0 && c.inside) {
     const size_t plane = (size_t)V.W * V.H;

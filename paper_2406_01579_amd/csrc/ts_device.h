@@ -140,6 +140,15 @@ __device__ __forceinline__ void unpack_rect(const ViewRec& r, int& i0, int& i1, 
   j1 = (int)(r.ry >> 16);
 }
 
+// Dispatch-order bucket of a list length: 0 for an empty list, then four
+// buckets per power of two.
+__device__ __forceinline__ int len_bucket(uint32_t len) {
+  if (len == 0) return 0;
+  const int b = 31 - __clz(len);  // floor(log2 len)
+  const int sub = b >= 2 ? (int)((len >> (b - 2)) & 3u) : (b == 1 ? (int)((len & 1u) << 1) : 0);
+  return 1 + 4 * b + sub;
+}
+
 // ---------------------------------------------------------------------------
 // Reverse mode of one (pixel, record) pair: the pixel's blend weight w and
 // dL/dalpha are chained to the record's 23 screen-space parameters.

@@ -166,7 +166,8 @@ hipError_t launch_composite_backward_mw(void* ws, const Layout& L, const render_
 hipError_t launch_composite_win(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_backward_win(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
-hipError_t launch_zero_grads(void* ws, const Layout& L, const DevScene* hs, hipStream_t st);
+hipError_t launch_desc_zero_grads(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                                  void* ws, const Layout& L, hipStream_t st);
 
 // radix sort of (uint32 key, uint32 value) pairs, stable, LSD over key bits
 // [0, bits).  n is read on the device from *n_dev (clamped to cap).  The
