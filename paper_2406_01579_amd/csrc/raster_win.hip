@@ -265,8 +265,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   }
 }
 
+// (a 5-waves-per-SIMD target fits it in 96 VGPRs without spills: one more
+// resident workgroup per CU)
 template <int NWV>
-__global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout L, float alpha_min,
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_composite_bwd_win(void* ws, Layout L, float alpha_min,
                                                                 float alpha_clamp, float t_min, int nw) {
   constexpr int NT = 64 * NWV;
   const DevView* vw = at<const DevView>(ws, L.o_view);
@@ -394,21 +396,16 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
         if (lane < (unsigned)TGRAD_STRIDE) gacc[e][lane] = 0.0f;
         continue;
       }
+      // branch-free: a lane that did not blend this entry chains zero
+      // weights (zero gradient)
       float g[32];
-#pragma unroll
-      for (int q = 0; q < 32; ++q) g[q] = 0.0f;
-      if (contrib) {
+      {
         const ViewRec& R = recs[e];
-        float alpha = 0.0f, e2 = 0.0f;
-        int fs = 0;
-        if (da != 0.0f) {
-          PixEval h;
-          pixel_eval(R, qx, qy, s, h);
-          alpha = h.alpha;
-          e2 = h.e2;
-          fs = h.fe | (h.fx << 2);
-        }
-        pair_grad(R, qx, qy, s, gr, da, w, alpha, e2, fs, g);
+        PixEval h;
+        pixel_eval(R, qx, qy, s, h);
+        float dd, dfn;
+        eq1_chain(da, h.alpha, h.e2, s, dd, dfn);
+        pair_grad_all(R, qx, qy, gr, dd, dfn, w, h.fe | (h.fx << 2), g);
       }
       const float tot = wave_transpose_sum32(g);
       const unsigned q = lane >> 1;
