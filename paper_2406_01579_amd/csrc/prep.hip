@@ -290,6 +290,7 @@ __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2
   ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
   uint32_t* count1 = at<uint32_t>(ws, L.o_count1);
   uint32_t* key1 = at<uint32_t>(ws, L.o_key1a);
+  uint4* rbox = at<uint4>(ws, L.o_rbox);
   const int v = blockIdx.y;
   const DevView V = vw[v];
   const int n = kcount[V.scene];
@@ -349,6 +350,8 @@ __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2
         R.view = v;
         R.entry0 = 0;
         vrec[r] = R;
+        // the fields the emit and vertex-backward kernels need, compact
+        rbox[r] = make_uint4(R.rx, R.ry, (uint32_t)v, 0u);
       }
     }
     count1[r] = cnt;
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   const uint32_t* srec = sorted_records(ws, L);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   const uint32_t* off = at<const uint32_t>(ws, L.o_off_sorted);
-  ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
+  uint4* rbox = at<uint4>(ws, L.o_rbox);
   uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
   uint32_t* val2 = at<uint32_t>(ws, L.o_val2a);
   // the tile ranges and the tile-length histogram (adjacent) start cleared
@@ -491,11 +494,12 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
     const uint32_t c = count1[r];
     if (c == 0) continue;
     const uint32_t o = off[q];
-    vrec[r].entry0 = o;
-    const ViewRec& R = vrec[r];
-    int i0, i1, j0, j1;
-    unpack_rect(R, i0, i1, j0, j1);
-    const DevView& V = vw[R.view];
+    // the record's first entry goes to its compact box (read there by the
+    // backward kernels), and so does the rectangle come from it
+    const uint4 bx = rbox[r];
+    rbox[r].w = o;
+    const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu), j1 = (int)(bx.y >> 16);
+    const DevView& V = vw[bx.z];
     const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
     const int nx = tx1 - tx0 + 1;
     for (uint32_t j = 0; j < c; ++j) {

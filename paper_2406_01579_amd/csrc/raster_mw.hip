@@ -246,10 +246,11 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   float Tnext = 1.0f;
   // chunks from the one holding pend - 1 down to start; only the first is partial
   const int64_t cb0 = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CHB) * CHB;
-  RecPipe<CHB, NT> rp;
+  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
+  RecPipe<CHB, NT, true> rp;
   if (pend > start) {
     rp.fetch_idx(srec, (uint32_t)cb0, (int)(pend - (uint32_t)cb0));
-    rp.fetch_rec(vrec);
+    rp.fetch_rec(vrec, rbox);
     if (cb0 - CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb0 - CHB), CHB);
   }
   for (int64_t cb = cb0; cb >= (int64_t)start && pend > start; cb -= CHB) {
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     const int n = (int)min((uint32_t)CHB, pend - base);
     __syncthreads();
     rp.store(recs, n);
-    if (cb - CHB >= (int64_t)start) rp.fetch_rec(vrec);
+    if (cb - CHB >= (int64_t)start) rp.fetch_rec(vrec, rbox);
     if (cb - 2 * CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb - 2 * CHB), CHB);
     __syncthreads();
     // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))
   for (uint32_t base = start; base < pend; base += CHW) {
     const int n = (int)min((uint32_t)CHW, pend - base);
     __syncthreads();
-    load_recs(recs, vrec, srec, base, n, NT);
+    load_recs(recs, vrec, srec, base, n, NT, at<const uint4>(ws, L.o_rbox));
     __syncthreads();
     for (int e = wave; e < n; e += NWV) {
       const float2 dw = *reinterpret_cast<const float2*>(&pairs[(size_t)(base + e) * 64 + lane]);

@@ -9,12 +9,17 @@
 namespace ts {
 namespace {
 
+// (with rbox, the copy's first-entry field comes from the record's compact
+// box, where the emit kernel writes it)
 __device__ __forceinline__ void load_recs(ViewRec* recs, const ViewRec* __restrict__ vrec,
-                                          const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads) {
+                                          const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads,
+                                          const uint4* __restrict__ rbox = nullptr) {
   for (int q = threadIdx.x; q < n * 8; q += nthreads) {
     const int e = q >> 3, part = q & 7;
     const uint32_t r = srec[base + e];
-    reinterpret_cast<float4*>(&recs[e])[part] = reinterpret_cast<const float4*>(&vrec[r])[part];
+    float4 t = reinterpret_cast<const float4*>(&vrec[r])[part];
+    if (rbox && part == 7) t.w = __uint_as_float(rbox[r].w);   // entry0 is the last word of the record
+    reinterpret_cast<float4*>(&recs[e])[part] = t;
   }
 }
 
@@ -163,8 +168,9 @@ __device__ __forceinline__ void for_each_pair(int n, const uint64_t* pmask, cons
 // chunk's records are in flight into registers and the record indices of the
 // one after it are in flight too, so a chunk's two dependent global loads
 // overlap the previous chunk's work.  Each thread owns PQ of the chunk's
-// 16-byte record parts.
-template <int CH, int NT>
+// 16-byte record parts.  With E0, the copy's first-entry field comes from
+// the record's compact box (loaded beside the last part).
+template <int CH, int NT, bool E0 = false>
 struct RecPipe {
   static constexpr int PQ = (CH * 8 + NT - 1) / NT;
   uint32_t idx[PQ];
@@ -177,7 +183,8 @@ struct RecPipe {
     }
   }
   // unconditional: a part past the chunk reads record 0 (allocated) and is never stored
-  __device__ __forceinline__ void fetch_rec(const ViewRec* __restrict__ vrec) {
+  __device__ __forceinline__ void fetch_rec(const ViewRec* __restrict__ vrec,
+                                            const uint4* __restrict__ rbox = nullptr) {
 #pragma unroll
     for (int j = 0; j < PQ; ++j) {
       const int q = (int)threadIdx.x + j * NT;
@@ -186,6 +193,7 @@ struct RecPipe {
       vy[j] = t.y;
       vz[j] = t.z;
       vw[j] = t.w;
+      if (E0 && (q & 7) == 7) vw[j] = __uint_as_float(rbox[idx[j]].w);   // entry0: the record's last word
     }
   }
   __device__ __forceinline__ void store(ViewRec* recs, int n) const {

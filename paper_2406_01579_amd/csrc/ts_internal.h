@@ -93,7 +93,7 @@ struct ViewRec {
   uint32_t ry;      // j0 | j1 << 16
   int32_t kept;     // global kept slot
   int32_t view;
-  uint32_t entry0;  // first tile-duplicated entry of this record (set by the emit step)
+  uint32_t entry0;  // first tile-duplicated entry: filled into LDS copies from the compact box
 };
 static_assert(sizeof(ViewRec) == 128, "view record is 128 bytes");
 
@@ -120,6 +120,7 @@ struct Layout {
   size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_off_sorted, o_scan_part;
+  size_t o_rbox;   // per record: pixel rectangle (rx, ry), view, first entry (16 B)
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
   size_t o_ranges, o_tile_hist, o_tile_order, o_tgrad, o_last, o_tlast;

@@ -8,9 +8,11 @@
 // chains the view-independent parts -- the SDF values, the tet normal
 // n = g/|g| (App. A.3, as the equivalent 3x3 edge system g = E^-1 (f_k - f_0))
 // and the mean colour -- and adds the result to the per-vertex gradients
-// (float atomics, one set per tet).  A record's loads form short dependent
-// rounds (the record, then its entry flags, then the flagged entries), and
-// the views of a tet are in flight together.
+// (combined per block in LDS, then float atomics).  A record's loads form
+// short dependent rounds (its compact box with the first entry, then its
+// entry flags, then the flagged entries; 1/Z is recomputed from the tet's
+// vertices with the projection's operations), and the views of a tet are in
+// flight together.
 #include "ts_device.h"
 
 namespace ts {
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
   const int32_t* scene_views = at<const int32_t>(ws, L.o_scene_views);
   const int32_t* kbase = at<const int32_t>(ws, L.o_scene_kept_base);
   const int32_t* rbase = at<const int32_t>(ws, L.o_view_rec_base);
-  const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
+  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
   const TetRec* trec = at<const TetRec>(ws, L.o_trec);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   const uint8_t* eflag = at<const uint8_t>(ws, L.o_eflag);
@@ -78,8 +80,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
         if (r >= nrec) continue;
         const uint32_t cnt = count1[r];
         if (cnt == 0) continue;
-        const ViewRec& R = vrec[r];
-        const uint32_t o = R.entry0;
+        const uint32_t o = rbox[r].w;   // the record's first entry
         const uint32_t n = (uint32_t)min((uint64_t)cnt, cap > o ? cap - o : 0ull);
         if (n == 0u) continue;  // entries past the capacity (an overflowed forward)
         // reached flags, bit j for entry o + j: the first eight from two
@@ -129,7 +130,8 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
           const float x = T.x[a][0], y = T.x[a][1], z = T.x[a][2];
           const float X = fmaf(V.R[0], x, fmaf(V.R[1], y, fmaf(V.R[2], z, V.t[0])));
           const float Y = fmaf(V.R[3], x, fmaf(V.R[4], y, fmaf(V.R[5], z, V.t[1])));
-          const float iz = R.iz[a];
+          // 1 / Z as the projection computed it (same operations)
+          const float iz = 1.0f / fmaf(V.R[6], x, fmaf(V.R[7], y, fmaf(V.R[8], z, V.t[2])));
           // x' = fx X/Z + cx, y' = fy Y/Z + cy; w = 1/Z; z_t = mean Z
           const float dpx = g[G_PX + a] * V.fx, dpy = g[G_PY + a] * V.fy;
           const float dX = dpx * iz, dY = dpy * iz;
