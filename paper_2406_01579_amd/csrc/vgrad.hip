@@ -17,6 +17,20 @@
 
 namespace ts {
 
+// Scene of a kept slot: scenes own consecutive slot ranges starting at
+// kbase[s] (non-decreasing; an empty scene shares its base with the next),
+// so the slot's scene is the last one whose base is at or below it.  Found
+// from the slot alone, so the record loads need not wait for the tet's own.
+__device__ __forceinline__ int scene_of_kept(const int32_t* kbase, int ns, uint32_t k) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint32_t)kbase[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // sum over aligned groups of P lanes (P a power of two <= 64)
 template <int P>
 __device__ __forceinline__ float group_sum(float x) {
@@ -35,8 +49,9 @@ constexpr int VB_HASH = 512;
 constexpr int VB_PROBES = 16;
 static_assert(VB_HASH == 1 << 9, "the slot hash keeps 9 bits");
 
+// (a 5-waves-per-SIMD target fits it in 96 VGPRs without spills)
 template <int P>
-__global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_vertex_bwd(void* ws, Layout L) {
   __shared__ uint32_t hkey[VB_HASH];   // vertex id + 1; 0: empty
   __shared__ float hval[7][VB_HASH];   // dverts xyz, dsdf, dcolors xyz
   __shared__ int bscene;
@@ -61,19 +76,20 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
        k += stride) {
     const bool tet_ok = k < nk;
     const TetRec& T = trec[tet_ok ? k : 0u];
+    const int ks = tet_ok ? scene_of_kept(kbase, L.ns, k) : 0;
     for (int h = threadIdx.x; h < VB_HASH; h += blockDim.x) {
       hkey[h] = 0u;
 #pragma unroll
       for (int m = 0; m < 7; ++m) hval[m][h] = 0.0f;
     }
-    if (threadIdx.x == 0) bscene = tet_ok ? T.scene : -1;   // thread 0 holds the block's first tet
+    if (threadIdx.x == 0) bscene = tet_ok ? ks : -1;   // thread 0 holds the block's first tet
     __syncthreads();
     float dv[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     float dfv[4] = {0, 0, 0, 0}, dn[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
     bool any = false;
     if (tet_ok) {
-      const DevScene& S = sc[T.scene];
-      const uint32_t kl = k - (uint32_t)kbase[T.scene];
+      const DevScene& S = sc[ks];
+      const uint32_t kl = k - (uint32_t)kbase[ks];
       for (int q = q0; q < S.view_count; q += P) {
         const int v = scene_views[S.view_first + q];
         const uint32_t r = (uint32_t)rbase[v] + kl;
@@ -165,7 +181,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
       }
     }
     if (tet_ok && any && q0 == 0) {
-    const DevScene& S = sc[T.scene];
+    const DevScene& S = sc[ks];
     // normal: n = g/|g|, g = E^-1 df
     if (dn[0] != 0.0f || dn[1] != 0.0f || dn[2] != 0.0f) {
       float e[3][3], df[3];
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(256) void k_vertex_bwd(void* ws, Layout L) {
       const uint32_t vv = (uint32_t)idx[a];
       const float val[7] = {dv[a][0], dv[a][1], dv[a][2], dfv[a], 0.25f * dc[0], 0.25f * dc[1], 0.25f * dc[2]};
       bool put = false;
-      if (T.scene == bscene) {
+      if (ks == bscene) {
         uint32_t h = (vv * 2654435761u) >> 23;   // 9 bits: VB_HASH slots
         for (int probe = 0; probe < VB_PROBES; ++probe) {
           const uint32_t old = atomicCAS(&hkey[h], 0u, vv + 1u);
