@@ -631,6 +631,8 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
   bucket_first(hist, first, lds);
   __syncthreads();
+  // the slots before bucket 0 are the tiles with something walked
+  if (blockIdx.x == 0 && threadIdx.x == 0) at<DevHeader>(ws, L.o_hdr)->bwd_work = first[0];
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   int b = 0;
   uint32_t rank = 0;

@@ -106,6 +106,41 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
   __syncthreads();
 }
 
+// Background of the tiles with an empty list (the last `count` dispatch
+// slots from `first`), `per` tiles per workgroup: the outputs of a pixel no
+// record reaches (T = 1), no blended entry, and the tile's end of blended
+// prefix at its start.
+constexpr uint32_t EMPTY_PER_WG = 16;
+template <int NT>
+__device__ __forceinline__ void background_tiles(void* ws, const Layout& L, const DevView* vw, uint32_t first,
+                                                 uint32_t count) {
+  const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
+  uint32_t* tpend = at<uint32_t>(ws, L.o_tile_pend);
+  int32_t* last_out = at<int32_t>(ws, L.o_last);
+  float* tlast_out = at<float>(ws, L.o_tlast);
+  for (uint32_t q = threadIdx.x; q < count * 64u; q += NT) {
+    const uint32_t slot = first + (q >> 6);
+    const int pix = (int)(q & 63u);
+    const TileSlot sl = slots[slot];
+    const DevView& V = vw[sl.view];
+    if (pix == 0) tpend[slot] = sl.start;
+    const int lt = (int)sl.tile - V.tile_base;
+    const int i = (lt % V.tiles_x) * 8 + (pix & 7), j = (lt / V.tiles_x) * 8 + (pix >> 3);
+    if (i >= V.W || j >= V.H) continue;
+    const size_t plane = (size_t)V.W * V.H;
+    const size_t px = (size_t)j * V.W + i;
+    float* out = V.out;
+    out[0 * plane + px] = V.bg[0];
+    out[1 * plane + px] = V.bg[1];
+    out[2 * plane + px] = V.bg[2];
+#pragma unroll
+    for (int k = 3; k < 8; ++k) out[k * plane + px] = 0.0f;
+    const size_t g = (size_t)V.pix_base + px;
+    last_out[g] = -1;
+    tlast_out[g] = 1.0f;
+  }
+}
+
 }  // namespace
 
 template <int NWV>
@@ -125,6 +160,19 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   __shared__ float feat[7][CHN];
   __shared__ unsigned long long done_mask;
 
+  // the tiles with an empty list take the last slots (length bucket 0):
+  // workgroups past the others write their background, EMPTY_PER_WG tiles
+  // each, and the rest of the grid leaves at once
+  {
+    const uint32_t n_empty = at<const uint32_t>(ws, L.o_tile_hist)[0];
+    const uint32_t n_work = (uint32_t)L.total_tiles - n_empty;
+    if (blockIdx.x >= n_work) {
+      const uint32_t first = n_work + (blockIdx.x - n_work) * EMPTY_PER_WG;
+      if (first < (uint32_t)L.total_tiles)
+        background_tiles<64 * NWV>(ws, L, vw, first, min(EMPTY_PER_WG, (uint32_t)L.total_tiles - first));
+      return;
+    }
+  }
   const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
   const float s = V.s;
@@ -194,6 +242,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   // dispatch order by the length the forward walked (longest first); the
   // tiles where nothing was blended come last and leave at once
   const TileSlot* bslots = at<const TileSlot>(ws, L.o_bwd_order);
+  if (!recompute && blockIdx.x >= at<const DevHeader>(ws, L.o_hdr)->bwd_work) return;
   if (!recompute && at<const uint32_t>(ws, L.o_bwd_pend)[blockIdx.x] == bslots[blockIdx.x].start) return;
   const Tile8 c = tile8(vw, bslots);
   const DevView& V = vw[c.view];

@@ -59,7 +59,8 @@ struct DevHeader {
   uint32_t entries_total;
   uint32_t overflow;
   uint32_t invalid_index;
-  uint32_t pad0[3];
+  uint32_t bwd_work;    // backward dispatch slots with a walked entry (they come first)
+  uint32_t pad0[2];
   int64_t entry_capacity, kept_capacity;
   uint64_t entries_needed;  // entries the last forward wanted (exact, also on overflow)
   uint32_t pad1[50];
