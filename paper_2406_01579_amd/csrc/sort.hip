@@ -7,7 +7,9 @@
 //               every (digit, block)'s global output offset
 //   downsweep - per block, in input order, the rank of every key among the
 //               equal digits before it (wave ballots + wave-private LDS
-//               counts), then a scatter to offset + rank.
+//               counts); the block's pairs are then laid out in LDS in
+//               digit order and written from there, so consecutive threads
+//               write consecutive places of a digit's run.
 // The element count lives on the device (it is produced by earlier kernels),
 // so grids are sized for the capacity and idle blocks exit at once.
 #include "ts_internal.h"
@@ -95,6 +97,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
   __shared__ uint32_t base[RADIX];
   __shared__ uint32_t wrun[WAVES][RADIX];
   __shared__ uint32_t part[WAVES];
+  __shared__ uint32_t lbase[RADIX];          // block-local start of each digit's run
+  __shared__ uint32_t skey[SORT_TILE], sval[SORT_TILE];   // the block's pairs in digit order
   const uint32_t n = sort_n(n_dev, cap);
   const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
   const uint32_t b = blockIdx.x;
@@ -147,24 +151,49 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
   }
   __syncthreads();
   {
+    // digit d: the block's count, its block-local start (an exclusive scan
+    // over the digits), and each wave's start inside the run
     const int d = threadIdx.x;
-    uint32_t s = base[d];
+    uint32_t cnt = 0;
     for (int w = 0; w < WAVES; ++w) {
       const uint32_t c = wrun[w][d];
-      wrun[w][d] = s;
-      s += c;
+      wrun[w][d] = cnt;
+      cnt += c;
     }
+    uint32_t x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) part[wave] = x;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int w = 0; w < wave; ++w) wb += part[w];
+    lbase[d] = wb + x - cnt;
   }
   __syncthreads();
+  // the pairs into LDS in (digit, input) order ...
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const uint32_t i = i0 + it * 64;
     if (i < n) {
       const uint32_t digit = (keys[it] >> shift) & mask;
-      const uint32_t pos = wrun[wave][digit] + rank[it];
-      kout[pos] = keys[it];
-      vout[pos] = vals[it];
+      const uint32_t li = lbase[digit] + wrun[wave][digit] + rank[it];
+      skey[li] = keys[it];
+      sval[li] = vals[it];
     }
+  }
+  __syncthreads();
+  // ... and out in that order: consecutive threads write consecutive places
+  // of a digit's run
+  const uint32_t nloc = min((uint32_t)SORT_TILE, n - b * SORT_TILE);
+  for (uint32_t li = threadIdx.x; li < nloc; li += SORT_THREADS) {
+    const uint32_t k = skey[li];
+    const uint32_t digit = (k >> shift) & mask;
+    const uint32_t pos = base[digit] + (li - lbase[digit]);
+    kout[pos] = k;
+    vout[pos] = sval[li];
   }
 }
 }  // namespace
