@@ -674,9 +674,11 @@ hipError_t launch_sort_records(void* ws, const Layout& L, hipStream_t st) {
 hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st) {
   uint32_t *ko, *vo;
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  // the entries are the larger sort: 8 keys per thread (longer digit runs
+  // per block, half the blocks for the spine)
   return radix_sort_pairs(at<uint32_t>(ws, L.o_key2a), at<uint32_t>(ws, L.o_val2a), at<uint32_t>(ws, L.o_key2b),
                           at<uint32_t>(ws, L.o_val2b), false, &hdr->entries_total, L.entry_cap, L.key2_bits,
-                          at<uint32_t>(ws, L.o_hist), L.sort_blocks_max, st, &ko, &vo);
+                          at<uint32_t>(ws, L.o_hist), L.sort_blocks_max, st, &ko, &vo, 8);
 }
 
 // ---------------------------------------------------------------------------

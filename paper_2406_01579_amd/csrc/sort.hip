@@ -26,19 +26,21 @@ __device__ __forceinline__ uint32_t sort_n(const uint32_t* n_dev, int64_t cap) {
   return (int64_t)n > cap ? (uint32_t)cap : n;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_up(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
                                                            int64_t cap, int shift, int digit_bits,
                                                            uint32_t* __restrict__ hist) {
+  constexpr uint32_t TILE_ = SORT_THREADS * ITEMS;
   __shared__ uint32_t h[RADIX];
   const uint32_t n = sort_n(n_dev, cap);
-  const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t nb = (n + TILE_ - 1) / TILE_;
   const uint32_t b = blockIdx.x;
   if (b >= nb) return;
   const uint32_t mask = (1u << digit_bits) - 1u;
   for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) h[d] = 0;
   __syncthreads();
-  const uint32_t i0 = b * SORT_TILE;
-  for (int it = 0; it < SORT_ITEMS; ++it) {
+  const uint32_t i0 = b * TILE_;
+  for (int it = 0; it < ITEMS; ++it) {
     uint32_t i = i0 + it * SORT_THREADS + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
   }
@@ -48,11 +50,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_up(const uint32_t* __res
 
 // one block per digit: exclusive scan of that digit's per-block counts (in
 // place) and the digit total
+template <int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_spine(uint32_t* hist, uint32_t* totals,
                                                               const uint32_t* n_dev, int64_t cap) {
+  constexpr uint32_t TILE_ = SORT_THREADS * ITEMS;
   __shared__ uint32_t part[SORT_THREADS];
   const uint32_t n = sort_n(n_dev, cap);
-  const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t nb = (n + TILE_ - 1) / TILE_;
   const uint32_t d = blockIdx.x;
   uint32_t* row = hist + (size_t)d * nb;
   const uint32_t per = (nb + SORT_THREADS - 1) / SORT_THREADS;
@@ -88,19 +92,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_spine(uint32_t* hist, ui
 // matching and wave-private running counts in LDS (no block barriers while
 // ranking); one exclusive prefix across the waves then turns the ranks into
 // output positions.  Input order is preserved for equal digits (stable).
+template <int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              const uint32_t* n_dev, int64_t cap, int shift,
                                                              int digit_bits, const uint32_t* __restrict__ hist,
                                                              const uint32_t* __restrict__ totals) {
+  constexpr uint32_t TILE_ = SORT_THREADS * ITEMS;
   __shared__ uint32_t base[RADIX];
   __shared__ uint32_t wrun[WAVES][RADIX];
   __shared__ uint32_t part[WAVES];
   __shared__ uint32_t lbase[RADIX];          // block-local start of each digit's run
-  __shared__ uint32_t skey[SORT_TILE], sval[SORT_TILE];   // the block's pairs in digit order
+  __shared__ uint32_t skey[TILE_], sval[TILE_];   // the block's pairs in digit order
   const uint32_t n = sort_n(n_dev, cap);
-  const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t nb = (n + TILE_ - 1) / TILE_;
   const uint32_t b = blockIdx.x;
   if (b >= nb) return;
   const uint32_t mask = (1u << digit_bits) - 1u;
@@ -123,18 +129,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
     base[threadIdx.x] = wbase + x - tot + hist[(size_t)threadIdx.x * nb + b];
   }
   // ranking: wave w owns items [b*TILE + w*SUB, b*TILE + (w+1)*SUB)
-  constexpr int SUB = SORT_ITEMS * 64;
-  const uint32_t i0 = b * SORT_TILE + wave * SUB + lane;
-  uint32_t keys[SORT_ITEMS], vals[SORT_ITEMS], rank[SORT_ITEMS];
+  constexpr int SUB = ITEMS * 64;
+  const uint32_t i0 = b * TILE_ + wave * SUB + lane;
+  uint32_t keys[ITEMS], vals[ITEMS], rank[ITEMS];
   // keys and values in flight together, before any ranking
 #pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
+  for (int it = 0; it < ITEMS; ++it) {
     const uint32_t i = i0 + it * 64;
     keys[it] = i < n ? kin[i] : 0u;
     vals[it] = i < n ? (vin ? vin[i] : i) : 0u;
   }
 #pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
+  for (int it = 0; it < ITEMS; ++it) {
     const uint32_t i = i0 + it * 64;
     const bool valid = i < n;
     const uint32_t digit = (keys[it] >> shift) & mask;
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
   __syncthreads();
   // the pairs into LDS in (digit, input) order ...
 #pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
+  for (int it = 0; it < ITEMS; ++it) {
     const uint32_t i = i0 + it * 64;
     if (i < n) {
       const uint32_t digit = (keys[it] >> shift) & mask;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
   __syncthreads();
   // ... and out in that order: consecutive threads write consecutive places
   // of a digit's run
-  const uint32_t nloc = min((uint32_t)SORT_TILE, n - b * SORT_TILE);
+  const uint32_t nloc = min((uint32_t)TILE_, n - b * TILE_);
   for (uint32_t li = threadIdx.x; li < nloc; li += SORT_THREADS) {
     const uint32_t k = skey[li];
     const uint32_t digit = (k >> shift) & mask;
@@ -198,10 +204,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_down(const uint32_t* __r
 }
 }  // namespace
 
-hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool identity,
-                            const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
-                            hipStream_t st, uint32_t** keys_out, uint32_t** vals_out) {
-  const unsigned nb = (unsigned)((cap + SORT_TILE - 1) / SORT_TILE);
+template <int ITEMS>
+static hipError_t radix_sort_impl(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
+                                  bool identity, const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist,
+                                  int64_t hist_blocks, hipStream_t st, uint32_t** keys_out, uint32_t** vals_out) {
+  constexpr int64_t TILE_ = (int64_t)SORT_THREADS * ITEMS;
+  const unsigned nb = (unsigned)((cap + TILE_ - 1) / TILE_);
   // digit totals live after the (digit, block) table
   uint32_t* totals = hist + (size_t)RADIX * (size_t)hist_blocks;
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
@@ -209,10 +217,10 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   for (int shift = 0; shift < bits; shift += SORT_BITS) {
     const int db = (bits - shift) < SORT_BITS ? (bits - shift) : SORT_BITS;
     if (nb > 0) {
-      k_radix_up<<<nb, SORT_THREADS, 0, st>>>(ki, n_dev, cap, shift, db, hist);
-      k_radix_spine<<<RADIX, SORT_THREADS, 0, st>>>(hist, totals, n_dev, cap);
-      k_radix_down<<<nb, SORT_THREADS, 0, st>>>(ki, (first && identity) ? nullptr : vi, ko, vo, n_dev, cap, shift, db,
-                                                  hist, totals);
+      k_radix_up<ITEMS><<<nb, SORT_THREADS, 0, st>>>(ki, n_dev, cap, shift, db, hist);
+      k_radix_spine<ITEMS><<<RADIX, SORT_THREADS, 0, st>>>(hist, totals, n_dev, cap);
+      k_radix_down<ITEMS><<<nb, SORT_THREADS, 0, st>>>(ki, (first && identity) ? nullptr : vi, ko, vo, n_dev, cap,
+                                                         shift, db, hist, totals);
     }
     first = false;
     uint32_t* t = ki; ki = ko; ko = t;
@@ -221,6 +229,17 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   *keys_out = ki;
   *vals_out = vi;
   return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool identity,
+                            const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
+                            hipStream_t st, uint32_t** keys_out, uint32_t** vals_out, int items) {
+  if (items == 8)
+    return radix_sort_impl<8>(keys_a, vals_a, keys_b, vals_b, identity, n_dev, cap, bits, hist, hist_blocks, st,
+                              keys_out, vals_out);
+  if (items != SORT_ITEMS) return hipErrorInvalidValue;
+  return radix_sort_impl<SORT_ITEMS>(keys_a, vals_a, keys_b, vals_b, identity, n_dev, cap, bits, hist, hist_blocks,
+                                     st, keys_out, vals_out);
 }
 
 }  // namespace ts

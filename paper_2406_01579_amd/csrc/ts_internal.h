@@ -175,10 +175,11 @@ hipError_t launch_desc_zero_grads(const DevScene* hs, int ns, const DevView* hv,
 // [0, bits).  n is read on the device from *n_dev (clamped to cap).  The
 // first pass takes vals_in == nullptr as the identity permutation.  On
 // return the sorted data is in (*keys_out, *vals_out), which point at one of
-// the two buffer pairs.
+// the two buffer pairs.  `items` (SORT_ITEMS or 8) is the keys per thread
+// of a block; hist_blocks is sized for SORT_ITEMS, enough for 8.
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool identity,
                             const uint32_t* n_dev, int64_t cap, int bits, uint32_t* hist, int64_t hist_blocks,
-                            hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
+                            hipStream_t st, uint32_t** keys_out, uint32_t** vals_out, int items = SORT_ITEMS);
 
 // unique-edge build, the Sec. 4.2 regularisers and Marching Tetrahedra (geom.hip)
 struct EdgeLayout {

@@ -12,7 +12,8 @@ IMG_TOL = 1e-5     # max-abs image error vs the float32 oracle
 # against the float64 oracle, an FP32 implementation cannot do better than
 # the float32 oracle itself does (cancelling per-pixel terms of the position
 # and SDF gradients leave it up to ~1e-3 off); the GPU must stay within twice
-# the float32 oracle's own element-wise error (or 1e-4, whichever is larger).
+# the float32 oracle's own element-wise error plus 1e-4 (the GPU sums each
+# vertex's contributions in another, atomic, order than the float32 oracle).
 GRAD_TOL = 1e-4
 
 
@@ -56,7 +57,7 @@ def check_gradient(name, got, r32, r64, label=""):
     print(f"{label} {name}: normwise vs f32 {n32:.2e}; element-wise vs f64 {e64:.2e} "
           f"(f32 oracle vs f64 {o64:.2e}); element-wise vs f32 {grad_err(got, r32):.2e}")
     assert n32 <= GRAD_TOL, (name, n32)
-    assert e64 <= max(2.0 * o64, GRAD_TOL), (name, e64, o64)
+    assert e64 <= 2.0 * o64 + GRAD_TOL, (name, e64, o64)
 
 
 def near_threshold_pixels(g, cams, params, pix, s):
