@@ -203,46 +203,12 @@ __device__ __forceinline__ void eq1_chain(float da, float alpha, float e2, float
   dfn = on ? dB * s * e2 - ddv : 0.0f;                   // d/df_next
 }
 
-// g (zeroed by the caller) <- the pair's gradient, given the blend weight
-// w = T alpha (colour, depth and normal enter linearly), dL/df_prev = dd and
-// dL/df_next = dfn, and the entry/exit faces fs = fe | fx << 2.
-__device__ __forceinline__ void pair_grad_f(const ViewRec& R, float qx, float qy, const float (&gr)[8], float dd,
-                                            float dfn, float w, int fs, float (&g)[32]) {
-  g[G_C + 0] = w * gr[0];
-  g[G_C + 1] = w * gr[1];
-  g[G_C + 2] = w * gr[2];
-  g[G_ZT] = w * gr[4];
-  g[G_N + 0] = w * gr[5];
-  g[G_N + 1] = w * gr[6];
-  g[G_N + 2] = w * gr[7];
-  if (dd != 0.0f || dfn != 0.0f) {
-    const int fe = fs & 3, fx = fs >> 2;
-    float ax[4], ay[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      ax[k] = R.px[k] - qx;
-      ay[k] = R.py[k] - qy;
-    }
-    const float e01 = ax[0] * ay[1] - ay[0] * ax[1];
-    const float e02 = ax[0] * ay[2] - ay[0] * ax[2];
-    const float e03 = ax[0] * ay[3] - ay[0] * ax[3];
-    const float e12 = ax[1] * ay[2] - ay[1] * ax[2];
-    const float e13 = ax[1] * ay[3] - ay[1] * ax[3];
-    const float e23 = ax[2] * ay[3] - ay[2] * ax[3];
-    const float w0 = (fe == 0 ? dd : 0.0f) + (fx == 0 ? dfn : 0.0f);
-    const float w1 = (fe == 1 ? dd : 0.0f) + (fx == 1 ? dfn : 0.0f);
-    const float w2 = (fe == 2 ? dd : 0.0f) + (fx == 2 ? dfn : 0.0f);
-    const float w3 = (fe == 3 ? dd : 0.0f) + (fx == 3 ? dfn : 0.0f);
-    if (w0 != 0.0f) face_geom_grad<0>(R, ax, ay, e12, -e02, e01, w0, g);
-    if (w1 != 0.0f) face_geom_grad<1>(R, ax, ay, e13, -e03, e01, w1, g);
-    if (w2 != 0.0f) face_geom_grad<2>(R, ax, ay, e23, -e03, e02, w2, g);
-    if (w3 != 0.0f) face_geom_grad<3>(R, ax, ay, e23, -e13, e12, w3, g);
-  }
-}
-
-// pair_grad_f without branches: all four faces are chained, a face whose
-// weight is zero contributes exactly zero (its 1/S is taken as 0), so g is
-// updated in place and a lane with w = dd = dfn = 0 returns zeros.
+// g <- the pair's gradient with respect to the record's 23 screen-space
+// parameters, given the blend weight w = T alpha (colour, depth and normal
+// enter linearly), dL/df_prev = dd and dL/df_next = dfn, and the entry/exit
+// faces fs = fe | fx << 2.  Without branches: all four faces are chained, a
+// face whose weight is zero contributes exactly zero (its 1/S is taken as 0),
+// so g is updated in place and a lane with w = dd = dfn = 0 returns zeros.
 __device__ __forceinline__ void pair_grad_all(const ViewRec& R, float qx, float qy, const float (&gr)[8], float dd,
                                               float dfn, float w, int fs, float (&g)[32]) {
 #pragma unroll
@@ -275,14 +241,6 @@ __device__ __forceinline__ void pair_grad_all(const ViewRec& R, float qx, float 
   face_geom_grad<1, true>(R, ax, ay, e13, -e03, e01, w1, g);
   face_geom_grad<2, true>(R, ax, ay, e23, -e03, e02, w2, g);
   face_geom_grad<3, true>(R, ax, ay, e23, -e13, e12, w3, g);
-}
-
-// The same from dL/dalpha = da, the raw alpha and e2 = exp(s f_next).
-__device__ __forceinline__ void pair_grad(const ViewRec& R, float qx, float qy, float s, const float (&gr)[8],
-                                          float da, float w, float alpha, float e2, int fs, float (&g)[32]) {
-  float dd, dfn;
-  eq1_chain(da, alpha, e2, s, dd, dfn);
-  pair_grad_f(R, qx, qy, gr, dd, dfn, w, fs, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,44 +290,6 @@ __device__ __forceinline__ float wave_transpose_sum32(const float (&v)[32]) {
   return z;
 }
 
-
-// Per 16-lane row (gfx950 DPP row operations only): afterwards lane L of a
-// row holds, in .x and .y, the sums over the row's 16 lanes of v[2 (L & 15)]
-// and v[2 (L & 15) + 1].  Each step halves the values per lane while pairing
-// lanes 8, 4 (half-row mirror), 2 and 1 apart.  Every lane must be active.
-__device__ __forceinline__ float2 row_transpose_sum32(const float (&v)[32]) {
-  const unsigned lane = __lane_id();
-  const bool b3 = lane & 8u, b2 = lane & 4u, b1 = lane & 2u, b0 = lane & 1u;
-  float x[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const float send = b3 ? v[k] : v[k + 16];
-    const float keep = b3 ? v[k + 16] : v[k];
-    x[k] = keep + dpp<0x128>(send);   // row_ror:8   (j <-> j ^ 8)
-  }
-  float y[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float send = b2 ? x[k] : x[k + 8];
-    const float keep = b2 ? x[k + 8] : x[k];
-    y[k] = keep + dpp<0x141>(send);   // row_half_mirror (j <-> j ^ 7 in each half-row)
-  }
-  float z[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float send = b1 ? y[k] : y[k + 4];
-    const float keep = b1 ? y[k + 4] : y[k];
-    z[k] = keep + dpp<0x4E>(send);    // quad_perm [2,3,0,1] (j <-> j ^ 2)
-  }
-  float u[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float send = b0 ? z[k] : z[k + 2];
-    const float keep = b0 ? z[k + 2] : z[k];
-    u[k] = keep + dpp<0xB1>(send);    // quad_perm [1,0,3,2] (j <-> j ^ 1)
-  }
-  return make_float2(u[0], u[1]);
-}
 
 // Per 8-lane group (half of a DPP row): afterwards lane L of a group holds,
 // in .x .. .w, the sums over the group's 8 lanes of v[4 (L & 7)] ..
