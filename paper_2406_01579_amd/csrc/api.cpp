@@ -197,6 +197,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_scene_kept_base = take(4 * (size_t)ns);
   L.o_scene_kept_count = take(4 * (size_t)ns);
   L.o_pf_cnt = take(4 * (size_t)(pf_blocks + 1));
+  L.o_pf_keep = take(4 * (size_t)(PF_TILE / 32) * (size_t)(pf_blocks + 1));
   L.o_kept_tet = take(4 * (size_t)kept_cap);
   L.o_trec = take(sizeof(TetRec) * (size_t)kept_cap);
   L.o_vrec = take(sizeof(ViewRec) * (size_t)rec_cap);

@@ -134,12 +134,22 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_count(void* ws, Layout L, flo
   const int s = find_scene_by_block(sc, L.ns, b);
   const DevScene S = sc[s];
   const int k0 = (b - S.block_base) * PF_TILE + threadIdx.x * PF_PER_THREAD;
-  uint32_t c = 0;
+  uint32_t c = 0, nib = 0;
+  static_assert(PF_PER_THREAD == 4 && PF_THREADS % 8 == 0, "a thread's four decisions are a nibble of a word");
 #pragma unroll
   for (int q = 0; q < PF_PER_THREAD; ++q) {
     int k = k0 + q;
-    if (k < S.K) c += keep_tet(S, k, tf, &hdr->invalid_index, nullptr) ? 1u : 0u;
+    const bool kp = k < S.K && keep_tet(S, k, tf, &hdr->invalid_index, nullptr);
+    c += kp ? 1u : 0u;
+    nib |= kp ? 1u << q : 0u;
   }
+  // the decisions, 4 bits per thread: eight threads fill a word
+  const int lane = threadIdx.x & 63;
+  uint32_t w = nib << (4 * (lane & 7));
+  w |= __shfl_xor(w, 1, 64);
+  w |= __shfl_xor(w, 2, 64);
+  w |= __shfl_xor(w, 4, 64);
+  if ((lane & 7) == 0) at<uint32_t>(ws, L.o_pf_keep)[(size_t)b * (PF_TILE / 32) + (threadIdx.x >> 3)] = w;
   uint32_t tot;
   block_exclusive_scan_256(c, lds, &tot);
   if (threadIdx.x == 0) cnt[b] = tot;
@@ -215,13 +225,16 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
   const int s = find_scene_by_block(sc, L.ns, b);
   const DevScene S = sc[s];
   const int k0 = (b - S.block_base) * PF_TILE + threadIdx.x * PF_PER_THREAD;
+  // the count kernel's decisions (this thread's nibble); only kept tets are read
+  const uint32_t nib =
+      (at<const uint32_t>(ws, L.o_pf_keep)[(size_t)b * (PF_TILE / 32) + (threadIdx.x >> 3)] >> (4 * (threadIdx.x & 7))) & 15u;
   bool kp[PF_PER_THREAD];
   int4 vi[PF_PER_THREAD];
   uint32_t c = 0;
 #pragma unroll
   for (int q = 0; q < PF_PER_THREAD; ++q) {
-    int k = k0 + q;
-    kp[q] = (k < S.K) && keep_tet(S, k, tf, nullptr, &vi[q]);
+    kp[q] = (nib >> q) & 1u;
+    vi[q] = kp[q] ? reinterpret_cast<const int4*>(S.tets)[k0 + q] : make_int4(0, 0, 0, 0);
     c += kp[q] ? 1u : 0u;
   }
   uint32_t tot;

@@ -120,6 +120,7 @@ struct Layout {
   int max_scene_views;  // largest number of views of one scene
   size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
+  size_t o_pf_keep;   // pre-filter decisions, one bit per tet (PF_TILE / 32 words per block)
   size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_off_sorted, o_scan_part;
   size_t o_rbox;   // per record: pixel rectangle (rx, ry), view, first entry (16 B)
   size_t o_hist;
