@@ -54,8 +54,9 @@ __device__ __forceinline__ TileCtx tile_ctx(const DevView* vw, const TileSlot* s
   return c;
 }
 
-// (with rbox, the copy's first-entry field comes from the record's compact
-// box, where the emit kernel writes it)
+// The records of sorted entries [base, base + n) into LDS, eight threads per
+// 128-byte record.  With rbox, the copy's first-entry field comes from the
+// record's compact box, where the emit kernel writes it.
 __device__ __forceinline__ void load_chunk(ViewRec* recs, const ViewRec* __restrict__ vrec,
                                            const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads,
                                            const uint4* __restrict__ rbox = nullptr) {

@@ -106,10 +106,10 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
   __syncthreads();
 }
 
-// Background of the tiles with an empty list (the last `count` dispatch
-// slots from `first`), `per` tiles per workgroup: the outputs of a pixel no
-// record reaches (T = 1), no blended entry, and the tile's end of blended
-// prefix at its start.
+// Background of `count` tiles with an empty list (the dispatch slots from
+// `first`; a workgroup takes up to EMPTY_PER_WG of them): the outputs of a
+// pixel no record reaches (T = 1), no blended entry, and the tile's end of
+// blended prefix at its start.
 constexpr uint32_t EMPTY_PER_WG = 16;
 template <int NT>
 __device__ __forceinline__ void background_tiles(void* ws, const Layout& L, const DevView* vw, uint32_t first,

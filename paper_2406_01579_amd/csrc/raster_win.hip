@@ -265,8 +265,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   }
 }
 
-// (a 5-waves-per-SIMD target fits it in 96 VGPRs without spills: one more
-// resident workgroup per CU)
+// A 5-waves-per-SIMD target fits the backward in 96 VGPRs without spills:
+// one more resident workgroup per CU.
 template <int NWV>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_composite_bwd_win(void* ws, Layout L, float alpha_min,
                                                                 float alpha_clamp, float t_min, int nw) {

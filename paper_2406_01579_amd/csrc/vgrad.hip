@@ -49,7 +49,7 @@ constexpr int VB_HASH = 512;
 constexpr int VB_PROBES = 16;
 static_assert(VB_HASH == 1 << 9, "the slot hash keeps 9 bits");
 
-// (a 5-waves-per-SIMD target fits it in 96 VGPRs without spills)
+// A 5-waves-per-SIMD target fits the kernel in 96 VGPRs without spills.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_vertex_bwd(void* ws, Layout L) {
   __shared__ uint32_t hkey[VB_HASH];   // vertex id + 1; 0: empty
