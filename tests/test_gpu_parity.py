@@ -180,6 +180,32 @@ def test_ragged_image_sizes(size):
         assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n)), (size, tile)
 
 
+@pytest.mark.parametrize("recompute", [False, True])
+@pytest.mark.parametrize("size", [(50, 37), (130, 9)])
+def test_ragged_image_gradients_multiwave(size, recompute):
+    """Partial 8x8 tiles at the right and bottom edges through the multi-wave
+    backward (including the tiles nothing reaches), against the oracle."""
+    import torch
+    s = 100.0
+    w = synth.tiny(s=s, bg=(0.2, 0.5, 0.1))
+    Wd, Hd = size
+    cam = synth.orbit_camera(0.7, 0.35, 2.5, 50.0, Wd, Hd, bg=(0.2, 0.5, 0.1))[None]
+    cam[0, 17] = Hd / 2.0
+    P = _params("default", (8, 8), waves=4, recompute_state=recompute)
+    r, plan, _ = gpu_forward(w.scenes[0], cam, P)
+    dout = np.random.default_rng(21).normal(size=(8, Hd, Wd)).astype(np.float32)
+    (dv, ds, dc), = r.backward(plan, [torch.from_numpy(dout).cuda()])
+    torch.cuda.synchronize()
+    g = oracle.Geometry.of(w.scenes[0])
+    op = oracle_params(P, s)
+    pix = oracle.all_pixels(cam)
+    dflat = np.stack([dout[:, j, i] for (_, i, j) in pix], 0).astype(np.float32)
+    ref32 = oracle.backward(g, cam, op, pix, dflat, prec=32)
+    ref64 = oracle.backward(g, cam, op, pix, dflat, prec=64)
+    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
+        check_gradient(name, got.cpu().numpy(), r32, r64, f"ragged {size} recompute={recompute}")
+
+
 def test_empty_scene_and_culled_views():
     import torch
     w = synth.tiny(s=20.0, bg=(0.25, 0.5, 0.75))
