@@ -207,7 +207,6 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_key1b = take(4 * (size_t)rec_cap);
   L.o_val1a = take(4 * (size_t)rec_cap);
   L.o_val1b = take(4 * (size_t)rec_cap);
-  L.o_off_sorted = take(4 * (size_t)rec_cap);
   L.o_scan_part = take(4 * (size_t)(L.scan_blocks_rec + 1));
   L.o_hist = take(4 * (size_t)(256 * L.sort_blocks_max + 256));
   L.o_key2a = take(4 * (size_t)entry_cap);

@@ -430,36 +430,6 @@ __global__ __launch_bounds__(1024) void k_scan_spine(void* ws, Layout L) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_scan_down(void* ws, Layout L, const uint32_t* srec) {
-  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
-  const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
-  const uint32_t* part = at<const uint32_t>(ws, L.o_scan_part);
-  uint32_t* off = at<uint32_t>(ws, L.o_off_sorted);
-  __shared__ uint32_t lds[8];
-  const uint32_t n = hdr->records_total;
-  const uint32_t q0 = blockIdx.x * SCAN_TILE;
-  if (q0 >= n) return;
-  constexpr int PER = SCAN_TILE / 256;
-  // thread t owns PER consecutive items
-  uint32_t c[PER];
-  uint32_t sum = 0;
-  const uint32_t base = q0 + threadIdx.x * PER;
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    uint32_t q = base + i;
-    c[i] = (q < n) ? count1[srec[q]] : 0u;
-    sum += c[i];
-  }
-  uint32_t tot;
-  uint32_t run = part[blockIdx.x] + block_exclusive_scan_256(sum, lds, &tot);
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    uint32_t q = base + i;
-    if (q < n) off[q] = run;
-    run += c[i];
-  }
-}
-
 // sorted record order lives in the buffer the record sort ended in
 __host__ __device__ static const uint32_t* sorted_records(void* ws, const Layout& L) {
   // 32-bit keys in 8-bit digits: 4 passes, a->b->a->b->a
@@ -469,9 +439,9 @@ __host__ __device__ static const uint32_t* sorted_records(void* ws, const Layout
 hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st) {
   const uint32_t* srec = sorted_records(ws, L);
   unsigned nb = (unsigned)L.scan_blocks_rec;
+  // per-record offsets are finished inside the emit kernel
   k_scan_reduce<<<nb, 256, 0, st>>>(ws, L, srec);
   k_scan_spine<<<1, 1024, 0, st>>>(ws, L);
-  k_scan_down<<<nb, 256, 0, st>>>(ws, L, srec);
   return hipGetLastError();
 }
 
@@ -484,7 +454,6 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = sorted_records(ws, L);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
-  const uint32_t* off = at<const uint32_t>(ws, L.o_off_sorted);
   uint4* rbox = at<uint4>(ws, L.o_rbox);
   uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
   uint32_t* val2 = at<uint32_t>(ws, L.o_val2a);
@@ -500,28 +469,60 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (uint32_t)TILE_BUCKETS; i += gridDim.x * blockDim.x)
       bh[i] = 0u;
   }
+  // one SCAN_TILE block of depth-sorted records at a time: its records'
+  // entry offsets (the block's exclusive prefix from the spine plus a block
+  // scan of the tile counts), each record's first entry into its box, then
+  // the block's entries with consecutive threads on consecutive entries (the
+  // record of an entry by binary search over the offsets)
+  constexpr int PER = SCAN_TILE / 256;
+  __shared__ uint32_t loff[SCAN_TILE];
+  __shared__ uint32_t lds[8];
+  const uint32_t* part = at<const uint32_t>(ws, L.o_scan_part);
   const uint32_t n = hdr->records_total;
   const uint64_t cap = (uint64_t)L.entry_cap;
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    const uint32_t r = srec[q];
-    const uint32_t c = count1[r];
-    if (c == 0) continue;
-    const uint32_t o = off[q];
-    // the record's first entry goes to its compact box (read there by the
-    // backward kernels), and so does the rectangle come from it
-    const uint4 bx = rbox[r];
-    rbox[r].w = o;
-    const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu), j1 = (int)(bx.y >> 16);
-    const DevView& V = vw[bx.z];
-    const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
-    const int nx = tx1 - tx0 + 1;
-    for (uint32_t j = 0; j < c; ++j) {
-      const uint64_t d = (uint64_t)o + j;
-      if (d >= cap) break;
-      const int ty = ty0 + (int)(j / nx), tx = tx0 + (int)(j % nx);
-      key2[d] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
-      val2[d] = r;
+  const uint32_t nblk = (n + SCAN_TILE - 1) / SCAN_TILE;
+  const int t = threadIdx.x;
+  for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const uint32_t q0 = blk * SCAN_TILE;
+    const uint32_t m = min((uint32_t)SCAN_TILE, n - q0);
+    uint32_t c[PER], rr[PER], sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t k = (uint32_t)(t * PER + i);
+      rr[i] = k < m ? srec[q0 + k] : 0u;
+      c[i] = k < m ? count1[rr[i]] : 0u;
+      sum += c[i];
     }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan_256(sum, lds, &tot);
+    const uint32_t base = part[blk];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      loff[t * PER + i] = run;
+      if (c[i] != 0u) rbox[rr[i]].w = base + run;
+      run += c[i];
+    }
+    __syncthreads();
+    const uint32_t ne = (uint64_t)base + tot <= cap ? tot : (base < cap ? (uint32_t)(cap - base) : 0u);
+    for (uint32_t e = (uint32_t)t; e < ne; e += 256u) {
+      int k = 0;
+#pragma unroll
+      for (int step = SCAN_TILE / 2; step > 0; step >>= 1) {
+        const int k2 = k + step;
+        k = (k2 < (int)m && loff[k2] <= e) ? k2 : k;
+      }
+      const uint32_t r = srec[q0 + (uint32_t)k];
+      const uint4 bx = rbox[r];   // rectangle and view (the first entry is not read here)
+      const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu);
+      const DevView& V = vw[bx.z];
+      const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
+      const int nx = tx1 - tx0 + 1;
+      const uint32_t j = e - loff[k];
+      const int ty = ty0 + (int)(j / (uint32_t)nx), tx = tx0 + (int)(j % (uint32_t)nx);
+      key2[base + e] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+      val2[base + e] = r;
+    }
+    __syncthreads();
   }
 }
 

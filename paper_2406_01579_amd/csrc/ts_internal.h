@@ -106,7 +106,7 @@ enum { G_PX = 0, G_PY = 4, G_IZ = 8, G_F = 12, G_C = 16, G_ZT = 19, G_N = 20 };
 // workspace layout
 // ---------------------------------------------------------------------------
 constexpr int PF_TILE = 1024;      // tets per pre-filter block
-constexpr int SCAN_TILE = 2048;    // items per scan block
+constexpr int SCAN_TILE = 512;     // records per scan block (the emit kernel's unit too)
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 4;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
@@ -121,7 +121,7 @@ struct Layout {
   size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_pf_keep;   // pre-filter decisions, one bit per tet (PF_TILE / 32 words per block)
-  size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_off_sorted, o_scan_part;
+  size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_scan_part;
   size_t o_rbox;   // per record: pixel rectangle (rx, ry), view, first entry (16 B)
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
