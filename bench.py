@@ -99,8 +99,8 @@ def pct(a, q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
-              "build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the renderer shards by view and scene "
+              "with no exchange in the forward, and a multi-GPU run is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.serve:

@@ -1,6 +1,6 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances (stated by the build's contract): tile ids, per-tile ranges and
+Tolerances: tile ids, per-tile ranges and
 sort order bit-exact; images within 1e-5 max-abs and gradients within 1e-4
 relative (|g-r| / (|r| + 1e-3 max|r|)) of the float32 oracle.  The error
 against the float64 oracle is printed per output.
