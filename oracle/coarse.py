@@ -1,9 +1,10 @@
 """Oracle of the coarse-to-fine pre-filter (App. B, geometry stage).  Test
 infrastructure only.
 
-Round 1 pre-filters the tets of a cube grid (the oracle's own pre-filter,
-Sec. 3.2); the bounding box of the kept tets' vertices is taken; the grid is
-rebuilt over that box and the SDF sampled at the new vertices for round 2.
+The first pass pre-filters the tets of a cube grid (the oracle's own
+pre-filter, Sec. 3.2); the bounding box of the kept tets' vertices is taken;
+the grid is rebuilt over that box and the SDF sampled at the new vertices for
+the second pass.
 
 Readings (listed with the rest of the paper's readings): the rebuilt grid
 keeps the resolution R and cubic cells: a cube centred on the box with side
@@ -36,7 +37,7 @@ def kept_bounds(verts, tets, sdf, s: float, params=None):
 
 
 def resized_cube(lo, hi, R: int, old_h: float):
-    """(cube low corner [3] float32, cell size float32) of the round-2 grid."""
+    """(cube low corner [3] float32, cell size float32) of the second-pass grid."""
     lo = np.asarray(lo, np.float32)
     hi = np.asarray(hi, np.float32)
     ext = float(np.max(hi - lo))

@@ -1,10 +1,10 @@
 """Coarse-to-fine pre-filtering (App. B, geometry stage).
 
-Round 1 pre-filters a cube grid over the initial domain; the box of the kept
+The first pass pre-filters a cube grid over the initial domain; the box of the kept
 tets' vertices comes from the GPU (`render_prefilter_bounds`); the grid is
 rebuilt at the same resolution over a cube around that box (side = the box's
 largest extent plus one coarse cell on each side) and the SDF is sampled at
-the new vertices for round 2, which is the ordinary forward's pre-filter.
+the new vertices for the second pass, which is the ordinary forward's pre-filter.
 The SDF is the caller's: a function from vertex positions [V,3] to values [V]
 on the device (in the paper, the hash-grid network)."""
 from __future__ import annotations
@@ -65,7 +65,7 @@ def prefilter_bounds(scene: SceneT, params: Params | None = None):
 
 
 def resized_cube(lo, hi, R: int, old_h: float):
-    """(low corner [3] float32, cell size float32) of the round-2 cube grid."""
+    """(low corner [3] float32, cell size float32) of the second-pass cube grid."""
     lo = np.asarray(lo, np.float32)
     hi = np.asarray(hi, np.float32)
     side = np.float32(float(np.max(hi - lo)) + 2.0 * old_h)
@@ -76,9 +76,9 @@ def resized_cube(lo, hi, R: int, old_h: float):
 
 def coarse_to_fine(sdf_fn, R: int, s: float, params: Params | None = None, lo: float = -1.0, hi: float = 1.0,
                    device="cuda"):
-    """Two-round pre-filter.  Returns (verts, tets, sdf, info) of the round-2
-    grid; info holds both rounds' boxes and kept counts.  One host read of the
-    round-1 box."""
+    """Two-pass pre-filter.  Returns (verts, tets, sdf, info) of the second-pass
+    grid; info holds both passes' boxes and kept counts.  One host read of the
+    first-pass box."""
     params = params or Params()
     low1 = np.full(3, lo, np.float32)
     h1 = np.float32((hi - lo) / R)
@@ -87,7 +87,7 @@ def coarse_to_fine(sdf_fn, R: int, s: float, params: Params | None = None, lo: f
     b, k = prefilter_bounds(SceneT(v1, t1, f1, v1, s), params)
     box = b.cpu().numpy()
     kept1 = int(k.item())
-    info = {"round1_box": box, "round1_kept": kept1}
+    info = {"pass1_box": box, "pass1_kept": kept1}
     if kept1 == 0 or not np.all(np.isfinite(box)):
         return v1, t1, f1, info
     low2, h2 = resized_cube(box[:3], box[3:], R, float(h1))

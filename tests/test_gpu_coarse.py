@@ -1,6 +1,6 @@
 """Coarse-to-fine pre-filtering on the GPU against the oracle: the kept box
 and count bit-exact (up to tets whose alpha_max lies within float32 rounding
-of T_f), NaN box for an empty kept set, and the whole two-round rebuild equal
+of T_f), NaN box for an empty kept set, and the whole two-pass rebuild equal
 to the oracle's composition of the same steps."""
 import numpy as np
 import pytest
@@ -46,7 +46,7 @@ def test_bounds_match_oracle(name):
     assert int(k2.item()) == 0 and np.all(np.isnan(b2.cpu().numpy()))
 
 
-def test_two_round_rebuild_matches_oracle():
+def test_two_pass_rebuild_matches_oracle():
     import torch
     from paper_2406_01579_amd.coarse import coarse_to_fine
     R, s = 32, 320.0
@@ -56,12 +56,12 @@ def test_two_round_rebuild_matches_oracle():
         return torch.linalg.norm(v - torch.as_tensor(c, device=v.device), dim=1) - r
 
     v2, t2, f2, info = coarse_to_fine(sdf_fn, R, s)
-    # oracle: round 1 on the same grid and SDF values, then the rebuilt cube
+    # oracle: the first pass on the same grid and SDF values, then the rebuilt cube
     verts1, tets1 = synth.kuhn_grid(R)
     v1 = ocoarse.grid_vertices(np.full(3, -1.0, np.float32), np.float32(2.0 / R), R)
     f1 = sdf_fn(torch.from_numpy(v1).cuda()).cpu().numpy()
     lo, hi, n = ocoarse.kept_bounds(v1, tets1, f1, s)
-    assert info["round1_kept"] == n and np.array_equal(info["round1_box"], np.concatenate([lo, hi]))
+    assert info["pass1_kept"] == n and np.array_equal(info["pass1_box"], np.concatenate([lo, hi]))
     low, h = ocoarse.resized_cube(lo, hi, R, np.float32(2.0 / R))
     assert np.array_equal(v2.cpu().numpy(), ocoarse.grid_vertices(low, h, R))
     assert np.array_equal(t2.cpu().numpy(), tets1.astype(np.int32))
