@@ -293,82 +293,116 @@ hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, h
 // projection, pixel rectangle, tile count, depth key (float32, fixed op
 // sequence), 2D face determinants, shading features.
 // ---------------------------------------------------------------------------
+// One block projects 256 consecutive kept tets of one view per step.  The
+// 96-byte tet records come in and the 128-byte view records go out through
+// LDS (a 9 x 16-byte stride per record, so 16-byte LDS accesses of eight
+// neighbouring threads meet no bank twice), so that every HBM access of the
+// records is contiguous across the block.
+constexpr int PROJ_STRIDE = 9;   // uint4 per record in LDS
+static_assert(sizeof(TetRec) == 6 * 16 && sizeof(ViewRec) == 8 * 16, "record sizes in 16-byte units");
+
 __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2, int th_log2) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const int32_t* kbase = at<const int32_t>(ws, L.o_scene_kept_base);
   const int32_t* kcount = at<const int32_t>(ws, L.o_scene_kept_count);
   const int32_t* rbase = at<const int32_t>(ws, L.o_view_rec_base);
-  const TetRec* trec = at<const TetRec>(ws, L.o_trec);
-  ViewRec* vrec = at<ViewRec>(ws, L.o_vrec);
+  const uint4* trec4 = at<const uint4>(ws, L.o_trec);
+  uint4* vrec4 = at<uint4>(ws, L.o_vrec);
   uint32_t* count1 = at<uint32_t>(ws, L.o_count1);
   uint32_t* key1 = at<uint32_t>(ws, L.o_key1a);
   uint4* rbox = at<uint4>(ws, L.o_rbox);
+  __shared__ uint4 sbuf[256 * PROJ_STRIDE];
+  __shared__ uint32_t svalid[256];
   const int v = blockIdx.y;
   const DevView V = vw[v];
   const int n = kcount[V.scene];
   const int r0 = rbase[v];
   const int kb = kbase[V.scene];
   if ((uint64_t)r0 + (uint64_t)n > (uint64_t)hdr->records_total) return;  // capacity overflow guard
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const TetRec T = trec[kb + k];
-    const int r = r0 + k;
-    float X[4], Y[4], Z[4], px[4], py[4];
-    bool culled = false;
+  const int t = threadIdx.x;
+  for (int k0 = blockIdx.x * 256; k0 < n; k0 += gridDim.x * 256) {
+    const int nloc = min(256, n - k0);
+    // tet records in, contiguous
+    const uint4* src = trec4 + (size_t)(kb + k0) * 6;
+    for (int q = t; q < nloc * 6; q += 256) sbuf[(q / 6) * PROJ_STRIDE + (q % 6)] = src[q];
+    __syncthreads();
+    TetRec T;
+    if (t < nloc) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const float x = T.x[a][0], y = T.x[a][1], z = T.x[a][2];
-      X[a] = fmaf(V.R[0], x, fmaf(V.R[1], y, fmaf(V.R[2], z, V.t[0])));
-      Y[a] = fmaf(V.R[3], x, fmaf(V.R[4], y, fmaf(V.R[5], z, V.t[1])));
-      Z[a] = fmaf(V.R[6], x, fmaf(V.R[7], y, fmaf(V.R[8], z, V.t[2])));
-      culled |= (Z[a] < V.znear);
+      for (int q = 0; q < 6; ++q) reinterpret_cast<uint4*>(&T)[q] = sbuf[t * PROJ_STRIDE + q];
     }
-    ViewRec R;
-    uint32_t cnt = 0, key = 0xffffffffu;
-    if (!culled) {
+    __syncthreads();
+    uint32_t valid = 0;
+    if (t < nloc) {
+      const int k = k0 + t;
+      const int r = r0 + k;
+      float X[4], Y[4], Z[4], px[4], py[4];
+      bool culled = false;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        px[a] = fmaf(V.fx, X[a] / Z[a], V.cx);
-        py[a] = fmaf(V.fy, Y[a] / Z[a], V.cy);
+        const float x = T.x[a][0], y = T.x[a][1], z = T.x[a][2];
+        X[a] = fmaf(V.R[0], x, fmaf(V.R[1], y, fmaf(V.R[2], z, V.t[0])));
+        Y[a] = fmaf(V.R[3], x, fmaf(V.R[4], y, fmaf(V.R[5], z, V.t[1])));
+        Z[a] = fmaf(V.R[6], x, fmaf(V.R[7], y, fmaf(V.R[8], z, V.t[2])));
+        culled |= (Z[a] < V.znear);
       }
-      const float zt = ((Z[0] + Z[1]) + (Z[2] + Z[3])) * 0.25f;
-      const float xmin = fminf(fminf(px[0], px[1]), fminf(px[2], px[3]));
-      const float xmax = fmaxf(fmaxf(px[0], px[1]), fmaxf(px[2], px[3]));
-      const float ymin = fminf(fminf(py[0], py[1]), fminf(py[2], py[3]));
-      const float ymax = fmaxf(fmaxf(py[0], py[1]), fmaxf(py[2], py[3]));
-      const int i0 = (int)fminf(fmaxf(ceilf(xmin - 0.5f), 0.0f), (float)V.W);
-      const int i1 = (int)fmaxf(fminf(floorf(xmax - 0.5f), (float)(V.W - 1)), -1.0f);
-      const int j0 = (int)fminf(fmaxf(ceilf(ymin - 0.5f), 0.0f), (float)V.H);
-      const int j1 = (int)fmaxf(fminf(floorf(ymax - 0.5f), (float)(V.H - 1)), -1.0f);
-      if (i0 <= i1 && j0 <= j1) {
-        const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2, ty1 = j1 >> th_log2;
-        cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-        key = __float_as_uint(zt);
+      uint32_t cnt = 0, key = 0xffffffffu;
+      if (!culled) {
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
-          R.px[a] = px[a];
-          R.py[a] = py[a];
-          R.iz[a] = 1.0f / Z[a];
-          R.f[a] = T.f[a];
+          px[a] = fmaf(V.fx, X[a] / Z[a], V.cx);
+          py[a] = fmaf(V.fy, Y[a] / Z[a], V.cy);
         }
-        for (int F = 0; F < 4; ++F) {
-          const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
-          R.D[F] = (px[B] - px[A]) * (py[C] - py[A]) - (py[B] - py[A]) * (px[C] - px[A]);
+        const float zt = ((Z[0] + Z[1]) + (Z[2] + Z[3])) * 0.25f;
+        const float xmin = fminf(fminf(px[0], px[1]), fminf(px[2], px[3]));
+        const float xmax = fmaxf(fmaxf(px[0], px[1]), fmaxf(px[2], px[3]));
+        const float ymin = fminf(fminf(py[0], py[1]), fminf(py[2], py[3]));
+        const float ymax = fmaxf(fmaxf(py[0], py[1]), fmaxf(py[2], py[3]));
+        const int i0 = (int)fminf(fmaxf(ceilf(xmin - 0.5f), 0.0f), (float)V.W);
+        const int i1 = (int)fmaxf(fminf(floorf(xmax - 0.5f), (float)(V.W - 1)), -1.0f);
+        const int j0 = (int)fminf(fmaxf(ceilf(ymin - 0.5f), 0.0f), (float)V.H);
+        const int j1 = (int)fmaxf(fminf(floorf(ymax - 0.5f), (float)(V.H - 1)), -1.0f);
+        if (i0 <= i1 && j0 <= j1) {
+          const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2, ty1 = j1 >> th_log2;
+          cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+          key = __float_as_uint(zt);
+          ViewRec R;
+          for (int a = 0; a < 4; ++a) {
+            R.px[a] = px[a];
+            R.py[a] = py[a];
+            R.iz[a] = 1.0f / Z[a];
+            R.f[a] = T.f[a];
+          }
+          for (int F = 0; F < 4; ++F) {
+            const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
+            R.D[F] = (px[B] - px[A]) * (py[C] - py[A]) - (py[B] - py[A]) * (px[C] - px[A]);
+          }
+          R.c[0] = T.c[0]; R.c[1] = T.c[1]; R.c[2] = T.c[2];
+          R.zt = zt;
+          R.n[0] = T.n[0]; R.n[1] = T.n[1]; R.n[2] = T.n[2];
+          R.rx = (uint32_t)i0 | ((uint32_t)i1 << 16);
+          R.ry = (uint32_t)j0 | ((uint32_t)j1 << 16);
+          R.kept = kb + k;
+          R.view = v;
+          R.entry0 = 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) sbuf[t * PROJ_STRIDE + q] = reinterpret_cast<const uint4*>(&R)[q];
+          valid = 1;
+          // the fields the emit and vertex-backward kernels need, compact
+          rbox[r] = make_uint4(R.rx, R.ry, (uint32_t)v, 0u);
         }
-        R.c[0] = T.c[0]; R.c[1] = T.c[1]; R.c[2] = T.c[2];
-        R.zt = zt;
-        R.n[0] = T.n[0]; R.n[1] = T.n[1]; R.n[2] = T.n[2];
-        R.rx = (uint32_t)i0 | ((uint32_t)i1 << 16);
-        R.ry = (uint32_t)j0 | ((uint32_t)j1 << 16);
-        R.kept = kb + k;
-        R.view = v;
-        R.entry0 = 0;
-        vrec[r] = R;
-        // the fields the emit and vertex-backward kernels need, compact
-        rbox[r] = make_uint4(R.rx, R.ry, (uint32_t)v, 0u);
       }
+      count1[r] = cnt;
+      key1[r] = key;
     }
-    count1[r] = cnt;
-    key1[r] = key;
+    svalid[t] = valid;
+    __syncthreads();
+    // view records out, contiguous (records that cover no pixel are skipped)
+    uint4* dst = vrec4 + (size_t)(r0 + k0) * 8;
+    for (int q = t; q < nloc * 8; q += 256)
+      if (svalid[q >> 3]) dst[q] = sbuf[(q >> 3) * PROJ_STRIDE + (q & 7)];
+    __syncthreads();
   }
 }
 
