@@ -44,8 +44,8 @@ MEASURED = {"sha256": {"paper_2406_01579_amd/csrc/raster_mw.hip":
                        "4eb10f57735cdf13db6c29e9bc49813dfc8dd5f4ea0926bed8326e855b5d4b51",
                        "paper_2406_01579_amd/csrc/tile8.h":
                        "4a4b1341699ef6b6b9e342a79db5c1405dd96dcb438c9428c912574d09dd0aa2"},
-            "composite_bwd": {"traffic": 125.9e6, "valu_issue_frac": 0.48},
-            "composite": {"traffic": 120.2e6, "valu_issue_frac": 0.56}}
+            "composite_bwd": {"traffic": 125.7e6, "valu_issue_frac": 0.48},
+            "composite": {"traffic": 120.4e6, "valu_issue_frac": 0.56}}
 
 
 def measured_counters(kernel, args):
