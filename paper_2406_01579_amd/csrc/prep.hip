@@ -295,9 +295,10 @@ hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, h
 // ---------------------------------------------------------------------------
 // One block projects 256 consecutive kept tets of one view per step.  The
 // 96-byte tet records come in and the 128-byte view records go out through
-// LDS (a 9 x 16-byte stride per record, so 16-byte LDS accesses of eight
-// neighbouring threads meet no bank twice), so that every HBM access of the
-// records is contiguous across the block.
+// LDS, so that every HBM access of the records is contiguous across the
+// block.  A record takes 9 x 16 bytes in LDS: when each thread reads or
+// writes its own record 16 bytes at a time, sixteen neighbouring threads
+// touch 64 distinct banks.
 constexpr int PROJ_STRIDE = 9;   // uint4 per record in LDS
 static_assert(sizeof(TetRec) == 6 * 16 && sizeof(ViewRec) == 8 * 16, "record sizes in 16-byte units");
 
