@@ -285,6 +285,34 @@ int render_prefilter_bounds(const render_scene* scene, const render_params* para
                             void* stream);
 
 /*
+ * Coarse-to-fine grid rebuild (App. B: the second pre-filter pass runs on a
+ * grid refitted around the tets the first pass keeps).  Grids are Kuhn cube
+ * grids: R^3 cubic cells of size h with low corner (lx, ly, lz), given as a
+ * DEVICE float[4] cube = (lx, ly, lz, h); vertex (x, y, z), 0 <= x, y, z <= R,
+ * has index x + (R+1)(y + (R+1) z) and position low + (x, y, z) h (float32,
+ * one product and one sum per coordinate); cell q = x + R(y + R z) is split
+ * into tets 6q + p along the six axis orders (a, b, c), p in lexicographic
+ * order, with vertices (v0, v0 + e_a, v0 + e_a + e_b, v0 + (1, 1, 1)).
+ *
+ * render_cube_grid writes verts: device float [(R+1)^3][3] and, unless tets
+ * is NULL, tets: device int32 [6 R^3][4] (16-byte aligned).  1 <= R <= 1024.
+ *
+ * render_refit_cube: the second-pass cube from bounds (as written by
+ * render_prefilter_bounds for the first pass) and the first-pass cube cube_in
+ * (device float[4]); writes cube_out (device float[4]).  The new cube keeps R
+ * and cubic cells: centred on the box, side = the box's largest extent plus
+ * one first-pass cell on each side (extents in float32, the side rounded to
+ * float32 from their double sum, centre and low corner in double rounded to
+ * float32, h = side / R in float32).  A NaN box (nothing kept) copies
+ * cube_in.  cube_out may not alias bounds.
+ *
+ * Both are asynchronous on stream, take no workspace and read nothing on the
+ * host, so the two passes need no synchronisation.
+ */
+int render_cube_grid(int32_t R, const float* cube, float* verts, int32_t* tets, void* stream);
+int render_refit_cube(const float* bounds, const float* cube_in, int32_t R, float* cube_out, void* stream);
+
+/*
  * render_marching_tets: triangle mesh of the zero level set (Marching
  * Tetrahedra, the mesh extraction of Sec. 4.1).  A vertex is inside when
  * f < 0.  Every edge of `edges` (as written by render_mesh_edges for the

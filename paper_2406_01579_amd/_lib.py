@@ -60,7 +60,7 @@ EXPORTS = ("render_workspace_size", "render_forward", "render_backward", "render
            "render_debug_pointers", "render_last_error", "render_profile", "render_profile_read",
            "render_decode_status", "render_mesh_edges_workspace_size", "render_mesh_edges",
            "render_regularizers_workspace_size", "render_regularizers", "render_marching_tets_workspace_size",
-           "render_marching_tets", "render_prefilter_bounds")
+           "render_marching_tets", "render_prefilter_bounds", "render_cube_grid", "render_refit_cube")
 STATUS_BYTES = 256
 
 STAGES = ("upload", "prefilter", "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "composite",
@@ -91,6 +91,8 @@ def lib():
         L.render_regularizers_workspace_size.argtypes = [I32, I32, C.POINTER(C.c_size_t)]
         L.render_regularizers.argtypes = [P, P, P, I32, I32, P, P, I64, P, P, P, P, P, C.c_size_t, P]
         L.render_prefilter_bounds.argtypes = [P, P, P, P, P]
+        L.render_cube_grid.argtypes = [I32, P, P, P, P]
+        L.render_refit_cube.argtypes = [P, P, I32, P, P]
         L.render_marching_tets_workspace_size.argtypes = [I32, I64, C.POINTER(C.c_size_t)]
         L.render_marching_tets.argtypes = [P, P, P, I32, I32, P, P, I64, P, I64, P, I64, P, P, C.c_size_t, P]
         for name in EXPORTS:

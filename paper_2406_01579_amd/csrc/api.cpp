@@ -324,6 +324,26 @@ int render_prefilter_bounds(const render_scene* scene, const render_params* para
   return RENDER_OK;
 }
 
+int render_cube_grid(int32_t R, const float* cube, float* verts, int32_t* tets, void* stream) {
+  if (R < 1 || R > 1024) return fail(RENDER_EINVAL, "R out of range (%d)", R);
+  if (!cube || !verts) return fail(RENDER_EINVAL, "null cube or verts");
+  if (((uintptr_t)cube & 3u) != 0 || ((uintptr_t)verts & 3u) != 0 || ((uintptr_t)tets & 15u) != 0)
+    return fail(RENDER_EINVAL, "misaligned cube, verts or tets");
+  hipError_t e = ts::launch_cube_grid(R, cube, verts, tets, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RENDER_EHIP, "cube grid: %s", hipGetErrorString(e));
+  return RENDER_OK;
+}
+
+int render_refit_cube(const float* bounds, const float* cube_in, int32_t R, float* cube_out, void* stream) {
+  if (R < 1 || R > 1024) return fail(RENDER_EINVAL, "R out of range (%d)", R);
+  if (!bounds || !cube_in || !cube_out) return fail(RENDER_EINVAL, "null bounds or cube");
+  if ((((uintptr_t)bounds | (uintptr_t)cube_in | (uintptr_t)cube_out) & 3u) != 0)
+    return fail(RENDER_EINVAL, "misaligned bounds or cube");
+  hipError_t e = ts::launch_refit_cube(bounds, cube_in, R, cube_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RENDER_EHIP, "refit cube: %s", hipGetErrorString(e));
+  return RENDER_OK;
+}
+
 int render_marching_tets_workspace_size(int32_t K, int64_t edge_capacity, size_t* bytes) {
   if (!bytes) return fail(RENDER_EINVAL, "null bytes");
   if (K < 0 || K > (1 << 30) || edge_capacity < 0 || edge_capacity > 0x7fffffffll)

@@ -868,4 +868,86 @@ hipError_t launch_prefilter_bounds(const DevScene& S, float tf, float* bounds, i
   return hipGetLastError();
 }
 
+
+
+// ---------------------------------------------------------------------------
+// Coarse-to-fine grid (App. B).  The second pass keeps the resolution R and
+// cubic cells: a cube centred on the first pass's kept box, whose side is the
+// box's largest extent plus one coarse cell on each side.  Arithmetic of the
+// cube: extents in float32, side rounded to float32 from the double sum, the
+// centre and low corner in double (rounded to float32 at the end), cell size
+// side / R in float32.  An empty kept set (NaN box) keeps the input cube.
+// ---------------------------------------------------------------------------
+__global__ void k_refit_cube(const float* __restrict__ box, const float* __restrict__ cube_in, int R,
+                             float* __restrict__ cube_out) {
+  if (threadIdx.x != 0) return;
+  float lo[3], hi[3];
+  bool empty = false;
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = box[c];
+    hi[c] = box[3 + c];
+    empty = empty || !(lo[c] == lo[c]) || !(hi[c] == hi[c]);
+  }
+  if (empty) {
+    for (int c = 0; c < 4; ++c) cube_out[c] = cube_in[c];
+    return;
+  }
+  float ext = hi[0] - lo[0];
+  ext = fmaxf(ext, hi[1] - lo[1]);
+  ext = fmaxf(ext, hi[2] - lo[2]);
+  const double pad = 2.0 * (double)cube_in[3];
+  const float side = (float)((double)ext + pad);
+  const double half = (double)side * 0.5;
+  for (int c = 0; c < 3; ++c) {
+    const double mid = ((double)lo[c] + (double)hi[c]) * 0.5;
+    cube_out[c] = (float)(mid - half);
+  }
+  cube_out[3] = side / (float)R;
+}
+
+// Vertex (x, y, z) = x + (R+1)(y + (R+1) z) at low + (x, y, z) h (float32:
+// one product, one sum, no fused multiply-add); cell q = x + R(y + R z) holds
+// tets 6q + p, p over the six axis orders (a, b, c) in lexicographic order,
+// with vertices (v0, v0 + e_a, v0 + e_a + e_b, v0 + (1, 1, 1)).
+__global__ __launch_bounds__(256) void k_cube_grid(int R, const float* __restrict__ cube, float* __restrict__ verts,
+                                                   int4* __restrict__ tets) {
+  const uint32_t n = (uint32_t)R + 1u;
+  const uint64_t nv = (uint64_t)n * n * n, nc = (uint64_t)R * R * R;
+  const float lx = cube[0], ly = cube[1], lz = cube[2], h = cube[3];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nv; t += stride) {
+    const uint32_t x = (uint32_t)(t % n), y = (uint32_t)((t / n) % n), z = (uint32_t)(t / ((uint64_t)n * n));
+    verts[3 * t + 0] = lx + (float)x * h;
+    verts[3 * t + 1] = ly + (float)y * h;
+    verts[3 * t + 2] = lz + (float)z * h;
+  }
+  if (!tets) return;
+  const int st[3] = {1, (int)n, (int)(n * n)};
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += stride) {
+    const uint32_t x = (uint32_t)(q % R), y = (uint32_t)((q / R) % R), z = (uint32_t)(q / ((uint64_t)R * R));
+    const int v0 = (int)(x + n * (y + n * z));
+    const int diag = v0 + 1 + (int)n + (int)(n * n);
+    // axis orders (0,1,2) (0,2,1) (1,0,2) (1,2,0) (2,0,1) (2,1,0): first and second axis
+    const int fa[6] = {0, 0, 1, 1, 2, 2}, fb[6] = {1, 2, 0, 2, 0, 1};
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const int a1 = v0 + st[fa[p]];
+      tets[6 * q + p] = make_int4(v0, a1, a1 + st[fb[p]], diag);
+    }
+  }
+}
+
+hipError_t launch_refit_cube(const float* bounds, const float* cube_in, int R, float* cube_out, hipStream_t st) {
+  k_refit_cube<<<1, 64, 0, st>>>(bounds, cube_in, R, cube_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cube_grid(int R, const float* cube, float* verts, int32_t* tets, hipStream_t st) {
+  const uint64_t nv = (uint64_t)(R + 1) * (R + 1) * (R + 1);
+  const uint64_t blocks = std::min<uint64_t>((nv + 255) / 256, 8192);
+  k_cube_grid<<<(unsigned)std::max<uint64_t>(blocks, 1), 256, 0, st>>>(R, cube, verts,
+                                                                       reinterpret_cast<int4*>(tets));
+  return hipGetLastError();
+}
+
 }  // namespace ts

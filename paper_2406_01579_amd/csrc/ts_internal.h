@@ -201,6 +201,8 @@ hipError_t launch_regularizers(const float* verts, const int32_t* tets, const fl
                                double* losses, float* dverts, float* dsdf, void* ws, const RegLayout& R,
                                hipStream_t st);
 hipError_t launch_prefilter_bounds(const DevScene& S, float tf, float* bounds, int64_t* kept, hipStream_t st);
+hipError_t launch_refit_cube(const float* bounds, const float* cube_in, int R, float* cube_out, hipStream_t st);
+hipError_t launch_cube_grid(int R, const float* cube, float* verts, int32_t* tets, hipStream_t st);
 
 struct MTLayout {
   uint64_t edge_blocks, tet_blocks;

@@ -232,3 +232,18 @@ def test_resort_window_arguments(L):
     p2.window = 3
     assert _size(L, s2, v2, p2)[0] == L.RENDER_EINVAL
     assert b"8x8" in L.lib().render_last_error()
+
+
+def test_coarse_grid_entry_points_validate_on_the_host(L):
+    """Bad resolutions, null and misaligned pointers are rejected before any
+    device work (the pointers below are never dereferenced)."""
+    lib = L.lib()
+    assert lib.render_cube_grid(0, 4096, 8192, 16384, None) == L.RENDER_EINVAL
+    assert lib.render_cube_grid(1025, 4096, 8192, 16384, None) == L.RENDER_EINVAL
+    assert lib.render_cube_grid(8, None, 8192, 16384, None) == L.RENDER_EINVAL
+    assert lib.render_cube_grid(8, 4096, None, 16384, None) == L.RENDER_EINVAL
+    assert lib.render_cube_grid(8, 4096, 8192, 16388, None) == L.RENDER_EINVAL
+    assert lib.render_refit_cube(4096, 8192, 0, 16384, None) == L.RENDER_EINVAL
+    assert lib.render_refit_cube(None, 8192, 8, 16384, None) == L.RENDER_EINVAL
+    assert lib.render_refit_cube(4096, 8192, 8, 16386, None) == L.RENDER_EINVAL
+    assert b"misaligned" in lib.render_last_error()
