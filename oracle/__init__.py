@@ -47,11 +47,18 @@ def lib():
         L.oracle_render.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, P, C.c_long, P, P, P]
         L.oracle_render_dual.argtypes = [P, P, P, P, C.c_int, C.c_int, P, P, P, P, C.c_int, P, P, C.c_long, P, P]
         L.oracle_backward.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, P, C.c_long, P, P, P, P]
+        L.oracle_render_errbound.argtypes = [P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, P, C.c_long, P, P]
+        L.oracle_alpha_errbound.argtypes = [C.c_double, C.c_double, C.c_double, P]
+        L.oracle_alpha_errbound.restype = C.c_double
+        L.oracle_backward_budget.argtypes = [P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, P, C.c_long, P,
+                                             P, P, P]
         L.oracle_prefilter.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, P, P, P, P, P]
         L.oracle_binning.argtypes = [P, P, P, C.c_int, C.c_int, P, C.c_int, P, C.c_long, P, P, P, P, P]
         L.oracle_binning.restype = C.c_long
         L.oracle_pixel_trace.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, C.c_int,
                                          C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P]
+        L.oracle_pixel_decisions.argtypes = [P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, C.c_int, C.c_int,
+                                             C.c_int, C.c_int, P, P, P, P]
         L.oracle_tet_pixel.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P]
         L.oracle_alpha.argtypes = [C.c_double, C.c_double, C.c_double]
         L.oracle_alpha.restype = C.c_double
@@ -162,6 +169,51 @@ def backward(g: Geometry, cams, params, pix, dout, prec: int = 64):
     return dv, ds, dc
 
 
+def render_error_bound(g: Geometry, cams, params, pix):
+    """(out [npix, 8] float64, bound [npix, 8]): the running error bound of a
+    float32 evaluation of ``render`` (first order, per channel)."""
+    cams = np.ascontiguousarray(cams, dtype=np.float32)
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    n = pix.shape[0]
+    out = np.zeros((n, 8), np.float64)
+    bnd = np.zeros((n, 8), np.float64)
+    lib().oracle_render_errbound(_p(g.verts), _p(g.tets), _p(g.sdf), _p(g.colors), g.V, g.K, _p(cams),
+                                 cams.shape[0], _p(params), _p(pix), n, _p(out), _p(bnd))
+    return out, bnd
+
+
+def alpha_error_bound(fprev, fnext, s):
+    """(alpha, bound): Eq. 1 in float64 and the running error bound of its float32 evaluation."""
+    b = np.zeros(1, np.float64)
+    a = lib().oracle_alpha_errbound(float(fprev), float(fnext), float(s), _p(b))
+    return float(a), float(b[0])
+
+
+def backward_budget(g: Geometry, cams, params, pix, dout):
+    """Error budget of a float32 evaluation of ``backward`` (float64 arrays,
+    each split as (dverts [V,3], dsdf [V], dcolors [V,3])):
+
+    A -- sum over (view, tet) of |J| times the summed per-pixel |g|: any order
+         and grouping of the float32 sums moves an element by at most
+         gamma_{n-1} A (Higham, Sec. 4.2, carried through the linear chain);
+    E -- sum over (view, tet) of |J| times the summed running error bounds of
+         the per-pixel terms (a term only one precision blends: in full);
+    N -- number of terms reaching the element.
+    """
+    cams = np.ascontiguousarray(cams, dtype=np.float32)
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    dout = _f64(dout)
+    A, E, N = (np.zeros((g.V, 7), np.float64) for _ in range(3))
+    rc = lib().oracle_backward_budget(_p(g.verts), _p(g.tets), _p(g.sdf), _p(g.colors), g.V, g.K, _p(cams),
+                                      cams.shape[0], _p(params), _p(pix), pix.shape[0], _p(dout), _p(A), _p(E),
+                                      _p(N))
+    assert rc == 0
+
+    def split(x):
+        return x[:, 0:3].copy(), x[:, 3].copy(), x[:, 4:7].copy()
+    return dict(A=split(A), E=split(E), N=split(N))
+
+
 def prefilter(g: Geometry, params, prec: int = 64):
     """keep [K] bool, alpha_max (float32 decision value) [K], normal [K,3], color [K,3], grad [K,3]."""
     K = g.K
@@ -208,6 +260,21 @@ def pixel_trace(g: Geometry, cams, params, view, i, j, prec: int = 64, cap: int 
                                  _p(fp), _p(fn), _p(zi))
     n = min(n, cap)
     return dict(tet=tid[:n], alpha=a[:n], T=T[:n], alpha_raw=ar[:n], fprev=fp[:n], fnext=fn[:n], zin=zi[:n])
+
+
+def pixel_decisions(g: Geometry, cams, params, view, i, j, cap: int = 8192):
+    """Threshold decisions of one pixel's walk: dict(kind, value, bound,
+    threshold) with kind 0 = alpha vs alpha_min, 1 = alpha vs alpha_clamp,
+    2 = T (1 - alpha) vs t_min; value in float64 and bound the running error
+    bound of a float32 evaluation of it."""
+    cams = np.ascontiguousarray(cams, dtype=np.float32)
+    kind = np.zeros(cap, np.int32)
+    val, bnd, thr = (np.zeros(cap, np.float64) for _ in range(3))
+    n = lib().oracle_pixel_decisions(_p(g.verts), _p(g.tets), _p(g.sdf), _p(g.colors), g.V, g.K, _p(cams),
+                                     cams.shape[0], _p(params), int(view), int(i), int(j), cap, _p(kind), _p(val),
+                                     _p(bnd), _p(thr))
+    n = min(n, cap)
+    return dict(kind=kind[:n], value=val[:n], bound=bnd[:n], threshold=thr[:n])
 
 
 def tet_pixel(px, py, Z, f, qx, qy, s):

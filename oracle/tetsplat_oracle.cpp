@@ -80,6 +80,51 @@ inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
 inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 inline bool operator==(Dual a, Dual b) { return a.v == b.v; }
 
+// ---------------------------------------------------------------------------
+// running error bound (Wilkinson's running error analysis; Higham, Accuracy
+// and Stability of Numerical Algorithms, 2nd ed., Sec. 3.3): v is the value
+// computed in float64 with exactly the double instantiation's operations, e a
+// first-order bound on how far a float32 evaluation of the same operations
+// can be from v.  Each float32 operation rounds with relative error at most
+// u = 2^-24 plus an absolute error of at most 2^-150 below the normal range
+// (Higham, Thm 2.3; the exponentials at most two units of u); inputs and
+// constants are float32 values, exact.  A result past the float32 range is
+// infinite there: its bound is infinite, and a finite value divided by it
+// (zero in float32) is off by at most its own magnitude.
+// ---------------------------------------------------------------------------
+constexpr double U32 = 1.0 / 16777216.0;
+constexpr double ETA32 = 0x1p-150;
+constexpr double FLT32_MAX = 3.4028234663852886e38;
+struct Rerr {
+  double v, e;
+  Rerr() : v(0), e(0) {}
+  Rerr(double x) : v(x), e(0) {}
+  Rerr(double x, double ex) : v(x), e(ex) {}
+};
+inline double rnd32(double v) {
+  return std::fabs(v) > FLT32_MAX ? HUGE_VAL : U32 * std::fabs(v) + ETA32;
+}
+inline Rerr operator+(Rerr a, Rerr b) { double v = a.v + b.v; return {v, a.e + b.e + rnd32(v)}; }
+inline Rerr operator-(Rerr a, Rerr b) { double v = a.v - b.v; return {v, a.e + b.e + rnd32(v)}; }
+inline Rerr operator-(Rerr a) { return {-a.v, a.e}; }
+inline Rerr operator*(Rerr a, Rerr b) {
+  double v = a.v * b.v;
+  return {v, std::fabs(b.v) * a.e + std::fabs(a.v) * b.e + rnd32(v)};
+}
+inline Rerr operator/(Rerr a, Rerr b) {
+  double v = a.v / b.v;
+  if (std::isinf(b.e) && !std::isinf(a.e)) return {v, std::fabs(v) + ETA32};
+  return {v, (a.e + std::fabs(v) * b.e) / std::fabs(b.v) + rnd32(v)};
+}
+inline Rerr& operator+=(Rerr& a, Rerr b) { a = a + b; return a; }
+inline Rerr& operator-=(Rerr& a, Rerr b) { a = a - b; return a; }
+inline Rerr& operator*=(Rerr& a, Rerr b) { a = a * b; return a; }
+inline bool operator<(Rerr a, Rerr b) { return a.v < b.v; }
+inline bool operator>(Rerr a, Rerr b) { return a.v > b.v; }
+inline bool operator<=(Rerr a, Rerr b) { return a.v <= b.v; }
+inline bool operator>=(Rerr a, Rerr b) { return a.v >= b.v; }
+inline bool operator==(Rerr a, Rerr b) { return a.v == b.v; }
+
 inline float r_exp(float x) { return std::exp(x); }
 inline double r_exp(double x) { return std::exp(x); }
 inline Dual r_exp(Dual x) { double e = std::exp(x.v); return {e, e * x.d}; }
@@ -89,15 +134,30 @@ inline Dual r_expm1(Dual x) { return {std::expm1(x.v), std::exp(x.v) * x.d}; }
 inline float r_sqrt(float x) { return std::sqrt(x); }
 inline double r_sqrt(double x) { return std::sqrt(x); }
 inline Dual r_sqrt(Dual x) { double r = std::sqrt(x.v); return {r, r > 0 ? x.d / (2 * r) : 0.0}; }
+inline Rerr r_exp(Rerr x) { double v = std::exp(x.v); return {v, v * x.e + 2 * rnd32(v)}; }
+inline Rerr r_expm1(Rerr x) {
+  double v = std::expm1(x.v);
+  return {v, std::exp(x.v) * x.e + 2 * rnd32(v)};
+}
+inline Rerr r_sqrt(Rerr x) {
+  double r = std::sqrt(x.v);
+  return {r, (r > 0 ? x.e / (2 * r) : std::sqrt(x.e)) + rnd32(r)};
+}
 inline float r_fma(float a, float b, float c) { return std::fma(a, b, c); }
 inline double r_fma(double a, double b, double c) { return std::fma(a, b, c); }
 inline Dual r_fma(Dual a, Dual b, Dual c) { return a * b + c; }
+inline Rerr r_fma(Rerr a, Rerr b, Rerr c) {
+  double v = std::fma(a.v, b.v, c.v);
+  return {v, std::fabs(b.v) * a.e + std::fabs(a.v) * b.e + c.e + rnd32(v)};
+}
 inline double val(float x) { return x; }
 inline double val(double x) { return x; }
 inline double val(Dual x) { return x.v; }
+inline double val(Rerr x) { return x.v; }
 inline double tan_(float) { return 0; }
 inline double tan_(double) { return 0; }
 inline double tan_(Dual x) { return x.d; }
+inline double tan_(Rerr x) { return x.e; }
 
 // ---------------------------------------------------------------------------
 // inputs
@@ -412,9 +472,20 @@ void resort_window(std::vector<Contrib<R>>& list, int nw, float alpha_min) {
   list.swap(out);
 }
 
+// One threshold decision of a pixel's walk: the quantity compared and the
+// threshold it was compared with (kind 0: alpha vs alpha_min, 1: alpha vs
+// alpha_clamp, 2: T (1 - alpha) vs t_min).
+template <class R>
+struct Decision {
+  int kind;
+  R value;
+  float threshold;
+};
+
 template <class R>
 void shade_pixel(const std::vector<KTet<R>>& kt, const std::vector<VTet<R>>& vt, const Cam& c,
-                 const Params& P, int i, int j, PixelResult<R>& pr, bool keep_list) {
+                 const Params& P, int i, int j, PixelResult<R>& pr, bool keep_list,
+                 std::vector<Decision<R>>* log = nullptr) {
   R qx = R(i + 0.5), qy = R(j + 0.5);
   std::vector<Contrib<R>> list;
   for (size_t k = 0; k < kt.size(); ++k) {
@@ -431,6 +502,8 @@ void shade_pixel(const std::vector<KTet<R>>& kt, const std::vector<VTet<R>>& vt,
   std::sort(list.begin(), list.end(), [](const Contrib<R>& a, const Contrib<R>& b) {
     return a.zbits != b.zbits ? a.zbits < b.zbits : a.tet_id < b.tet_id;
   });
+  if (log)
+    for (const auto& ct : list) log->push_back({0, ct.hit.alpha, P.alpha_min});
   if (P.window > 0) resort_window(list, P.window, P.alpha_min);
   for (int q = 0; q < 8; ++q) pr.out[q] = R(0);
   R T = R(1);
@@ -441,8 +514,10 @@ void shade_pixel(const std::vector<KTet<R>>& kt, const std::vector<VTet<R>>& vt,
     ct.blended = false;
     ct.clamped = false;
     if (a < R(P.alpha_min)) continue;
+    if (log) log->push_back({1, a, P.alpha_clamp});
     if (a > R(P.alpha_clamp)) { a = R(P.alpha_clamp); ct.clamped = true; }
     R Tn = T * (R(1) - a);
+    if (log) log->push_back({2, Tn, P.t_min});
     if (Tn < R(P.t_min)) break;
     const KTet<R>& t = kt[ct.slot];
     R w = T * a;
@@ -751,6 +826,155 @@ void backward_impl(const Scene<R>& sc, const float* cams, int nv, const Params& 
   for (int i = 0; i < sc.V; ++i) dsdf[i] = val(gs[i]);
 }
 
+// ---------------------------------------------------------------------------
+// Error budget of a float32 backward.  Every gradient element x (the x, y, z
+// of a vertex position, its SDF value, its r, g, b) is a sum of terms, one per
+// (pixel, tet) pair the pixel blended: the pair's screen-space gradient g (the
+// TGrad above) carried to the tet's four vertices by a chain J that is linear
+// in g (projection, mean depth, normal, mean colour).  For these sums:
+//   A[x] = sum over (view, tet) of |J| (sum over pixels of |g|), with |J| the
+//          element-wise absolute chain.  Summing n terms in any order and
+//          grouping moves the result by at most gamma_{n-1} times the sum of
+//          the terms' magnitudes (Higham, Sec. 4.2); carried through J in
+//          absolute value that is gamma times A[x].
+//   E[x] = sum over (view, tet) of |J| (sum over pixels of the running error
+//          bound of g): how far a float32 evaluation of each term, by the
+//          operations written above, can be from its exact value.  A term
+//          that the float32 and float64 walks do not both blend (a threshold
+//          decision that rounding flips) counts with its full magnitude.
+//   N[x] = the number of terms that reach x.
+// Output arrays are [V, 7] (dverts xyz, dsdf, dcolors xyz).
+// ---------------------------------------------------------------------------
+double& tgrad_at(TGrad<double>& g, int k) {
+  if (k < 4) return g.px[k];
+  if (k < 8) return g.py[k - 4];
+  if (k < 12) return g.Z[k - 8];
+  if (k < 16) return g.f[k - 12];
+  if (k < 19) return g.c[k - 16];
+  if (k == 19) return g.zt;
+  return g.n[k - 20];
+}
+template <class R>
+R tgrad_get(const TGrad<R>& g, int k) {
+  if (k < 4) return g.px[k];
+  if (k < 8) return g.py[k - 4];
+  if (k < 12) return g.Z[k - 8];
+  if (k < 16) return g.f[k - 12];
+  if (k < 19) return g.c[k - 16];
+  if (k == 19) return g.zt;
+  return g.n[k - 20];
+}
+constexpr int TGRAD_N = 23;
+
+// J g for one tet in one view, per vertex: (dverts xyz, dsdf, dcolors xyz).
+void chain_term(const KTet<double>& t, const VTet<double>& v, const Cam& c, const TGrad<double>& g,
+                double out[4][7]) {
+  double dv[4][3], nv_[4][3], nf[4];
+  tet_view_backward(t, v, c, g, dv);
+  normal_backward(t, g.n, nv_, nf);
+  for (int a = 0; a < 4; ++a) {
+    for (int j = 0; j < 3; ++j) {
+      out[a][j] = dv[a][j] + nv_[a][j];
+      out[a][4 + j] = g.c[j] * 0.25;
+    }
+    out[a][3] = g.f[a] + nf[a];
+  }
+}
+
+struct BudgetTerm {
+  int slot;
+  TGrad<double> mag, err;  // |g| and the float32 error bound of g, per component
+};
+
+void budget_impl(const double* verts, const int* tets, const double* sdf, const double* colors, int V, int K,
+                 const float* cams, int nv, const Params& P, const int* pix, long npix, const double* dout,
+                 double* A, double* E, double* N) {
+  Inputs<double> in64;
+  Inputs<Rerr> inr;
+  Inputs<float> in32;
+  load_inputs(in64, verts, tets, sdf, colors, V, K);
+  load_inputs(inr, verts, tets, sdf, colors, V, K);
+  load_inputs(in32, verts, tets, sdf, colors, V, K);
+  Prepared<double> p64;
+  Prepared<Rerr> pr;
+  Prepared<float> p32;
+  prepare(in64.sc, cams, nv, P, p64);
+  prepare(inr.sc, cams, nv, P, pr);
+  prepare(in32.sc, cams, nv, P, p32);
+  const size_t nk = p64.kt.size();  // the kept set is a float32 decision: the same in all three
+  std::vector<std::vector<BudgetTerm>> per(npix);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long q = 0; q < npix; ++q) {
+    const int v = pix[3 * q], i = pix[3 * q + 1], j = pix[3 * q + 2];
+    std::vector<std::pair<int, TGrad<Rerr>>> cr;
+    std::vector<std::pair<int, TGrad<float>>> c32;
+    pixel_backward(pr.kt, pr.vt[v], pr.cams[v], P, i, j, dout + 8 * q, cr);
+    pixel_backward(p32.kt, p32.vt[v], p32.cams[v], P, i, j, dout + 8 * q, c32);
+    std::vector<int> slots;
+    for (auto& x : cr) slots.push_back(x.first);
+    for (auto& x : c32) slots.push_back(x.first);
+    std::sort(slots.begin(), slots.end());
+    slots.erase(std::unique(slots.begin(), slots.end()), slots.end());
+    for (int sl : slots) {
+      const TGrad<Rerr>* gr = nullptr;
+      const TGrad<float>* g32 = nullptr;
+      for (auto& x : cr)
+        if (x.first == sl) gr = &x.second;
+      for (auto& x : c32)
+        if (x.first == sl) g32 = &x.second;
+      BudgetTerm t;
+      t.slot = sl;
+      for (int k = 0; k < TGRAD_N; ++k) {
+        const double m = gr ? std::fabs(tgrad_get(*gr, k).v) : 0.0;
+        const double m32 = g32 ? std::fabs((double)tgrad_get(*g32, k)) : 0.0;
+        tgrad_at(t.mag, k) = std::max(m, m32);
+        // blended by both walks: the running bound; by one only: the whole term
+        tgrad_at(t.err, k) = (gr && g32) ? tgrad_get(*gr, k).e : (gr ? m + tgrad_get(*gr, k).e : m32);
+      }
+      per[q].push_back(t);
+    }
+  }
+  std::fill(A, A + 7 * (size_t)V, 0.0);
+  std::fill(E, E + 7 * (size_t)V, 0.0);
+  std::fill(N, N + 7 * (size_t)V, 0.0);
+  std::vector<TGrad<double>> mag(nk * (size_t)nv), err(nk * (size_t)nv);
+  for (auto& g : mag) g.zero();
+  for (auto& g : err) g.zero();
+  std::vector<long> cnt(nk * (size_t)nv, 0);
+  for (long q = 0; q < npix; ++q) {
+    const int v = pix[3 * q];
+    for (const BudgetTerm& t : per[q]) {
+      const size_t r = (size_t)v * nk + t.slot;
+      mag[r].add(t.mag);
+      err[r].add(t.err);
+      ++cnt[r];
+    }
+  }
+  for (int v = 0; v < nv; ++v)
+    for (size_t k = 0; k < nk; ++k) {
+      const size_t r = (size_t)v * nk + k;
+      if (cnt[r] == 0) continue;
+      const KTet<double>& t = p64.kt[k];
+      for (int c = 0; c < TGRAD_N; ++c) {
+        const double m = tgrad_at(mag[r], c), e = tgrad_at(err[r], c);
+        if (m == 0.0 && e == 0.0) continue;
+        TGrad<double> one;
+        one.zero();
+        tgrad_at(one, c) = 1.0;
+        double col[4][7];
+        chain_term(t, p64.vt[v][k], p64.cams[v], one, col);
+        for (int a = 0; a < 4; ++a)
+          for (int q = 0; q < 7; ++q) {
+            if (col[a][q] == 0.0) continue;  // (an infinite bound times a zero chain entry adds nothing)
+            A[7 * (size_t)t.vi[a] + q] += std::fabs(col[a][q]) * m;
+            E[7 * (size_t)t.vi[a] + q] += std::fabs(col[a][q]) * e;
+          }
+      }
+      for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 7; ++q) N[7 * (size_t)t.vi[a] + q] += (double)cnt[r];
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -787,6 +1011,25 @@ int oracle_render(int prec, const double* verts, const int* tets, const double* 
   return 0;
 }
 
+// Running error bound of the forward: out = float64 value, bound = first-order
+// bound on a float32 evaluation's distance from it (per channel).
+int oracle_render_errbound(const double* verts, const int* tets, const double* sdf, const double* colors, int V,
+                           int K, const float* cams, int nv, const float* params, const int* pix, long npix,
+                           double* out, double* bound) {
+  Params P = load_params(params);
+  Inputs<Rerr> in;
+  load_inputs(in, verts, tets, sdf, colors, V, K);
+  render_impl(in.sc, cams, nv, P, pix, npix, out, bound, nullptr, nullptr);
+  return 0;
+}
+
+// Eq. 1 (stable form) with its running error bound.
+double oracle_alpha_errbound(double fprev, double fnext, double s, double* bound) {
+  Rerr a = alpha_eq1<Rerr>(Rerr(fprev), Rerr(fnext), Rerr(s));
+  *bound = a.e;
+  return a.v;
+}
+
 // Forward-mode derivative: out = value, tout = directional derivative along
 // (tverts, tsdf, tcolors).  Any tangent pointer may be null.
 int oracle_render_dual(const double* verts, const int* tets, const double* sdf, const double* colors, int V,
@@ -814,6 +1057,16 @@ int oracle_backward(int prec, const double* verts, const int* tets, const double
   } else {
     return -1;
   }
+  return 0;
+}
+
+// Error budget of a float32 backward for the upstream gradient dout (see
+// budget_impl): A, E, N are float64 [V, 7] = (dverts xyz, dsdf, dcolors xyz).
+int oracle_backward_budget(const double* verts, const int* tets, const double* sdf, const double* colors, int V,
+                           int K, const float* cams, int nv, const float* params, const int* pix, long npix,
+                           const double* dout, double* A, double* E, double* N) {
+  Params P = load_params(params);
+  budget_impl(verts, tets, sdf, colors, V, K, cams, nv, P, pix, npix, dout, A, E, N);
   return 0;
 }
 
@@ -933,6 +1186,32 @@ int oracle_pixel_trace(int prec, const double* verts, const int* tets, const dou
   if (prec == 32) return run(0.0f);
   if (prec == 64) return run(0.0);
   return -1;
+}
+
+// Threshold decisions of one pixel's walk (the skip, clamp and stop tests of
+// every candidate it reaches, the one that stops it included), each with the
+// float64 value decided on and its running error bound (how far a float32
+// evaluation of the same operations can be from it).  Returns the number of
+// decisions; writes at most cap.
+int oracle_pixel_decisions(const double* verts, const int* tets, const double* sdf, const double* colors, int V,
+                           int K, const float* cams, int nv, const float* params, int view, int i, int j, int cap,
+                           int* kind, double* value, double* bound, double* threshold) {
+  Params P = load_params(params);
+  Inputs<Rerr> in;
+  load_inputs(in, verts, tets, sdf, colors, V, K);
+  Prepared<Rerr> pp;
+  prepare(in.sc, cams, nv, P, pp);
+  PixelResult<Rerr> pr;
+  std::vector<Decision<Rerr>> log;
+  shade_pixel(pp.kt, pp.vt[view], pp.cams[view], P, i, j, pr, false, &log);
+  int n = (int)log.size();
+  for (int q = 0; q < n && q < cap; ++q) {
+    kind[q] = log[q].kind;
+    value[q] = log[q].value.v;
+    bound[q] = log[q].value.e;
+    threshold[q] = log[q].threshold;
+  }
+  return n;
 }
 
 // One tet against one pixel centre from already-projected data:

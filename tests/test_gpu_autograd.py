@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import check_gradient, oracle_params
+from tests.gpu_helpers import check_gradients, oracle_gradients, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -43,10 +43,8 @@ def test_autograd_matches_oracle_gradient_tiny():
     pix = oracle.all_pixels(w.cams)
     g = oracle.Geometry.of(sc)
     d = wts[0].reshape(8, -1).T.astype(np.float64)
-    ref32 = oracle.backward(g, w.cams, oracle_params(P, 20.0), pix, d, prec=32)
-    ref64 = oracle.backward(g, w.cams, oracle_params(P, 20.0), pix, d, prec=64)
-    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
-        check_gradient(name, got, r32, r64, "autograd tiny")
+    refs = oracle_gradients(g, w.cams, oracle_params(P, 20.0), pix, d)
+    check_gradients((dv, ds, dc), refs, "autograd tiny")
 
 
 def test_autograd_central_differences_training():

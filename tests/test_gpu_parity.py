@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import (IMG_TOL, check_gradient, compare_images, gpu_forward, gpu_tiling,
+from tests.gpu_helpers import (IMG_TOL, check_gradients, oracle_gradients, compare_images, gpu_forward, gpu_tiling,
                                oracle_params)
 
 pytestmark = pytest.mark.gpu
@@ -82,11 +82,13 @@ def test_tile_shape_does_not_change_image(tile):
 @pytest.mark.parametrize("recompute", [False, True])
 @pytest.mark.parametrize("s", [20.0, 100.0])
 @pytest.mark.parametrize("mode", ["exact", "default"])
-def test_tiny_gradients(mode, s, recompute):
+@pytest.mark.parametrize("tile", TILES)
+def test_tiny_gradients(tile, mode, s, recompute):
+    """Every tile shape the autotuner may pick (8x8 with four waves per tile)."""
     import torch
     w = synth.tiny(s=s, bg=(0.3, 0.1, 0.2))
     sc = w.scenes[0]
-    P = _params(mode, recompute_state=recompute)
+    P = _params(mode, tile, recompute_state=recompute)
     r, plan, _ = gpu_forward(sc, w.cams, P)
     rng = np.random.default_rng(5)
     dout = rng.normal(size=(8, 64, 64)).astype(np.float32)
@@ -96,10 +98,8 @@ def test_tiny_gradients(mode, s, recompute):
     op = oracle_params(P, s)
     pix = oracle.all_pixels(w.cams)
     dflat = dout.reshape(8, -1).T.copy()
-    ref32 = oracle.backward(g, w.cams, op, pix, dflat, prec=32)
-    ref64 = oracle.backward(g, w.cams, op, pix, dflat, prec=64)
-    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
-        check_gradient(name, got.cpu().numpy(), r32, r64, f"tiny {mode} s={s} recompute={recompute}")
+    refs = oracle_gradients(g, w.cams, op, pix, dflat)
+    check_gradients((dv, ds, dc), refs, f"tiny {tile} {mode} s={s} recompute={recompute}")
 
 
 def test_recompute_state_matches_stored_state():
@@ -157,10 +157,8 @@ def test_scenes_of_uneven_size_in_one_launch():
         pix = oracle.all_pixels(cams[sel])
         dflat = np.concatenate([douts[v].cpu().numpy().reshape(8, -1).T for v in sel], 0)
         gg = oracle.Geometry.of(sc)
-        ref32 = oracle.backward(gg, cams[sel], oracle_params(P, 320.0), pix, dflat, prec=32)
-        ref64 = oracle.backward(gg, cams[sel], oracle_params(P, 320.0), pix, dflat, prec=64)
-        for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads[si], ref32, ref64):
-            check_gradient(name, got.cpu().numpy(), r32, r64, f"multi-scene scene {si}")
+        refs = oracle_gradients(gg, cams[sel], oracle_params(P, 320.0), pix, dflat)
+        check_gradients(grads[si], refs, f"multi-scene scene {si}")
 
 
 # ---------------------------------------------------------------------------
@@ -208,24 +206,24 @@ def test_vertex_gradients_without_shared_vertices():
         op = oracle_params(P, s)
         pix = oracle.all_pixels(cam)
         dflat = dout.reshape(8, -1).T.copy()
-        ref32 = oracle.backward(g, cam, op, pix, dflat, prec=32)
-        ref64 = oracle.backward(g, cam, op, pix, dflat, prec=64)
-        for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
-            check_gradient(name, got.cpu().numpy(), r32, r64, f"tet soup tile {P.tile_w}x{P.tile_h}")
+        refs = oracle_gradients(g, cam, op, pix, dflat)
+        check_gradients((dv, ds, dc), refs, f"tet soup tile {P.tile_w}x{P.tile_h}")
 
 
 @pytest.mark.parametrize("recompute", [False, True])
 @pytest.mark.parametrize("size", [(50, 37), (130, 9)])
-def test_ragged_image_gradients_multiwave(size, recompute):
-    """Partial 8x8 tiles at the right and bottom edges through the multi-wave
-    backward (including the tiles nothing reaches), against the oracle."""
+@pytest.mark.parametrize("tile", TILES)
+def test_ragged_image_gradients(tile, size, recompute):
+    """Partial tiles at the right and bottom edges (including the tiles
+    nothing reaches) through the backward of every tile shape, against the
+    oracle."""
     import torch
     s = 100.0
     w = synth.tiny(s=s, bg=(0.2, 0.5, 0.1))
     Wd, Hd = size
     cam = synth.orbit_camera(0.7, 0.35, 2.5, 50.0, Wd, Hd, bg=(0.2, 0.5, 0.1))[None]
     cam[0, 17] = Hd / 2.0
-    P = _params("default", (8, 8), waves=4, recompute_state=recompute)
+    P = _params("default", tile, recompute_state=recompute)
     r, plan, _ = gpu_forward(w.scenes[0], cam, P)
     dout = np.random.default_rng(21).normal(size=(8, Hd, Wd)).astype(np.float32)
     (dv, ds, dc), = r.backward(plan, [torch.from_numpy(dout).cuda()])
@@ -234,10 +232,8 @@ def test_ragged_image_gradients_multiwave(size, recompute):
     op = oracle_params(P, s)
     pix = oracle.all_pixels(cam)
     dflat = np.stack([dout[:, j, i] for (_, i, j) in pix], 0).astype(np.float32)
-    ref32 = oracle.backward(g, cam, op, pix, dflat, prec=32)
-    ref64 = oracle.backward(g, cam, op, pix, dflat, prec=64)
-    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
-        check_gradient(name, got.cpu().numpy(), r32, r64, f"ragged {size} recompute={recompute}")
+    refs = oracle_gradients(g, cam, op, pix, dflat)
+    check_gradients((dv, ds, dc), refs, f"ragged {tile} {size} recompute={recompute}")
 
 
 def test_empty_scene_and_culled_views():
@@ -316,9 +312,10 @@ def training():
     return w, oracle.Geometry.of(w.scenes[0])
 
 
-def test_training_tiling_bit_exact(training):
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_training_tiling_bit_exact(training, tile):
     w, g = training
-    P = _params("default")
+    P = _params("default", tile)
     r, plan, _ = gpu_forward(w.scenes[0], w.cams, P)
     d, tets = gpu_tiling(r, plan)
     op = oracle_params(P, 320.0)
@@ -340,7 +337,7 @@ def test_training_tiling_bit_exact(training):
         m_ref = ~np.isin(ref["tet"], diff)
         assert np.array_equal(d["tile_keys"][m_gpu], ref["tile"][m_ref].astype(np.uint32))
         assert np.array_equal(tets[m_gpu], ref["tet"][m_ref])
-    print(f"training tiling: E={d['entries']}, kept={d['kept']}, kept-set differences {diff.size}")
+    print(f"training tiling {tile}: E={d['entries']}, kept={d['kept']}, kept-set differences {diff.size}")
 
 
 def _sample_pixels(w, n, seed):
@@ -392,10 +389,8 @@ def test_training_gradients_of_sparse_upstream(training):
     grads, = r.backward(plan, [torch.from_numpy(d).cuda() for d in douts])
     torch.cuda.synchronize()
     op = oracle_params(P, 320.0)
-    ref32 = oracle.backward(g, w.cams, op, upix, dflat, prec=32)
-    ref64 = oracle.backward(g, w.cams, op, upix, dflat, prec=64)
-    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads, ref32, ref64):
-        check_gradient(name, got.cpu().numpy(), r32, r64, "training sparse-upstream")
+    refs = oracle_gradients(g, w.cams, op, upix, dflat)
+    check_gradients(grads, refs, "training sparse-upstream")
 
 
 @pytest.mark.parametrize("waves", [1, 2, 4, 8])
@@ -416,3 +411,40 @@ def test_waves_per_tile_do_not_change_results(waves):
         assert np.array_equal(img, ref_img)
         for a, b in zip(grads, ref_g):
             np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * np.abs(b).max())
+
+
+# ---------------------------------------------------------------------------
+# the training-shaped workload in the launch configuration the benchmark
+# times (8x8 tiles, four waves per tile): every pixel of all four views, and
+# the gradient of a dense upstream gradient on every pixel
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["exact", "default"])
+def test_training_full_images_timed_shape(training, mode):
+    w, g = training
+    P = _params(mode, (8, 8), waves=4)
+    _, _, imgs = gpu_forward(w.scenes[0], w.cams, P)
+    op = oracle_params(P, 320.0)
+    err, n_ex, n = compare_images(imgs, g, w.cams, op, 320.0)
+    pix = _sample_pixels(w, 20000, 12)
+    got = np.stack([imgs[v][:, j, i] for (v, i, j) in pix], 0)
+    e64 = np.abs(got - oracle.render(g, w.cams, op, pix, prec=64)).max(0)
+    print(f"training 8x8/4 waves {mode}: all {n} pixels max-abs vs f32 {err:.3e} (excluded {n_ex}); "
+          f"vs f64 per channel (20000 sampled) {e64}")
+    assert n == 4 * 512 * 512
+    assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n))
+
+
+def test_training_gradients_dense_upstream_timed_shape(training):
+    import torch
+    w, g = training
+    P = _params("default", (8, 8), waves=4)
+    r, plan, _ = gpu_forward(w.scenes[0], w.cams, P)
+    douts = np.random.default_rng(13).normal(size=(4, 8, 512, 512)).astype(np.float32)
+    grads, = r.backward(plan, [torch.from_numpy(d).cuda() for d in douts])
+    torch.cuda.synchronize()
+    pix = oracle.all_pixels(w.cams)
+    dflat = douts.transpose(0, 2, 3, 1).reshape(-1, 8).astype(np.float64)
+    # all_pixels lists each view row by row (j outer, i inner): the same order
+    assert np.array_equal(pix[:3, 1], [0, 1, 2]) and pix[512, 2] == 1
+    refs = oracle_gradients(g, w.cams, oracle_params(P, 320.0), pix, dflat)
+    check_gradients(grads, refs, "training 8x8/4 waves dense upstream")

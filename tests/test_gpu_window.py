@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import IMG_TOL, check_gradient, compare_images, gpu_forward, oracle_params
+from tests.gpu_helpers import IMG_TOL, check_gradients, oracle_gradients, compare_images, gpu_forward, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -71,10 +71,8 @@ def test_tiny_window_gradients(mode, s, window):
     op = oracle_params(P, s)
     pix = oracle.all_pixels(w.cams)
     dflat = dout.reshape(8, -1).T.copy()
-    ref32 = oracle.backward(g, w.cams, op, pix, dflat, prec=32)
-    ref64 = oracle.backward(g, w.cams, op, pix, dflat, prec=64)
-    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), (dv, ds, dc), ref32, ref64):
-        check_gradient(name, got.cpu().numpy(), r32, r64, f"window {window} {mode} s={s}")
+    refs = oracle_gradients(g, w.cams, op, pix, dflat)
+    check_gradients((dv, ds, dc), refs, f"window {window} {mode} s={s}")
 
 
 @pytest.mark.parametrize("waves", [1, 2, 8])
@@ -198,10 +196,8 @@ def test_training_window_gradients_of_sparse_upstream(training):
     grads, = r.backward(plan, [torch.from_numpy(d).cuda() for d in douts])
     torch.cuda.synchronize()
     op = oracle_params(P, 320.0)
-    ref32 = oracle.backward(g, w.cams, op, upix, dflat, prec=32)
-    ref64 = oracle.backward(g, w.cams, op, upix, dflat, prec=64)
-    for name, got, r32, r64 in zip(("dverts", "dsdf", "dcolors"), grads, ref32, ref64):
-        check_gradient(name, got.cpu().numpy(), r32, r64, "training window 5 sparse-upstream")
+    refs = oracle_gradients(g, w.cams, op, upix, dflat)
+    check_gradients(grads, refs, "training window 5 sparse-upstream")
 
 
 # ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import IMG_TOL, check_gradient, compare_images, oracle_params
+from tests.gpu_helpers import IMG_TOL, check_gradients, oracle_gradients, compare_images, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -111,10 +111,8 @@ def _sparse_backward(w, r, plan, imgs, scenes, P, seed, label):
         views, local, vals = per_scene[s_idx]
         g = oracle.Geometry.of(w.scenes[s_idx])
         op = oracle_params(P, w.scenes[s_idx].s)
-        ref32 = oracle.backward(g, w.cams[views], op, local, vals, prec=32)
-        ref64 = oracle.backward(g, w.cams[views], op, local, vals, prec=64)
-        for name, a, r32, r64 in zip(("dverts", "dsdf", "dcolors"), got, ref32, ref64):
-            check_gradient(name, a, r32, r64, f"{label} scene {s_idx}")
+        refs = oracle_gradients(g, w.cams[views], op, local, vals)
+        check_gradients(got, refs, f"{label} scene {s_idx}")
 
 
 def test_batched_gradients_of_sparse_upstream(batched):

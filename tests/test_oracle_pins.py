@@ -478,3 +478,133 @@ def test_float32_oracle_close_to_float64(oracle_lib):
     a = oracle.render_images(g, w.cams, P, prec=32)[0]
     b = oracle.render_images(g, w.cams, P, prec=64)[0]
     assert np.abs(a - b).max() < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# error budget of a float32 backward (the element-wise gradient bound of the
+# GPU tests is built from it)
+# ---------------------------------------------------------------------------
+def _gamma(n):
+    u = 2.0 ** -24
+    return n * u / (1.0 - n * u)
+
+
+def test_alpha_running_error_bound(oracle_lib):
+    """The running error bound of Eq. 1 covers the float32 evaluation's actual
+    error on random float32 inputs, and is not vacuous."""
+    rng = np.random.default_rng(51)
+    worst, rel = 0.0, []
+    for s in (20.0, 320.0, 2000.0):
+        fp = rng.uniform(-0.05, 0.05, 4000).astype(np.float32)
+        fn = (fp - rng.uniform(0.0, 0.03, 4000)).astype(np.float32)
+        for a_, b_ in zip(fp, fn):
+            v, e = oracle.alpha_error_bound(a_, b_, s)
+            err = abs(oracle.alpha_f32(a_, b_, s) - v)
+            assert err <= e, (a_, b_, s, err, e)
+            if v > 1e-3:
+                rel.append(e / v)
+    assert np.median(rel) < 1e-4
+
+
+@pytest.mark.parametrize("s", [20.0, 100.0])
+def test_forward_running_error_bound(oracle_lib, s):
+    """Every channel of every pixel of the float32 oracle lies within the
+    running error bound of the float64 value (exact mode: the walks blend the
+    same tets except where float32 T reaches exactly 0)."""
+    w = synth.tiny(s=s, bg=(0.3, 0.1, 0.2))
+    g = oracle.Geometry.of(w.scenes[0])
+    P = oracle.params_array(s, **EXACT)
+    pix = oracle.all_pixels(w.cams)
+    v, e = oracle.render_error_bound(g, w.cams, P, pix)
+    assert np.array_equal(v, oracle.render(g, w.cams, P, pix, prec=64))
+    r32, nb32, _ = oracle.render(g, w.cams, P, pix, prec=32, want_state=True)
+    _, nb64, _ = oracle.render(g, w.cams, P, pix, prec=64, want_state=True)
+    same = nb32 == nb64
+    assert same.mean() > 0.9
+    assert np.all(np.abs(r32 - v)[same] <= e[same])
+    covered = v[:, 3] > 0.1
+    assert np.median(e[covered & same, 0]) < 1e-3   # a few hundred units of u on O(1) colours
+
+
+@pytest.mark.parametrize("s", [20.0, 100.0])
+@pytest.mark.parametrize("mode", ["exact", "default"])
+def test_backward_budget(oracle_lib, mode, s):
+    """The float32 oracle's own error obeys its budget element by element; A
+    bounds the float64 gradient (triangle inequality); an element no term
+    reaches is exactly zero.  The colour part of A and N is recomputed from
+    per-pixel traces (a colour term is 0.25 T alpha dL/dRGB per vertex of the
+    blended tet), and its E is at least the float32 oracle's actual error in
+    those terms, fl(fl(T a) g) against T a g."""
+    w = synth.tiny(s=s, bg=(0.3, 0.1, 0.2))
+    g = oracle.Geometry.of(w.scenes[0])
+    P = oracle.params_array(s, **(EXACT if mode == "exact" else {}))
+    allpix = oracle.all_pixels(w.cams)
+    rng = np.random.default_rng(41)
+    pix = allpix[rng.choice(allpix.shape[0], 300, replace=False)]
+    dout = rng.normal(size=(pix.shape[0], 8)).astype(np.float32).astype(np.float64)
+    r32 = oracle.backward(g, w.cams, P, pix, dout, prec=32)
+    r64 = oracle.backward(g, w.cams, P, pix, dout, prec=64)
+    b = oracle.backward_budget(g, w.cams, P, pix, dout)
+    for k in range(3):
+        A, E, N = b["A"][k], b["E"][k], b["N"][k]
+        err = np.abs(r32[k] - r64[k])
+        assert np.all(err <= E + _gamma(N + 32) * A), k
+        assert np.all(np.abs(r64[k]) <= A * (1 + 1e-12)), k
+        none = N == 0
+        assert np.all(A[none] == 0) and np.all(E[none] == 0)
+        assert np.all(r32[k][none] == 0) and np.all(r64[k][none] == 0)
+    # colour part from traces
+    Ac = np.zeros((g.V, 3))
+    Ec = np.zeros((g.V, 3))
+    Nc = np.zeros(g.V)
+    for (v, i, j), d in zip(pix, dout):
+        t64 = oracle.pixel_trace(g, w.cams, P, int(v), int(i), int(j), prec=64)
+        t32 = oracle.pixel_trace(g, w.cams, P, int(v), int(i), int(j), prec=32)
+        # the precisions may blend different lists (in exact mode float32 alpha
+        # can round to 1 and end the walk): a term of one list only counts in full
+        w64 = {int(t): T * a for t, T, a in zip(t64["tet"], t64["T"], t64["alpha"])}
+        w32 = {int(t): np.float32(np.float32(T) * np.float32(a)) for t, T, a in zip(t32["tet"], t32["T"], t32["alpha"])}
+        for tet in set(w64) | set(w32):
+            g32 = (w32[tet] * d[:3].astype(np.float32)).astype(np.float64) if tet in w32 else np.zeros(3)
+            g64 = w64[tet] * d[:3] if tet in w64 else np.zeros(3)
+            for vi in g.tets[tet]:
+                Ac[vi] += 0.25 * np.maximum(np.abs(g32), np.abs(g64))
+                Ec[vi] += 0.25 * np.abs(g32 - g64)
+                Nc[vi] += 1
+    np.testing.assert_allclose(b["A"][2], Ac, rtol=1e-12, atol=0)
+    assert np.all(b["E"][2] >= Ec)
+    assert np.array_equal(b["N"][2][:, 0], Nc)
+    assert Nc.max() > 1 and np.count_nonzero(Ec) > 0
+
+
+def test_pixel_decisions_follow_the_walk(oracle_lib):
+    """The decision log of a pixel lists every candidate's skip test, then per
+    blended tet its clamp and stop tests (the stopping tet's stop test last);
+    its float64 values are the walk's own and the float32 walk's values lie
+    within their running bounds."""
+    w = synth.tiny(s=100.0)
+    g = oracle.Geometry.of(w.scenes[0])
+    P = oracle.params_array(100.0)
+    out = oracle.render(g, w.cams, P)
+    pix = oracle.all_pixels(w.cams)
+    hot = pix[out[:, 3] > 0.05]
+    rng = np.random.default_rng(61)
+    stopped = 0
+    for (v, i, j) in hot[rng.choice(hot.shape[0], 150, replace=False)]:
+        d = oracle.pixel_decisions(g, w.cams, P, v, i, j)
+        t64 = oracle.pixel_trace(g, w.cams, P, v, i, j, prec=64)
+        t32 = oracle.pixel_trace(g, w.cams, P, v, i, j, prec=32)
+        nb = len(t64["tet"])
+        k = d["kind"]
+        n0 = int(np.sum(k == 0))
+        assert np.all(k[:n0] == 0) and np.all(k[n0:][0::2] == 1) and np.all(k[n0:][1::2] == 2)
+        assert n0 >= nb and np.sum(k == 2) in (nb, nb + 1)
+        stopped += int(np.sum(k == 2) == nb + 1)
+        a_cl = d["value"][n0:][0::2][:nb]
+        assert np.array_equal(a_cl, t64["alpha_raw"])
+        # T (1 - alpha) of a blended tet is the next tet's T
+        tn = d["value"][n0:][1::2][:nb - 1]
+        assert np.allclose(tn, t64["T"][1:], rtol=1e-15, atol=0)
+        if np.array_equal(t32["tet"], t64["tet"]):
+            assert np.all(np.abs(t32["alpha_raw"] - a_cl) <= d["bound"][n0:][0::2][:nb])
+    assert stopped > 0
