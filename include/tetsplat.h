@@ -164,6 +164,32 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
 int render_read_status(const void* workspace, render_status* status, void* stream);
 
 /*
+ * render_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same forward, with the library's own static device workspace of
+ * RENDER_STATIC_WORKSPACE_BYTES in place of a caller buffer.  The caller
+ * still passes inputs and outputs (views[v].out).  The call allocates
+ * nothing: the workspace is a file-scope device array that each GPU the
+ * library runs on holds until the process ends; its address is looked up
+ * once per device on the first call made with that device current.
+ *   - A problem whose workspace (render_workspace_size with the same
+ *     arguments) exceeds RENDER_STATIC_WORKSPACE_BYTES returns RENDER_ENOSPC
+ *     before anything is launched.
+ *   - header_copy (optional, may be NULL): device or pinned host memory of
+ *     RENDER_STATUS_BYTES; the status header is copied there asynchronously
+ *     on the stream after the forward (decode it with render_decode_status
+ *     once the stream has reached it).
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (the forward initialises everything it reads): calls
+ *     that overlap on one GPU race, and render_backward cannot follow this
+ *     call (it needs the caller's workspace).
+ */
+#define RENDER_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int render_forward_static(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                          const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                          void* header_copy, void* stream);
+
+/*
  * For callers that do not want a synchronisation after every forward: copy
  * the first RENDER_STATUS_BYTES bytes of the workspace to host memory
  * asynchronously (e.g. into pinned memory on the same stream), wait for that

@@ -60,7 +60,9 @@ EXPORTS = ("render_workspace_size", "render_forward", "render_backward", "render
            "render_debug_pointers", "render_last_error", "render_profile", "render_profile_read",
            "render_decode_status", "render_mesh_edges_workspace_size", "render_mesh_edges",
            "render_regularizers_workspace_size", "render_regularizers", "render_marching_tets_workspace_size",
-           "render_marching_tets", "render_prefilter_bounds", "render_cube_grid", "render_refit_cube")
+           "render_marching_tets", "render_prefilter_bounds", "render_cube_grid", "render_refit_cube",
+           "render_forward_static")
+STATIC_WORKSPACE_BYTES = 64 << 20
 STATUS_BYTES = 256
 
 STAGES = ("upload", "prefilter", "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "composite",
@@ -78,6 +80,7 @@ def lib():
         P, I, I64 = C.c_void_p, C.c_int, C.c_int64
         L.render_workspace_size.argtypes = [P, I, P, I, P, I64, I64, C.POINTER(C.c_size_t)]
         L.render_forward.argtypes = [P, I, P, I, P, I64, I64, P, C.c_size_t, P]
+        L.render_forward_static.argtypes = [P, I, P, I, P, I64, I64, P, P]
         L.render_backward.argtypes = [P, I, P, I, P, I64, I64, P, C.c_size_t, P, P, P]
         L.render_read_status.argtypes = [P, P, P]
         L.render_debug_pointers.argtypes = [P, I, P, I, P, I64, I64, P, P]

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -274,6 +275,31 @@ render_params with_waves(render_params p) {
     }                                                                 \
   } while (0)
 
+// The workspace of render_forward_static: one copy per device, reached only
+// through the address hipGetSymbolAddress returns for the current device (the
+// array's name is a host-side stand-in in host code).
+__device__ __align__(256) unsigned char scratch[RENDER_STATIC_WORKSPACE_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int static_workspace(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "get device");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RENDER_EINVAL, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "static workspace address");
+    if (!p) return fail(RENDER_EHIP, "static workspace address is null");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RENDER_OK;
+}
+
 }  // namespace
 }  // namespace ts
 
@@ -479,6 +505,32 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
                                 : launch_composite_backward(workspace, L, *params, st),
            "composite backward");
   TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
+  return RENDER_OK;
+}
+
+int render_forward_static(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
+                          const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
+                          void* header_copy, void* stream) {
+  int rc = check_args(scenes, n_scenes, views, n_views, params);
+  if (rc) return rc;
+  Layout L;
+  const char* why = nullptr;
+  if (!plan_layout(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, L, &why))
+    return fail(RENDER_EINVAL, "%s", why);
+  if (L.bytes > RENDER_STATIC_WORKSPACE_BYTES)
+    return fail(RENDER_ENOSPC, "the problem needs a %zu-byte workspace; the static workspace holds %zu", L.bytes,
+                (size_t)RENDER_STATIC_WORKSPACE_BYTES);
+  void* ws = nullptr;
+  rc = static_workspace(&ws);
+  if (rc) return rc;
+  rc = render_forward(scenes, n_scenes, views, n_views, params, kept_capacity, entry_capacity, ws,
+                      RENDER_STATIC_WORKSPACE_BYTES, stream);
+  if (rc) return rc;
+  if (header_copy) {
+    hipError_t e = hipMemcpyAsync(header_copy, ws, RENDER_STATUS_BYTES, hipMemcpyDefault,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "status header copy");
+  }
   return RENDER_OK;
 }
 

@@ -153,6 +153,26 @@ def test_bad_arguments_rejected_before_device_work(L):
                                None) == L.RENDER_EINVAL
 
 
+def test_static_forward_rejects_a_problem_past_its_workspace(L):
+    """The no-allocation forward checks its size on the host, before any
+    device work: a problem whose workspace exceeds the static array is
+    refused with RENDER_ENOSPC; bad arguments as render_forward."""
+    lib = L.lib()
+    w = synth.training(s=320.0, R=8, size=64, views=1)
+    scenes, views, p = _args(L, w)
+    assert lib.render_forward_static(None, 1, C.byref(views), 1, C.byref(p), 0, 0, None, None) == L.RENDER_EINVAL
+    # 8 views at 4096^2 of the same scene: far past 64 MiB
+    big = (L.render_view * 8)()
+    for v in range(8):
+        C.memmove(C.byref(big[v]), C.byref(views[0]), C.sizeof(L.render_view))
+        big[v].width = big[v].height = 4096
+    rc, need = _size(L, scenes, big, p)
+    assert rc == 0 and need > L.STATIC_WORKSPACE_BYTES
+    assert lib.render_forward_static(C.byref(scenes), 1, C.byref(big), 8, C.byref(p), 0, 0, None,
+                                     None) == L.RENDER_ENOSPC
+    assert b"static workspace" in lib.render_last_error()
+
+
 def test_decode_status_roundtrip(L):
     hdr = np.zeros(64, np.uint32)
     hdr[0], hdr[1], hdr[2], hdr[3], hdr[4] = 11, 22, 33, 2, 0
