@@ -58,11 +58,22 @@ enum {
 
 /* render_params.flags */
 enum {
-  RENDER_RECOMPUTE_STATE = 1, /* backward recomputes each pixel's last contributor and
-                                 transmittance by a forward sweep instead of reading them */
-  RENDER_VALIDATE = 2         /* accepted for compatibility: tet indices are always checked
+  RENDER_RECOMPUTE_STATE = 1, /* the workspace keeps no per-pixel compositing state (8 B per
+                                 pixel less: each pixel's last blended entry and the
+                                 transmittance before it); the backward recomputes it by a
+                                 forward sweep over the tile */
+  RENDER_VALIDATE = 2,        /* accepted for compatibility: tet indices are always checked
                                  against [0, V) on the device; a tet with an index outside it is
                                  dropped and counted in render_status.invalid_index */
+  RENDER_DETERMINISTIC = 4,   /* bitwise-reproducible gradients: every sum runs in a fixed order
+                                 (an entry's pixel groups in group order; a vertex's per-tet terms
+                                 in kept-tet order, after a stable sort of the kept tets' corners
+                                 by vertex).  Slower; needs 4 x 48 B more workspace per kept tet.
+                                 Not with RENDER_RECORD_GRADS */
+  RENDER_RECORD_GRADS = 8     /* the compositing backward adds each tile's gradient of a record
+                                 into one 96 B accumulator per (view, kept tet) record (float
+                                 atomics) instead of storing 96 B per (record, tile) entry: a
+                                 smaller workspace, gradients reproducible to rounding only */
 };
 
 typedef struct {
@@ -152,8 +163,10 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
  * views, params and capacities, inputs unchanged), overwrites grads[s] for
  * every scene s.  Gradients flow through Eq. 1, the barycentric and
  * perspective interpolation, the projection, the normal and the colour mean;
- * clamped, skipped and unreached tets contribute zero.  Per-vertex sums use
- * float atomics, so the result is reproducible to rounding, not bitwise.
+ * clamped, skipped and unreached tets contribute zero.  Without
+ * RENDER_DETERMINISTIC, sums over an entry's pixel groups and over a vertex's
+ * tets use float atomics, so the result is reproducible to rounding, not
+ * bitwise; with it, bitwise.
  */
 int render_backward(const render_scene* scenes, int n_scenes, const render_view* views, int n_views,
                      const render_params* params, int64_t kept_capacity, int64_t entry_capacity,
@@ -208,7 +221,7 @@ int render_decode_status(const void* header_copy, render_status* status);
  *                       holds kept slot scene_kept_base[scene] + r - base
  *   scene_kept_base[ns], scene_kept_count[ns]  int32
  *   ranges[tiles][2]    uint32 half-open entry range of each global tile
- *   last[pixels], t_last[pixels]  per-pixel compositing state
+ *   last[pixels], t_last[pixels]  per-pixel compositing state (NULL with RENDER_RECOMPUTE_STATE)
  * Global tile ids concatenate the views' row-major tile grids; pixel ids
  * concatenate the views' row-major pixel grids.
  */

@@ -9,7 +9,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtetsplat.so")
 
 RENDER_OK, RENDER_EINVAL, RENDER_ENOSPC, RENDER_EHIP, RENDER_EOVERFLOW = 0, -1, -2, -3, -4
-RENDER_RECOMPUTE_STATE, RENDER_VALIDATE = 1, 2
+RENDER_RECOMPUTE_STATE, RENDER_VALIDATE, RENDER_DETERMINISTIC, RENDER_RECORD_GRADS = 1, 2, 4, 8
 RENDER_WINDOW_MAX = 8
 
 

@@ -64,7 +64,10 @@ int check_args(const render_scene* scenes, int ns, const render_view* views, int
   if (ns <= 0 || nv <= 0) return fail(RENDER_EINVAL, "need at least one scene and one view (got %d, %d)", ns, nv);
   if (!tile_ok(p->tile_w, p->tile_h))
     return fail(RENDER_EINVAL, "unsupported tile %dx%d (8x8, 16x8, 8x16, 16x16, 32x8)", p->tile_w, p->tile_h);
-  if (p->flags & ~(RENDER_RECOMPUTE_STATE | RENDER_VALIDATE)) return fail(RENDER_EINVAL, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(RENDER_RECOMPUTE_STATE | RENDER_VALIDATE | RENDER_DETERMINISTIC | RENDER_RECORD_GRADS))
+    return fail(RENDER_EINVAL, "unknown flags 0x%x", p->flags);
+  if ((p->flags & RENDER_DETERMINISTIC) && (p->flags & RENDER_RECORD_GRADS))
+    return fail(RENDER_EINVAL, "RENDER_DETERMINISTIC and RENDER_RECORD_GRADS exclude each other");
   if (!(p->alpha_clamp > 0.0f && p->alpha_clamp <= 1.0f)) return fail(RENDER_EINVAL, "alpha_clamp must be in (0, 1]");
   if (!(p->waves == 0 || p->waves == 1 || p->waves == 2 || p->waves == 4 || p->waves == 8))
     return fail(RENDER_EINVAL, "waves must be 0, 1, 2, 4 or 8 (got %d)", p->waves);
@@ -94,7 +97,10 @@ void fill_desc(const render_scene* scenes, int ns, const render_view* views, int
                const Layout& L, std::vector<DevScene>& hs, std::vector<DevView>& hv, std::vector<int32_t>& sv) {
   hs.assign(ns, DevScene{});
   int blk = 0;
+  int64_t vb = 0;
   for (int s = 0; s < ns; ++s) {
+    hs[s].vbase = (int32_t)vb;
+    vb += scenes[s].V;
     DevScene& d = hs[s];
     d.verts = scenes[s].verts;
     d.tets = scenes[s].tets;
@@ -147,9 +153,11 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L = Layout{};
   L.ns = ns;
   L.nv = nv;
-  int64_t sumK = 0, pf_blocks = 0;
+  L.flags = p->flags;
+  int64_t sumK = 0, sumV = 0, pf_blocks = 0;
   for (int s = 0; s < ns; ++s) {
     sumK += scenes[s].K;
+    sumV += scenes[s].V;
     pf_blocks += (scenes[s].K + PF_TILE - 1) / PF_TILE;
   }
   if (kept_cap <= 0 || kept_cap > sumK) kept_cap = sumK;
@@ -165,8 +173,10 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   if (rec_cap < 1) rec_cap = 1;
   if (kept_cap < 1) kept_cap = 1;
   const int64_t lim = (int64_t)1 << 31;
-  if (rec_cap >= lim || entry_cap >= lim || tiles >= lim || pixels >= lim || kept_cap >= lim) {
-    *why = "problem exceeds 2^31 records, entries, tiles or pixels";
+  const bool det = (p->flags & RENDER_DETERMINISTIC) != 0;
+  if (rec_cap >= lim || entry_cap >= lim || tiles >= lim || pixels >= lim || kept_cap >= lim || sumV >= lim ||
+      (det && 4 * kept_cap >= lim)) {
+    *why = "problem exceeds 2^31 records, entries, tiles, pixels, vertices or kept-tet corners";
     return false;
   }
   L.kept_cap = kept_cap;
@@ -174,13 +184,17 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.entry_cap = entry_cap;
   L.pf_blocks = pf_blocks;
   L.scan_blocks_rec = (rec_cap + SCAN_TILE - 1) / SCAN_TILE;
-  const int64_t smax = rec_cap > entry_cap ? rec_cap : entry_cap;
+  int64_t smax = rec_cap > entry_cap ? rec_cap : entry_cap;
+  if (det && 4 * kept_cap > smax) smax = 4 * kept_cap;
   L.sort_blocks_max = (smax + SORT_TILE - 1) / SORT_TILE;
   L.total_tiles = tiles;
   L.total_pixels = pixels;
   int kb = 1;
   while (((int64_t)1 << kb) < tiles) ++kb;
   L.key2_bits = kb;
+  int vbits = 1;
+  while (((int64_t)1 << vbits) < sumV) ++vbits;
+  L.vkey_bits = vbits;
   {
     std::vector<int> vps(ns, 0);
     for (int v = 0; v < nv; ++v) ++vps[views[v].scene];
@@ -222,10 +236,21 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_bwd_hist = take(4 * 2 * (size_t)TILE_BUCKETS);
   L.o_bwd_order = take(sizeof(TileSlot) * (size_t)tiles);
   L.o_bwd_pend = take(4 * (size_t)tiles);
-  L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE * (size_t)entry_cap);
-  L.o_last = take(4 * (size_t)pixels);
-  L.o_tlast = take(4 * (size_t)pixels);
+  // screen-space gradients: one per entry, or one accumulator per record
+  L.o_tgrad = take(4 * (size_t)TGRAD_STRIDE *
+                   (size_t)((p->flags & RENDER_RECORD_GRADS) ? rec_cap : entry_cap));
+  const bool keep_state = (p->flags & RENDER_RECOMPUTE_STATE) == 0;
+  L.o_last = keep_state ? take(4 * (size_t)pixels) : 0;
+  L.o_tlast = keep_state ? take(4 * (size_t)pixels) : 0;
   L.o_wpair = p->window > 0 ? take(16 * 64 * (size_t)entry_cap) : 0;
+  if (det) {
+    const size_t nc = 4 * (size_t)kept_cap;
+    L.o_vkey_a = take(4 * nc);
+    L.o_vkey_b = take(4 * nc);
+    L.o_vval_a = take(4 * nc);
+    L.o_vval_b = take(4 * nc);
+    L.o_vterm = take(32 * nc);
+  }
   L.bytes = o;
   return true;
 }
@@ -505,6 +530,7 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
                                 : launch_composite_backward(workspace, L, *params, st),
            "composite backward");
   TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
+  if (deterministic(L)) TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_gather(workspace, L, st), "vertex gather");
   return RENDER_OK;
 }
 
@@ -586,8 +612,8 @@ int render_debug_pointers(const render_scene* scenes, int n_scenes, const render
   out->scene_kept_base = at<const int32_t>(ws, L.o_scene_kept_base);
   out->scene_kept_count = at<const int32_t>(ws, L.o_scene_kept_count);
   out->ranges = at<const uint32_t>(ws, L.o_ranges);
-  out->last = at<const int32_t>(ws, L.o_last);
-  out->t_last = at<const float>(ws, L.o_tlast);
+  out->last = L.o_last ? at<const int32_t>(ws, L.o_last) : nullptr;   // null: state not kept
+  out->t_last = L.o_tlast ? at<const float>(ws, L.o_tlast) : nullptr;
   out->total_tiles = L.total_tiles;
   out->total_pixels = L.total_pixels;
   return RENDER_OK;

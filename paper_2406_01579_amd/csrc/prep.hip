@@ -751,6 +751,12 @@ __device__ __forceinline__ void zero_grads_body(const DevScene& S, void* ws, con
   for (size_t i = i0; i < words; i += stride) f[i] = 0u;
   uint32_t* bcur = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
   for (size_t i = i0; i < (size_t)TILE_BUCKETS; i += stride) bcur[i] = 0u;
+  if (record_grads(L)) {
+    // the records' gradient accumulators
+    float4* acc = at<float4>(ws, L.o_tgrad);
+    const size_t n4 = (size_t)min(hdr->records_total, (uint32_t)L.rec_cap) * (TGRAD_STRIDE / 4);
+    for (size_t i = i0; i < n4; i += stride) acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
 }
 
 __global__ void k_zero_grads(void* ws, Layout L) {

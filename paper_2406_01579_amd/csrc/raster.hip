@@ -154,9 +154,11 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
     out[5 * plane + px] = acc[4];
     out[6 * plane + px] = acc[5];
     out[7 * plane + px] = acc[6];
-    const size_t g = (size_t)V.pix_base + px;
-    last_out[g] = last;
-    tlast_out[g] = Tb;
+    if (keeps_pixel_state(L)) {
+      const size_t g = (size_t)V.pix_base + px;
+      last_out[g] = last;
+      tlast_out[g] = Tb;
+    }
   }
 }
 
@@ -192,11 +194,15 @@ __device__ __forceinline__ void face_grad(const ViewRec& R, const PixEval& h, fl
   g[G_PY + C] += a[0] * Bx - a[1] * Ax;
 }
 
-template <int TW, int TH>
+// DET (tiles of more than one wave): each wave's sum of an entry goes to its
+// own LDS slot and the slots are added in wave order, instead of LDS float
+// atomics in arrival order.
+template <int TW, int TH, bool DET>
 __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, float alpha_min, float alpha_clamp,
                                                           float t_min, int recompute) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
+  constexpr bool WSLOT = DET && NW > 1;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
@@ -206,6 +212,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
   __shared__ ViewRec recs[CH];
   __shared__ float gacc[CH][TGRAD_STRIDE];
+  __shared__ float gaccw[WSLOT ? NW : 1][WSLOT ? CH : 1][TGRAD_STRIDE];
   __shared__ int smax[NW];
 
   const TileCtx c = tile_ctx<TW, TH>(vw, at<const TileSlot>(ws, L.o_tile_order));
@@ -277,7 +284,9 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
     const uint32_t base = (uint32_t)cb;
     const int n = (int)min((uint32_t)CH, pend - base);
     load_chunk(recs, vrec, srec, base, n, NT, at<const uint4>(ws, L.o_rbox));
-    if (NW > 1)
+    if (WSLOT)
+      for (int q = threadIdx.x; q < NW * CH * TGRAD_STRIDE; q += NT) (&gaccw[0][0][0])[q] = 0.0f;
+    else if (NW > 1)
       for (int q = threadIdx.x; q < CH * TGRAD_STRIDE; q += NT) (&gacc[0][0])[q] = 0.0f;
     __syncthreads();
     for (int e = n - 1; e >= 0; --e) {
@@ -338,10 +347,30 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
       const unsigned q = lane >> 1;
       if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) {
         if (NW == 1) gacc[e][q] = tot;
+        else if (WSLOT) gaccw[threadIdx.x >> 6][e][q] = tot;
         else atomicAdd(&gacc[e][q], tot);
       }
     }
     __syncthreads();
+    if (WSLOT) {
+      for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) {
+        const int e = q / TGRAD_STRIDE, k = q - e * TGRAD_STRIDE;
+        float acc = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) acc += gaccw[w][e][k];
+        gacc[e][k] = acc;
+      }
+      __syncthreads();
+    }
+    if (record_grads(L)) {
+      for (int q = threadIdx.x; q < n * (TGRAD_STRIDE - 1); q += NT) {
+        const int e = q / (TGRAD_STRIDE - 1), k = q - e * (TGRAD_STRIDE - 1);
+        const float v = gacc[e][k];
+        if (v != 0.0f) unsafeAtomicAdd(&tgrad[(size_t)srec[base + e] * TGRAD_STRIDE + k], v);
+      }
+      __syncthreads();
+      continue;
+    }
     // each entry's gradient goes to its pre-sort slot: the record's first
     // entry plus this tile's row-major index inside the record's tile rectangle
     for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) {
@@ -364,8 +393,13 @@ static void launch_fwd(void* ws, const Layout& L, const render_params& p, hipStr
 }
 template <int TW, int TH>
 static void launch_bwd(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  k_composite_bwd<TW, TH><<<(unsigned)L.total_tiles, TW * TH, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp, p.t_min,
-                                                                       (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0);
+  const int rc = (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0;
+  if (deterministic(L))
+    k_composite_bwd<TW, TH, true><<<(unsigned)L.total_tiles, TW * TH, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                               p.t_min, rc);
+  else
+    k_composite_bwd<TW, TH, false><<<(unsigned)L.total_tiles, TW * TH, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                                p.t_min, rc);
 }
 
 #define TS_TILE_SWITCH(FN)                                          \

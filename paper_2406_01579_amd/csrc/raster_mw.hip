@@ -9,8 +9,10 @@
 // on that state.  So NWV waves share one 8x8 tile: for each LDS chunk of
 // entries they evaluate interleaved entries in parallel into LDS, one wave
 // runs the recurrence over the chunk, and (backward) the waves then build and
-// reduce the per-entry gradients in parallel.  Results are bit-identical to
-// the one-wave kernels: the same per-pair arithmetic in the same order.
+// reduce the per-entry gradients in parallel.  Images are bit-identical to
+// the one-wave kernels (the same per-pair arithmetic in the same order);
+// gradients agree to rounding (an entry's pixel groups are added in LDS in
+// arrival order), bitwise with the deterministic variant.
 #include "tile8.h"
 
 namespace ts {
@@ -135,9 +137,11 @@ __device__ __forceinline__ void background_tiles(void* ws, const Layout& L, cons
     out[2 * plane + px] = V.bg[2];
 #pragma unroll
     for (int k = 3; k < 8; ++k) out[k * plane + px] = 0.0f;
-    const size_t g = (size_t)V.pix_base + px;
-    last_out[g] = -1;
-    tlast_out[g] = 1.0f;
+    if (keeps_pixel_state(L)) {
+      const size_t g = (size_t)V.pix_base + px;
+      last_out[g] = -1;
+      tlast_out[g] = 1.0f;
+    }
   }
 }
 
@@ -207,17 +211,22 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
     out[5 * plane + px] = acc[4];
     out[6 * plane + px] = acc[5];
     out[7 * plane + px] = acc[6];
-    const size_t g = (size_t)V.pix_base + px;
-    last_out[g] = last;
-    tlast_out[g] = Tb;
+    if (keeps_pixel_state(L)) {
+      const size_t g = (size_t)V.pix_base + px;
+      last_out[g] = last;
+      tlast_out[g] = Tb;
+    }
   }
 }
 
-template <int NWV>
+// DET: every entry's gradient is the sum of its 8-pixel groups in group
+// order (group sums staged in LDS), not LDS float atomics in arrival order;
+// the chunk is halved (16 entries) to make room.
+template <int NWV, bool DET>
 __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout L, float alpha_min,
                                                                float alpha_clamp, float t_min, int recompute) {
   constexpr int NT = 64 * NWV;
-  constexpr int CHB = 32;
+  constexpr int CHB = DET ? 16 : 32;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
@@ -238,6 +247,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   __shared__ float feat[7][CHB];     // per entry: c[3], zt, n[3] (conflict-free gathers)
   __shared__ unsigned long long done_mask;
   __shared__ int smax;
+  __shared__ __align__(16) float gsum[DET ? CHB * 8 : 1][TGRAD_STRIDE];  // DET: per 8-pixel group
 
   // dispatch order by the length the forward walked (longest first); the
   // tiles where nothing was blended come last and leave at once
@@ -423,8 +433,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         float g[32];
         pair_grad_all(recs[e], px_, py_, grp8, dd, dfn, w, sel[e][pix], g);
         const float4 r = row8_transpose_sum32(g);
-        if (gv && 4 * l8 < TGRAD_STRIDE - 1) {
-          static_assert(TGRAD_STRIDE - 1 == 23, "23 gradient slots: lane 5 holds the last three");
+        static_assert(TGRAD_STRIDE - 1 == 23, "23 gradient slots: lane 5 holds the last three");
+        if constexpr (DET) {
+          if (gv && 4 * l8 < TGRAD_STRIDE) *reinterpret_cast<float4*>(&gsum[grp][4 * l8]) = r;
+        } else if (gv && 4 * l8 < TGRAD_STRIDE - 1) {
           atomicAdd(&gacc[e][4 * l8], r.x);
           atomicAdd(&gacc[e][4 * l8 + 1], r.y);
           atomicAdd(&gacc[e][4 * l8 + 2], r.z);
@@ -433,7 +445,17 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       }
     }
     __syncthreads();
-    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT);
+    if constexpr (DET) {
+      // each entry: its groups' sums in group order
+      for (int q = threadIdx.x; q < n * (TGRAD_STRIDE - 1); q += NT) {
+        const int e = q / (TGRAD_STRIDE - 1), k = q - e * (TGRAD_STRIDE - 1);
+        float acc = 0.0f;
+        for (uint32_t gi = poff[e]; gi < poff[e + 1]; ++gi) acc += gsum[gi][k];
+        gacc[e][k] = acc;
+      }
+      __syncthreads();
+    }
+    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, record_grads(L) ? srec + base : nullptr);
   }
 }
 
@@ -443,8 +465,13 @@ static void launch_fwd_mw(void* ws, const Layout& L, const render_params& p, hip
 }
 template <int NWV>
 static void launch_bwd_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  k_composite_bwd_mw<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(
-      ws, L, p.alpha_min, p.alpha_clamp, p.t_min, (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0);
+  const int rc = (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0;
+  if (deterministic(L))
+    k_composite_bwd_mw<NWV, true><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                                p.t_min, rc);
+  else
+    k_composite_bwd_mw<NWV, false><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                                 p.t_min, rc);
 }
 
 hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {

@@ -258,9 +258,11 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
       out[5 * plane + px] = acc[4];
       out[6 * plane + px] = acc[5];
       out[7 * plane + px] = acc[6];
-      const size_t g = (size_t)V.pix_base + px;
-      last_out[g] = last;
-      tlast_out[g] = Tb;
+      if (keeps_pixel_state(L)) {
+        const size_t g = (size_t)V.pix_base + px;
+        last_out[g] = last;
+        tlast_out[g] = Tb;
+      }
     }
   }
 }
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))
       if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
     }
     __syncthreads();
-    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT);
+    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, record_grads(L) ? srec + base : nullptr);
   }
 }
 

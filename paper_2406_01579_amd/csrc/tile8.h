@@ -59,10 +59,20 @@ __device__ __forceinline__ Tile8 tile8(const DevView* vw, const TileSlot* slots)
 // The tile's reduced gradient of each chunk entry (gacc[e][0..TGRAD_STRIDE))
 // goes to the entry's pre-sort slot: the record's first entry plus this
 // tile's row-major index inside the record's tile rectangle; the slot is
-// flagged as reached.
+// flagged as reached.  With chunk_rec (the chunk's record indices) it is
+// added into its record's accumulator instead.
 __device__ __forceinline__ void store_entry_grads(const ViewRec* recs, const float (*gacc)[TGRAD_STRIDE], int n,
                                                   const Tile8& c, float* __restrict__ tgrad,
-                                                  uint8_t* __restrict__ eflag, int nthreads) {
+                                                  uint8_t* __restrict__ eflag, int nthreads,
+                                                  const uint32_t* __restrict__ chunk_rec = nullptr) {
+  if (chunk_rec) {
+    for (int q = threadIdx.x; q < n * (TGRAD_STRIDE - 1); q += nthreads) {
+      const int e = q / (TGRAD_STRIDE - 1), k = q - e * (TGRAD_STRIDE - 1);
+      const float v = gacc[e][k];
+      if (v != 0.0f) unsafeAtomicAdd(&tgrad[(size_t)chunk_rec[e] * TGRAD_STRIDE + k], v);
+    }
+    return;
+  }
   for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += nthreads) {
     const int e = q / TGRAD_STRIDE, k = q - e * TGRAD_STRIDE;
     const ViewRec& R = recs[e];

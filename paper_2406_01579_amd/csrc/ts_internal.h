@@ -28,7 +28,7 @@ struct DevScene {
   int32_t n_blocks;
   int32_t view_first;   // this scene's views: scene_views[view_first .. + view_count)
   int32_t view_count;
-  int32_t pad;
+  int32_t vbase;        // first vertex of this scene in the concatenation of all scenes' vertices
 };
 
 struct DevView {
@@ -60,7 +60,8 @@ struct DevHeader {
   uint32_t overflow;
   uint32_t invalid_index;
   uint32_t bwd_work;    // backward dispatch slots with a walked entry (they come first)
-  uint32_t pad0[2];
+  uint32_t corners_total;  // deterministic backward: 4 x kept tets, the corners sorted by vertex
+  uint32_t pad0;
   int64_t entry_capacity, kept_capacity;
   uint64_t entries_needed;  // entries the last forward wanted (exact, also on overflow)
   uint32_t pad1[50];
@@ -114,6 +115,7 @@ constexpr int SORT_BITS = 8;
 
 struct Layout {
   int ns, nv;
+  int flags;            // render_params.flags of the call
   int64_t kept_cap, rec_cap, entry_cap;
   int64_t pf_blocks, scan_blocks_rec, sort_blocks_max, total_tiles, total_pixels;
   int key2_bits;
@@ -129,6 +131,10 @@ struct Layout {
   size_t o_tile_pend;    // per dispatch slot: end of the entries the forward blended (backward walk)
   size_t o_bwd_hist, o_bwd_order, o_bwd_pend;  // backward dispatch order (by walked length)
   size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
+  // deterministic backward (0 otherwise): per kept-tet corner a vertex key and
+  // corner id (double-buffered for the sort) and its 7 gradient terms (8 floats)
+  size_t o_vkey_a, o_vkey_b, o_vval_a, o_vval_b, o_vterm;
+  int vkey_bits;         // bit length of the total vertex count
   size_t bytes;
 };
 
@@ -169,6 +175,14 @@ hipError_t launch_composite_backward_mw(void* ws, const Layout& L, const render_
 hipError_t launch_composite_win(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_backward_win(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+// deterministic backward: sort the kept tets' corners by vertex, sum each vertex's terms in corner order
+hipError_t launch_vertex_gather(void* ws, const Layout& L, hipStream_t st);
+
+// per-pixel compositing state is kept (not recomputed by the backward)
+inline __host__ __device__ bool keeps_pixel_state(const Layout& L) { return L.o_last != 0; }
+// one gradient accumulator per record instead of one gradient per entry
+inline __host__ __device__ bool record_grads(const Layout& L) { return (L.flags & RENDER_RECORD_GRADS) != 0; }
+inline __host__ __device__ bool deterministic(const Layout& L) { return (L.flags & RENDER_DETERMINISTIC) != 0; }
 hipError_t launch_desc_zero_grads(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
                                   void* ws, const Layout& L, hipStream_t st);
 

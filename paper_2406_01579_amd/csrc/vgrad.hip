@@ -49,13 +49,16 @@ constexpr int VB_HASH = 512;
 constexpr int VB_PROBES = 16;
 static_assert(VB_HASH == 1 << 9, "the slot hash keeps 9 bits");
 
+// With DET the per-vertex terms of every kept tet's four corners are written
+// out (with the corner's global vertex id as a sort key) instead of being
+// combined, and k_vertex_gather adds them in a fixed order.
 // A 5-waves-per-SIMD target fits the kernel in 96 VGPRs without spills.
-template <int P>
+template <int P, bool DET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_vertex_bwd(void* ws, Layout L) {
-  __shared__ uint32_t hkey[VB_HASH];   // vertex id + 1; 0: empty
-  __shared__ float hval[7][VB_HASH];   // dverts xyz, dsdf, dcolors xyz
+  __shared__ uint32_t hkey[DET ? 1 : VB_HASH];   // vertex id + 1; 0: empty
+  __shared__ float hval[7][DET ? 1 : VB_HASH];   // dverts xyz, dsdf, dcolors xyz
   __shared__ int bscene;
-  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
   const int32_t* scene_views = at<const int32_t>(ws, L.o_scene_views);
@@ -68,6 +71,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   const float* tgrad = at<const float>(ws, L.o_tgrad);
   const uint32_t nk = min(hdr->kept_total, (uint32_t)L.kept_cap);
   const uint32_t nrec = hdr->records_total;
+  const bool per_record = record_grads(L);
+  if (DET && blockIdx.x == 0 && threadIdx.x == 0) hdr->corners_total = 4u * nk;
   const uint64_t cap = (uint64_t)L.entry_cap;
   const int q0 = (int)(threadIdx.x % P);
   const uint32_t stride = gridDim.x * (blockDim.x / P);
@@ -77,13 +82,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const bool tet_ok = k < nk;
     const TetRec& T = trec[tet_ok ? k : 0u];
     const int ks = tet_ok ? scene_of_kept(kbase, L.ns, k) : 0;
-    for (int h = threadIdx.x; h < VB_HASH; h += blockDim.x) {
-      hkey[h] = 0u;
+    if constexpr (!DET) {
+      for (int h = threadIdx.x; h < VB_HASH; h += blockDim.x) {
+        hkey[h] = 0u;
 #pragma unroll
-      for (int m = 0; m < 7; ++m) hval[m][h] = 0.0f;
+        for (int m = 0; m < 7; ++m) hval[m][h] = 0.0f;
+      }
+      if (threadIdx.x == 0) bscene = tet_ok ? ks : -1;   // thread 0 holds the block's first tet
+      __syncthreads();
     }
-    if (threadIdx.x == 0) bscene = tet_ok ? ks : -1;   // thread 0 holds the block's first tet
-    __syncthreads();
     float dv[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     float dfv[4] = {0, 0, 0, 0}, dn[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
     bool any = false;
@@ -96,6 +103,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         if (r >= nrec) continue;
         const uint32_t cnt = count1[r];
         if (cnt == 0) continue;
+        float g[23];
+        bool hit = false;
+        if (per_record) {
+          // the record's accumulator (zero if no tile reached it)
+          const float4* src = reinterpret_cast<const float4*>(tgrad + (size_t)r * TGRAD_STRIDE);
+#pragma unroll
+          for (int z = 0; z < 6; ++z) {
+            const float4 x = src[z];
+            if (4 * z + 0 < 23) g[4 * z + 0] = x.x;
+            if (4 * z + 1 < 23) g[4 * z + 1] = x.y;
+            if (4 * z + 2 < 23) g[4 * z + 2] = x.z;
+            if (4 * z + 3 < 23) g[4 * z + 3] = x.w;
+          }
+#pragma unroll
+          for (int z = 0; z < 23; ++z) hit = hit || g[z] != 0.0f;
+        } else {
         const uint32_t o = rbox[r].w;   // the record's first entry
         const uint32_t n = (uint32_t)min((uint64_t)cnt, cap > o ? cap - o : 0ull);
         if (n == 0u) continue;  // entries past the capacity (an overflowed forward)
@@ -113,10 +136,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
           for (uint32_t j = 8; j < n && j < 32u; ++j) fl |= eflag[o + j] ? (1u << j) : 0u;
           if (n < 32u) fl &= (1u << n) - 1u;
         }
-        float g[23];
 #pragma unroll
         for (int z = 0; z < 23; ++z) g[z] = 0.0f;
-        bool hit = false;
         for (uint32_t t = fl; t != 0u; t &= t - 1u) {
           const uint64_t d = (uint64_t)o + (uint64_t)(__ffs(t) - 1);
           const float4* src = reinterpret_cast<const float4*>(tgrad + (size_t)d * TGRAD_STRIDE);
@@ -137,6 +158,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
           const float* src = tgrad + (size_t)d * TGRAD_STRIDE;
           for (int z = 0; z < 23; ++z) g[z] += src[z];
           hit = true;
+        }
         }
         if (!hit) continue;
         any = true;
@@ -180,7 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         dc[m] = group_sum<P>(dc[m]);
       }
     }
-    if (tet_ok && any && q0 == 0) {
+    if (tet_ok && (any || DET) && q0 == 0) {
     const DevScene& S = sc[ks];
     // normal: n = g/|g|, g = E^-1 df
     if (dn[0] != 0.0f || dn[1] != 0.0f || dn[2] != 0.0f) {
@@ -222,6 +244,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     }
     const int4 vi = reinterpret_cast<const int4*>(S.tets)[T.tet];
     const int idx[4] = {vi.x, vi.y, vi.z, vi.w};
+    if constexpr (DET) {
+      // the four corners' terms and sort keys (corner id 4 k + a is the
+      // sort's identity value)
+      uint32_t* key = at<uint32_t>(ws, L.o_vkey_a);
+      float4* term = at<float4>(ws, L.o_vterm);
+      for (int a = 0; a < 4; ++a) {
+        const size_t cid = 4 * (size_t)k + (size_t)a;
+        key[cid] = (uint32_t)S.vbase + (uint32_t)idx[a];
+        term[2 * cid] = make_float4(dv[a][0], dv[a][1], dv[a][2], dfv[a]);
+        term[2 * cid + 1] = make_float4(0.25f * dc[0], 0.25f * dc[1], 0.25f * dc[2], 0.0f);
+      }
+    } else
     for (int a = 0; a < 4; ++a) {
       const uint32_t vv = (uint32_t)idx[a];
       const float val[7] = {dv[a][0], dv[a][1], dv[a][2], dfv[a], 0.25f * dc[0], 0.25f * dc[1], 0.25f * dc[2]};
@@ -249,6 +283,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       }
     }
     }
+    if constexpr (DET) continue;
     __syncthreads();
     if (bscene >= 0) {
       const DevScene& S = sc[bscene];
@@ -267,6 +302,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   }
 }
 
+template <bool DET>
+static void launch_vbwd(void* ws, const Layout& L, unsigned blocks, int nvs, hipStream_t st) {
+  if (nvs <= 1) k_vertex_bwd<1, DET><<<blocks, 256, 0, st>>>(ws, L);
+  else if (nvs <= 2) k_vertex_bwd<2, DET><<<blocks, 256, 0, st>>>(ws, L);
+  else if (nvs <= 4) k_vertex_bwd<4, DET><<<blocks, 256, 0, st>>>(ws, L);
+  else k_vertex_bwd<8, DET><<<blocks, 256, 0, st>>>(ws, L);
+}
+
 hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
   (void)p;
   // lanes per tet: the largest view count of a scene, rounded up to a power of two (at most 8)
@@ -274,10 +317,67 @@ hipError_t launch_vertex_backward(void* ws, const Layout& L, const render_params
   const int64_t threads = L.kept_cap * (nvs <= 1 ? 1 : nvs <= 2 ? 2 : nvs <= 4 ? 4 : 8);
   const int64_t b = (threads + 255) / 256;
   const unsigned blocks = (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
-  if (nvs <= 1) k_vertex_bwd<1><<<blocks, 256, 0, st>>>(ws, L);
-  else if (nvs <= 2) k_vertex_bwd<2><<<blocks, 256, 0, st>>>(ws, L);
-  else if (nvs <= 4) k_vertex_bwd<4><<<blocks, 256, 0, st>>>(ws, L);
-  else k_vertex_bwd<8><<<blocks, 256, 0, st>>>(ws, L);
+  if (deterministic(L)) launch_vbwd<true>(ws, L, blocks, nvs, st);
+  else launch_vbwd<false>(ws, L, blocks, nvs, st);
+  return hipGetLastError();
+}
+
+// Deterministic vertex sums: the corners, sorted by vertex (stable, so a
+// vertex's corners keep ascending corner id, i.e. kept-tet order), are
+// walked from the first corner of each vertex and added in that order; one
+// thread writes each vertex that some kept tet touches (the others stay as
+// the gradient clear left them, zero).
+__global__ __launch_bounds__(256) void k_vertex_gather(void* ws, Layout L, const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ cids) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
+  const float4* term = at<const float4>(ws, L.o_vterm);
+  const uint32_t n = min(hdr->corners_total, (uint32_t)(4 * L.kept_cap));
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t key = keys[i];
+    if (i > 0 && keys[i - 1] == key) continue;
+    float acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t j = i; j < n && keys[j] == key; ++j) {
+      const float4 a = term[2 * (size_t)cids[j]], b = term[2 * (size_t)cids[j] + 1];
+      acc[0] += a.x;
+      acc[1] += a.y;
+      acc[2] += a.z;
+      acc[3] += a.w;
+      acc[4] += b.x;
+      acc[5] += b.y;
+      acc[6] += b.z;
+    }
+    // the scene: the last one whose first vertex is at or below the key
+    int lo = 0, hi = L.ns - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((uint32_t)sc[mid].vbase <= key) lo = mid;
+      else hi = mid - 1;
+    }
+    const DevScene& S = sc[lo];
+    const size_t v = (size_t)(key - (uint32_t)S.vbase);
+    S.dverts[3 * v] = acc[0];
+    S.dverts[3 * v + 1] = acc[1];
+    S.dverts[3 * v + 2] = acc[2];
+    S.dsdf[v] = acc[3];
+    S.dcolors[3 * v] = acc[4];
+    S.dcolors[3 * v + 1] = acc[5];
+    S.dcolors[3 * v + 2] = acc[6];
+  }
+}
+
+hipError_t launch_vertex_gather(void* ws, const Layout& L, hipStream_t st) {
+  uint32_t *ko, *vo;
+  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+  const int64_t nc = 4 * L.kept_cap;
+  hipError_t e = radix_sort_pairs(at<uint32_t>(ws, L.o_vkey_a), at<uint32_t>(ws, L.o_vval_a),
+                                  at<uint32_t>(ws, L.o_vkey_b), at<uint32_t>(ws, L.o_vval_b), true,
+                                  &hdr->corners_total, nc, L.vkey_bits, at<uint32_t>(ws, L.o_hist),
+                                  L.sort_blocks_max, st, &ko, &vo);
+  if (e != hipSuccess) return e;
+  const int64_t b = (nc + 255) / 256;
+  const unsigned blocks = (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+  k_vertex_gather<<<blocks, 256, 0, st>>>(ws, L, ko, vo);
   return hipGetLastError();
 }
 

@@ -31,13 +31,19 @@ class Params:
     alpha_clamp: float = 0.99
     t_min: float = 1e-4
     prefilter_tf: float = 1.0 / 255.0
-    recompute_state: bool = False
+    recompute_state: bool = False   # no per-pixel state in the workspace; the backward recomputes it
     waves: int = 4   # waves sharing one 8x8 tile
     window: int = 0  # per-pixel resort window N_w (Sec. 3.3); 0: per-tile order
+    deterministic: bool = False     # bitwise-reproducible gradients (fixed-order sums)
+    record_grads: bool = False      # one gradient accumulator per record instead of per entry
+
+    def flags(self) -> int:
+        return ((_lib.RENDER_RECOMPUTE_STATE if self.recompute_state else 0) |
+                (_lib.RENDER_DETERMINISTIC if self.deterministic else 0) |
+                (_lib.RENDER_RECORD_GRADS if self.record_grads else 0))
 
     def c(self) -> _lib.render_params:
-        return _lib.render_params(self.tile_w, self.tile_h,
-                                  _lib.RENDER_RECOMPUTE_STATE if self.recompute_state else 0, self.waves,
+        return _lib.render_params(self.tile_w, self.tile_h, self.flags(), self.waves,
                                   self.alpha_min, self.alpha_clamp, self.t_min, self.prefilter_tf, self.window)
 
     @classmethod
@@ -313,8 +319,8 @@ class Renderer:
             scene_kept_base=grab(d.scene_kept_base, len(plan.scenes), np.int32),
             scene_kept_count=grab(d.scene_kept_count, len(plan.scenes), np.int32),
             ranges=grab(d.ranges, 2 * int(d.total_tiles), np.uint32).reshape(-1, 2),
-            last=grab(d.last, int(d.total_pixels), np.int32),
-            t_last=grab(d.t_last, int(d.total_pixels), np.float32),
+            last=grab(d.last, int(d.total_pixels), np.int32) if d.last else None,
+            t_last=grab(d.t_last, int(d.total_pixels), np.float32) if d.t_last else None,
             entries=E, kept=int(stt.kept), records=int(stt.records),
         )
 

@@ -117,8 +117,14 @@ class Scheduler:
         self.max_in_flight = max(self.max_in_flight, self.in_flight)
         return batch
 
-    def release(self, batch):
-        self.in_flight -= sum(r.footprint for r in batch)
+    def charge(self, nbytes: int):
+        """Bytes beyond the admitted footprints that a running launch took
+        (a re-run with larger capacities); released with its batch."""
+        self.in_flight += int(nbytes)
+        self.max_in_flight = max(self.max_in_flight, self.in_flight)
+
+    def release(self, batch, extra: int = 0):
+        self.in_flight -= sum(r.footprint for r in batch) + int(extra)
 
 
 # ----------------------------------------------------------------------------
@@ -183,6 +189,7 @@ class _Launch:
     headers: list = field(default_factory=list)
     end: object = None
     reruns: int = 0
+    extra_bytes: int = 0   # workspace its re-runs took beyond the admitted footprints
 
 
 class Server:
@@ -305,10 +312,15 @@ class Server:
                 factor = max(1.0, need[1] / max(1, caps[1])) * 1.25
                 for v in range(len(cams)):
                     self.reg.grow(sids[int(vs[v])], int(cams[v][0]), int(cams[v][1]), factor)
+                old_bytes = L.plans[i].workspace.numel()
                 with torch.cuda.stream(st):
                     plan = self.renderer.forward([self.reg.scenes[x] for x in sids], cams, vs, caps=need)
                     hdr2 = torch.empty(_lib.STATUS_BYTES, dtype=torch.uint8, pin_memory=True)
                     hdr2.copy_(plan.workspace[:_lib.STATUS_BYTES], non_blocking=True)
+                # the larger workspace counts against the HBM budget until the batch completes
+                grown = max(0, plan.workspace.numel() - old_bytes)
+                L.extra_bytes += grown
+                self.sched.charge(grown)
                 L.plans[i], L.headers[i], L.args[i] = plan, hdr2, (sids, cams, vs, need)
                 L.reruns += 1
                 self.reruns += 1
@@ -326,7 +338,7 @@ class Server:
             j += r.views
             if r.error is None:
                 r.done_at = t_done
-        self.sched.release(L.requests)
+        self.sched.release(L.requests, L.extra_bytes)
         self.slots[k] = None
         return len(L.requests)
 

@@ -267,3 +267,32 @@ def test_coarse_grid_entry_points_validate_on_the_host(L):
     assert lib.render_refit_cube(None, 8192, 8, 16384, None) == L.RENDER_EINVAL
     assert lib.render_refit_cube(4096, 8192, 8, 16386, None) == L.RENDER_EINVAL
     assert b"misaligned" in lib.render_last_error()
+
+
+def test_memory_flags_shrink_or_grow_the_workspace(L):
+    """RENDER_RECOMPUTE_STATE drops the 8 B per pixel of compositing state;
+    RENDER_RECORD_GRADS replaces 96 B per entry by 96 B per record;
+    RENDER_DETERMINISTIC adds its corner sort (4 x 48 B per kept tet); the
+    last two exclude each other."""
+    w = synth.training(s=320.0, R=16, size=128, views=2)
+    scenes, views, p = _args(L, w, (8, 8))
+    kept, ent = 3000, 40000
+    rc, base = _size(L, scenes, views, p, kept, ent)
+    assert rc == 0
+    pixels = 2 * 128 * 128
+    rec = 2 * kept
+    p.flags = L.RENDER_RECOMPUTE_STATE
+    rc, a = _size(L, scenes, views, p, kept, ent)
+    assert rc == 0 and abs((base - a) - 8 * pixels) <= 512
+    p.flags = L.RENDER_RECORD_GRADS
+    rc, b = _size(L, scenes, views, p, kept, ent)
+    assert rc == 0 and abs((base - b) - 96 * (ent - rec)) <= 512
+    p.flags = L.RENDER_RECOMPUTE_STATE | L.RENDER_RECORD_GRADS
+    rc, c = _size(L, scenes, views, p, kept, ent)
+    assert rc == 0 and abs((base - c) - 8 * pixels - 96 * (ent - rec)) <= 1024
+    p.flags = L.RENDER_DETERMINISTIC
+    rc, d = _size(L, scenes, views, p, kept, ent)
+    assert rc == 0 and d - base >= 4 * kept * 48
+    p.flags = L.RENDER_DETERMINISTIC | L.RENDER_RECORD_GRADS
+    rc, _ = _size(L, scenes, views, p, kept, ent)
+    assert rc == L.RENDER_EINVAL and b"exclude" in L.lib().render_last_error()

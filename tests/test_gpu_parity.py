@@ -448,3 +448,93 @@ def test_training_gradients_dense_upstream_timed_shape(training):
     assert np.array_equal(pix[:3, 1], [0, 1, 2]) and pix[512, 2] == 1
     refs = oracle_gradients(g, w.cams, oracle_params(P, 320.0), pix, dflat)
     check_gradients(grads, refs, "training 8x8/4 waves dense upstream")
+
+
+# ---------------------------------------------------------------------------
+# memory and reproducibility modes of the backward
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["record_grads", "deterministic", "record_grads+recompute"])
+@pytest.mark.parametrize("tile", TILES)
+def test_tiny_gradients_backward_modes(tile, mode):
+    """Per-record gradient accumulators, the deterministic reductions and the
+    recomputed per-pixel state against the oracle, for every tile shape."""
+    import torch
+    s = 100.0
+    w = synth.tiny(s=s, bg=(0.3, 0.1, 0.2))
+    sc = w.scenes[0]
+    P = _params("default", tile, record_grads="record_grads" in mode, deterministic=mode == "deterministic",
+                recompute_state="recompute" in mode)
+    r, plan, _ = gpu_forward(sc, w.cams, P)
+    dout = np.random.default_rng(5).normal(size=(8, 64, 64)).astype(np.float32)
+    (dv, ds, dc), = r.backward(plan, [torch.from_numpy(dout).cuda()])
+    torch.cuda.synchronize()
+    g = oracle.Geometry.of(sc)
+    pix = oracle.all_pixels(w.cams)
+    refs = oracle_gradients(g, w.cams, oracle_params(P, s), pix, dout.reshape(8, -1).T.copy())
+    check_gradients((dv, ds, dc), refs, f"tiny {tile} {mode}")
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_training_deterministic_gradients_are_bitwise_repeatable(training, tile):
+    """RENDER_DETERMINISTIC: three backward passes of one forward and a
+    second forward + backward give bitwise-identical gradients, equal to the
+    default mode's to rounding."""
+    import torch
+    w, g = training
+    douts = [torch.from_numpy(d).cuda()
+             for d in np.random.default_rng(17).normal(size=(4, 8, 512, 512)).astype(np.float32)]
+    P = _params("default", tile, deterministic=True)
+    r, plan, _ = gpu_forward(w.scenes[0], w.cams, P)
+    runs = []
+    for _ in range(3):
+        runs.append([t.cpu().numpy() for t in r.backward(plan, douts)[0]])
+    r2, plan2, _ = gpu_forward(w.scenes[0], w.cams, P)
+    runs.append([t.cpu().numpy() for t in r2.backward(plan2, douts)[0]])
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
+    rd, pd, _ = gpu_forward(w.scenes[0], w.cams, _params("default", tile))
+    ref = [t.cpu().numpy() for t in rd.backward(pd, douts)[0]]
+    for name, a, b in zip(("dverts", "dsdf", "dcolors"), runs[0], ref):
+        n = float(np.abs(a - b).max() / np.abs(b).max())
+        print(f"deterministic {tile} {name}: normwise vs default mode {n:.2e}")
+        assert n <= 1e-5
+
+
+def test_training_record_grads_and_recomputed_state_shrink_the_workspace(training):
+    """RENDER_RECORD_GRADS + RENDER_RECOMPUTE_STATE at the training shape:
+    a smaller workspace, the same image, gradients of a sparse upstream
+    gradient against the oracle and equal to the default mode's to rounding."""
+    import torch
+    w, g = training
+    Pd = _params("default", (8, 8))
+    Pm = _params("default", (8, 8), record_grads=True, recompute_state=True)
+    rd, pd, imd = gpu_forward(w.scenes[0], w.cams, Pd)
+    rm, pm, imm = gpu_forward(w.scenes[0], w.cams, Pm)
+    for a, b in zip(imd, imm):
+        assert np.array_equal(a, b)
+    caps = rm.capacity(pm.scenes, w.cams)   # the capacities sized by the first forward
+    nd = rd.workspace_bytes(pd.scene_c, pd.view_c, pd.params_c, *caps)
+    nm = rm.workspace_bytes(pm.scene_c, pm.view_c, pm.params_c, *caps)
+    print(f"workspace at the same capacities {caps}: default {nd / 2**20:.1f} MiB, record grads + recomputed "
+          f"state {nm / 2**20:.1f} MiB")
+    assert nm < 0.75 * nd
+    cov = np.argwhere(np.stack(imd)[:, 3] > 0.01)
+    pick = cov[np.random.default_rng(3).choice(len(cov), 2000, replace=False)]
+    pix = np.ascontiguousarray(pick[:, [0, 2, 1]], dtype=np.int32)
+    key = pix[:, 0] * 512 * 512 + pix[:, 2] * 512 + pix[:, 1]
+    _, first = np.unique(key, return_index=True)
+    upix = pix[first]
+    vals = np.random.default_rng(4).normal(size=(upix.shape[0], 8)).astype(np.float32)
+    douts = [np.zeros((8, 512, 512), np.float32) for _ in range(4)]
+    for (v, i, j), x in zip(upix, vals):
+        douts[v][:, j, i] = x
+    dt = [torch.from_numpy(d).cuda() for d in douts]
+    gm = rm.backward(pm, dt)[0]
+    gd = rd.backward(pd, dt)[0]
+    torch.cuda.synchronize()
+    for name, a, b in zip(("dverts", "dsdf", "dcolors"), gm, gd):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert float(np.abs(a - b).max() / np.abs(b).max()) <= 1e-5, name
+    refs = oracle_gradients(g, w.cams, oracle_params(Pm, 320.0), upix, vals.astype(np.float64))
+    check_gradients(gm, refs, "training record grads + recomputed state")

@@ -53,3 +53,19 @@ def test_without_batching_one_request_per_launch():
     for i in range(3):
         s.submit(_req(i, nv=2))
     assert [len(s.next_batch()) for _ in range(3)] == [1, 1, 1]
+
+
+def test_rerun_growth_is_charged_until_release():
+    """A launch re-run with larger capacities charges the extra workspace to
+    the in-flight bytes (admission sees it) and gives it back with its batch."""
+    s = Scheduler(budget_bytes=1000)
+    for i in range(4):
+        s.submit(_req(i, fp=300))
+    b1 = s.next_batch()
+    assert s.in_flight == 900
+    s.charge(200)                              # the re-run's larger workspace
+    assert s.in_flight == 1100 and s.max_in_flight == 1100
+    assert s.next_batch() == []
+    s.release(b1, 200)
+    assert s.in_flight == 0
+    assert [r.id for r in s.next_batch()] == [3]
