@@ -184,7 +184,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.entry_cap = entry_cap;
   L.pf_blocks = pf_blocks;
   L.scan_blocks_rec = (rec_cap + SCAN_TILE - 1) / SCAN_TILE;
-  int64_t smax = rec_cap > entry_cap ? rec_cap : entry_cap;
+  int64_t smax = entry_cap;
   if (det && 4 * kept_cap > smax) smax = 4 * kept_cap;
   L.sort_blocks_max = (smax + SORT_TILE - 1) / SORT_TILE;
   L.total_tiles = tiles;
@@ -219,9 +219,6 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_rbox = take(16 * (size_t)rec_cap);
   L.o_count1 = take(4 * (size_t)rec_cap);
   L.o_key1a = take(4 * (size_t)rec_cap);
-  L.o_key1b = take(4 * (size_t)rec_cap);
-  L.o_val1a = take(4 * (size_t)rec_cap);
-  L.o_val1b = take(4 * (size_t)rec_cap);
   L.o_scan_part = take(4 * (size_t)(L.scan_blocks_rec + 1));
   L.o_hist = take(4 * (size_t)(256 * L.sort_blocks_max + 256));
   L.o_key2a = take(4 * (size_t)entry_cap);
@@ -481,12 +478,12 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_PREFILTER, launch_prefilter(workspace, L, *params, st), "pre-filter");
   TS_STAGE(RENDER_STAGE_PROJECT, launch_project(workspace, L, *params, st), "project");
-  TS_STAGE(RENDER_STAGE_DEPTH_SORT, launch_sort_records(workspace, L, st), "depth sort");
   TS_STAGE(RENDER_STAGE_SCAN, launch_count_scan(workspace, L, st), "count scan");
   TS_STAGE(RENDER_STAGE_EMIT, launch_emit(workspace, L, *params, st), "emit");
   TS_STAGE(RENDER_STAGE_TILE_SORT, launch_sort_entries(workspace, L, st), "tile sort");
   TS_STAGE(RENDER_STAGE_RANGES, launch_finalize(workspace, L, st), "tile ranges");
   TS_STAGE(RENDER_STAGE_RANGES, launch_tile_order(workspace, L, st), "tile order");
+  TS_STAGE(RENDER_STAGE_DEPTH_SORT, launch_tile_depth_sort(workspace, L, st), "depth order in tiles");
   TS_STAGE(RENDER_STAGE_COMPOSITE,
            params->window > 0 ? launch_composite_win(workspace, L, with_waves(*params), st)
            : multiwave(*params) ? launch_composite_mw(workspace, L, with_waves(*params), st)

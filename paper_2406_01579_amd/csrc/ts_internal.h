@@ -123,7 +123,7 @@ struct Layout {
   size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_pf_keep;   // pre-filter decisions, one bit per tet (PF_TILE / 32 words per block)
-  size_t o_vrec, o_count1, o_key1a, o_key1b, o_val1a, o_val1b, o_scan_part;
+  size_t o_vrec, o_count1, o_key1a, o_scan_part;   // key1a: depth float bits per record
   size_t o_rbox;   // per record: pixel rectangle (rx, ry), view, first entry (16 B)
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
@@ -160,7 +160,7 @@ hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int 
                              void* ws, const Layout& L, bool reset_header, hipStream_t st);
 hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hipStream_t st);
-hipError_t launch_sort_records(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_tile_depth_sort(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st);

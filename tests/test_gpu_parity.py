@@ -538,3 +538,42 @@ def test_training_record_grads_and_recomputed_state_shrink_the_workspace(trainin
         assert float(np.abs(a - b).max() / np.abs(b).max()) <= 1e-5, name
     refs = oracle_gradients(g, w.cams, oracle_params(Pm, 320.0), upix, vals.astype(np.float64))
     check_gradients(gm, refs, "training record grads + recomputed state")
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (32, 8)])
+def test_tile_lists_longer_than_the_lds_depth_sort(tile):
+    """A dense soup of 30,000 small tets: tiles with over 10,000 entries, more
+    than the per-tile depth sort holds in LDS (4096), so their runs are merged
+    in HBM (two merge rounds).  Tiling bit-exact, image and gradients against
+    the oracle."""
+    import torch
+    rng = np.random.default_rng(71)
+    K = 30000
+    centres = rng.normal(scale=0.04, size=(K, 1, 3))
+    verts = (centres + rng.normal(scale=0.04, size=(K, 4, 3))).reshape(-1, 3).astype(np.float32)
+    tets = np.arange(4 * K, dtype=np.int32).reshape(K, 4)
+    sdf = rng.uniform(-0.03, 0.02, size=4 * K).astype(np.float32)
+    colors = rng.uniform(0.0, 1.0, size=(4 * K, 3)).astype(np.float32)
+    s = 40.0
+    sc = synth.Scene(verts, tets, sdf, colors, s, "dense soup")
+    cam = synth.orbit_camera(0.7, 0.35, 2.5, 50.0, 64, 64, (0.1, 0.2, 0.3))[None]
+    P = _params("default", tile)
+    r, plan, imgs = gpu_forward(sc, cam, P)
+    d, tets_sorted = gpu_tiling(r, plan)
+    g = oracle.Geometry.of(sc)
+    op = oracle_params(P, s)
+    ref = oracle.binning(g, cam, op)
+    lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    print(f"soup {tile}: E={ref['E']}, longest list {lens.max()}, lists over 4096: {(lens > 4096).sum()}")
+    assert lens.max() > 3 * 4096
+    assert d["entries"] == ref["E"]
+    assert np.array_equal(d["tile_keys"], ref["tile"].astype(np.uint32))
+    assert np.array_equal(tets_sorted, ref["tet"])
+    assert np.array_equal(d["ranges"].astype(np.int64), ref["ranges"].astype(np.int64))
+    err, n_ex, n = compare_images(imgs, g, cam, op, s)
+    assert err <= IMG_TOL and n_ex <= max(1, int(1e-4 * n))
+    dout = rng.normal(size=(8, 64, 64)).astype(np.float32)
+    (dv, ds, dc), = r.backward(plan, [torch.from_numpy(dout).cuda()])
+    torch.cuda.synchronize()
+    refs = oracle_gradients(g, cam, op, oracle.all_pixels(cam), dout.reshape(8, -1).T.copy())
+    check_gradients((dv, ds, dc), refs, f"soup {tile}")
