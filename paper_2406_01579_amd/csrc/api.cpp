@@ -184,14 +184,12 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.entry_cap = entry_cap;
   L.pf_blocks = pf_blocks;
   L.scan_blocks_rec = (rec_cap + SCAN_TILE - 1) / SCAN_TILE;
-  int64_t smax = entry_cap;
-  if (det && 4 * kept_cap > smax) smax = 4 * kept_cap;
+  // the radix sort is left for the deterministic backward's corner sort
+  const int64_t smax = det ? 4 * kept_cap : 1;
   L.sort_blocks_max = (smax + SORT_TILE - 1) / SORT_TILE;
   L.total_tiles = tiles;
   L.total_pixels = pixels;
-  int kb = 1;
-  while (((int64_t)1 << kb) < tiles) ++kb;
-  L.key2_bits = kb;
+  L.tile_blocks = (tiles + 1023) / 1024;
   int vbits = 1;
   while (((int64_t)1 << vbits) < sumV) ++vbits;
   L.vkey_bits = vbits;
@@ -226,6 +224,8 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_val2a = take(4 * (size_t)entry_cap);
   L.o_val2b = take(4 * (size_t)entry_cap);
   L.o_eflag = take((size_t)entry_cap + 16);  // padded: the vertex backward reads aligned 8-byte words
+  L.o_tile_cnt = take(4 * (size_t)tiles);
+  L.o_tile_bsum = take(4 * (size_t)(L.tile_blocks + 1));   // right after the counts: cleared together
   L.o_ranges = take(8 * (size_t)tiles);
   L.o_tile_hist = take(4 * 2 * (size_t)TILE_BUCKETS);  // right after the ranges: cleared together
   L.o_tile_order = take(sizeof(TileSlot) * (size_t)tiles);
@@ -478,10 +478,8 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
            "upload descriptors");
   TS_STAGE(RENDER_STAGE_PREFILTER, launch_prefilter(workspace, L, *params, st), "pre-filter");
   TS_STAGE(RENDER_STAGE_PROJECT, launch_project(workspace, L, *params, st), "project");
-  TS_STAGE(RENDER_STAGE_SCAN, launch_count_scan(workspace, L, st), "count scan");
+  TS_STAGE(RENDER_STAGE_SCAN, launch_count_scan(workspace, L, *params, st), "count scan and tile lists");
   TS_STAGE(RENDER_STAGE_EMIT, launch_emit(workspace, L, *params, st), "emit");
-  TS_STAGE(RENDER_STAGE_TILE_SORT, launch_sort_entries(workspace, L, st), "tile sort");
-  TS_STAGE(RENDER_STAGE_RANGES, launch_finalize(workspace, L, st), "tile ranges");
   TS_STAGE(RENDER_STAGE_RANGES, launch_tile_order(workspace, L, st), "tile order");
   TS_STAGE(RENDER_STAGE_DEPTH_SORT, launch_tile_depth_sort(workspace, L, st), "depth order in tiles");
   TS_STAGE(RENDER_STAGE_COMPOSITE,

@@ -315,6 +315,21 @@ __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2
   uint4* rbox = at<uint4>(ws, L.o_rbox);
   __shared__ uint4 sbuf[256 * PROJ_STRIDE];
   __shared__ uint32_t svalid[256];
+  {
+    // the per-tile entry counters and tile-block sums, the dispatch-order
+    // histograms and cursors (forward and backward) start cleared for the
+    // binning kernels that follow
+    const uint64_t nb = (uint64_t)gridDim.x * gridDim.y, b = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    uint32_t* tcnt = at<uint32_t>(ws, L.o_tile_cnt);
+    const uint64_t ncnt = (L.o_tile_bsum - L.o_tile_cnt) / 4 + (uint64_t)L.tile_blocks;
+    for (uint64_t i = b * 256 + threadIdx.x; i < ncnt; i += nb * 256) tcnt[i] = 0u;
+    if (b == 0) {
+      uint32_t* th = at<uint32_t>(ws, L.o_tile_hist);
+      for (int i = threadIdx.x; i < 2 * TILE_BUCKETS; i += 256) th[i] = 0u;
+      uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
+      for (int i = threadIdx.x; i < TILE_BUCKETS; i += 256) bh[i] = 0u;
+    }
+  }
   const int v = blockIdx.y;
   const DevView V = vw[v];
   const int n = kcount[V.scene];
@@ -415,29 +430,141 @@ hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hip
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of the tile counts in record order -> entry offsets
+// a3-a5a: binning.  Records are taken in record order (per view ascending
+// kept slot, i.e. ascending tet id), SCAN_TILE at a time.  Two counts come
+// out of one pass over every record's (record, tile) entries: the entries
+// per record (their exclusive scan is each record's first entry: the slot of
+// its per-(record, tile) gradient) and the entries per tile.  The tiles'
+// exclusive scan is where each tile's list starts; the emit kernel then
+// places every entry in its tile's list through a per-tile cursor.  The
+// order inside a list is left to the atomics: the per-tile depth sort that
+// follows imposes the final order.  Entries of one wave that share a tile
+// (neighbouring records touch neighbouring tiles) are combined first, so
+// each wave issues one global atomic per distinct tile, all at once.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scan_reduce(void* ws, Layout L) {
+// The wave's lanes with `active` set, grouped by tile: returns the lane's
+// place in its group; *lead is the group's first lane and *cnt (in that lane
+// only, else 0) the group's size.  Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_group_by_tile(uint32_t tile, bool active, int* lead, uint32_t* cnt) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint64_t pending = __ballot(active);
+  uint32_t off = 0;
+  *lead = lane;
+  *cnt = 0u;
+  while (pending != 0ull) {
+    const int l0 = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t t0 = (uint32_t)__shfl((int)tile, l0, 64);
+    const uint64_t m = __ballot(active && tile == t0) & pending;
+    if ((m >> lane) & 1ull) {
+      *lead = l0;
+      off = (uint32_t)__popcll(m & lt);
+    }
+    if (lane == l0) *cnt = (uint32_t)__popcll(m);
+    pending &= ~m;
+  }
+  return off;
+}
+
+// Round k of a block's entries: entry e = e0 + 256 k + threadIdx.x for every
+// thread (active if e < ne) -- its record (binary search over the block's
+// record offsets loff) and tile.
+__device__ __forceinline__ void block_entry(const uint32_t* loff, uint32_t m, uint32_t q0, uint32_t e,
+                                            const uint4* __restrict__ rbox, const DevView* __restrict__ vw,
+                                            int tw_log2, int th_log2, uint32_t& r, uint32_t& tile) {
+  int k = 0;
+#pragma unroll
+  for (int step = SCAN_TILE / 2; step > 0; step >>= 1) {
+    const int k2 = k + step;
+    k = (k2 < (int)m && loff[k2] <= e) ? k2 : k;
+  }
+  r = q0 + (uint32_t)k;
+  const uint4 bx = rbox[r];   // rectangle and view
+  const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu);
+  const DevView& V = vw[bx.z];
+  const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
+  const int nx = tx1 - tx0 + 1;
+  const uint32_t j = e - loff[k];
+  const int ty = ty0 + (int)(j / (uint32_t)nx), tx = tx0 + (int)(j % (uint32_t)nx);
+  tile = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+}
+
+// The block's records: counts, their exclusive scan (loff) and the total.
+__device__ __forceinline__ uint32_t block_record_offsets(const uint32_t* __restrict__ count1, uint32_t q0, uint32_t m,
+                                                         uint32_t* loff, uint32_t* lds, uint32_t (&c)[SCAN_TILE / 256]) {
+  constexpr int PER = SCAN_TILE / 256;
+  const int t = threadIdx.x;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t k = (uint32_t)(t * PER + i);
+    c[i] = k < m ? count1[q0 + k] : 0u;
+    sum += c[i];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan_256(sum, lds, &tot);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    loff[t * PER + i] = run;
+    run += c[i];
+  }
+  __syncthreads();
+  return tot;
+}
+
+// per SCAN_TILE records: the block's entry total, and its entries counted per
+// tile
+__global__ __launch_bounds__(256) void k_scan_reduce(void* ws, Layout L, int tw_log2, int th_log2) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
+  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
   uint32_t* part = at<uint32_t>(ws, L.o_scan_part);
+  uint32_t* tcnt = at<uint32_t>(ws, L.o_tile_cnt);
+  __shared__ uint32_t loff[SCAN_TILE];
   __shared__ uint32_t lds[8];
   const uint32_t n = hdr->records_total;
   const uint32_t q0 = blockIdx.x * SCAN_TILE;
   if (q0 >= n) return;
-  uint32_t sum = 0;
-  for (uint32_t q = q0 + threadIdx.x; q < min(n, q0 + SCAN_TILE); q += 256) sum += count1[q];
-  uint32_t tot;
-  block_exclusive_scan_256(sum, lds, &tot);
+  const uint32_t m = min((uint32_t)SCAN_TILE, n - q0);
+  uint32_t c[SCAN_TILE / 256];
+  const uint32_t tot = block_record_offsets(count1, q0, m, loff, lds, c);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  for (uint32_t e0 = 0; e0 < tot; e0 += 256u) {
+    const uint32_t e = e0 + threadIdx.x;
+    const bool active = e < tot;
+    uint32_t r = 0, tile = 0;
+    if (active) block_entry(loff, m, q0, e, rbox, vw, tw_log2, th_log2, r, tile);
+    int lead;
+    uint32_t cnt;
+    wave_group_by_tile(tile, active, &lead, &cnt);
+    if (cnt) atomicAdd(&tcnt[tile], cnt);
+  }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_spine(void* ws, Layout L) {
-  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
-  uint32_t* part = at<uint32_t>(ws, L.o_scan_part);
-  __shared__ unsigned long long lp[1024];
-  const uint32_t n = hdr->records_total;
-  const int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
+// per 1024 tiles: the entry total of the block's tiles (for the spine)
+__global__ __launch_bounds__(1024) void k_tile_block_sum(void* ws, Layout L) {
+  const uint32_t* tcnt = at<const uint32_t>(ws, L.o_tile_cnt);
+  uint32_t* tbsum = at<uint32_t>(ws, L.o_tile_bsum);
+  __shared__ uint32_t lds[16];
+  const uint32_t t = blockIdx.x * 1024u + threadIdx.x;
+  uint32_t x = t < (uint32_t)L.total_tiles ? tcnt[t] : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sum = 0;
+    for (int w = 0; w < 16; ++w) sum += lds[w];
+    tbsum[blockIdx.x] = sum;
+  }
+}
+
+// one block: exclusive scans of the record-block entry totals (the blocks'
+// first entries) and of the tile-block entry totals (the tile blocks' first
+// list places), the entry total and the capacity check
+__device__ __forceinline__ void spine_scan_1024(uint32_t* part, int nb, unsigned long long* lp,
+                                                unsigned long long* total) {
   const int per = (nb + 1023) / 1024;
   const int t = threadIdx.x;
   unsigned long long sum = 0;
@@ -456,8 +583,18 @@ __global__ __launch_bounds__(1024) void k_scan_spine(void* ws, Layout L) {
     part[i] = (uint32_t)run;
     run += c;
   }
-  if (t == 1023) {
-    unsigned long long total = lp[1023];
+  *total = lp[1023];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_scan_spine(void* ws, Layout L) {
+  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+  __shared__ unsigned long long lp[1024];
+  const uint32_t n = hdr->records_total;
+  unsigned long long total, ttotal;
+  spine_scan_1024(at<uint32_t>(ws, L.o_scan_part), (int)((n + SCAN_TILE - 1) / SCAN_TILE), lp, &total);
+  spine_scan_1024(at<uint32_t>(ws, L.o_tile_bsum), (int)L.tile_blocks, lp, &ttotal);
+  if (threadIdx.x == 0) {
     uint32_t E = total > (unsigned long long)L.entry_cap ? (uint32_t)L.entry_cap : (uint32_t)total;
     if (total > (unsigned long long)L.entry_cap) hdr->overflow |= 2u;
     hdr->entries_total = E;
@@ -465,43 +602,76 @@ __global__ __launch_bounds__(1024) void k_scan_spine(void* ws, Layout L) {
   }
 }
 
-hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st) {
+// per 1024 tiles: each tile's list [start, end) (clamped to the entry
+// capacity; (0, 0) when empty), its cursor (the list start, for the emit
+// kernel), and the dispatch-order histogram of the list lengths
+__device__ __forceinline__ uint32_t block_exclusive_scan_1024(uint32_t v, uint32_t* lds /*[16]*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int w = 0; w < wave; ++w) wbase += lds[w];
+  __syncthreads();
+  return wbase + x - v;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_lists(void* ws, Layout L) {
+  uint32_t* tcnt = at<uint32_t>(ws, L.o_tile_cnt);
+  const uint32_t* tbpre = at<const uint32_t>(ws, L.o_tile_bsum);
+  uint32_t* ranges = at<uint32_t>(ws, L.o_ranges);
+  uint32_t* hist = at<uint32_t>(ws, L.o_tile_hist);
+  __shared__ uint32_t lds[16];
+  __shared__ uint32_t hb[TILE_BUCKETS];
+  if (threadIdx.x < TILE_BUCKETS) hb[threadIdx.x] = 0u;
+  const uint64_t cap = (uint64_t)L.entry_cap;
+  const uint32_t t = blockIdx.x * 1024u + threadIdx.x;
+  const bool in = t < (uint32_t)L.total_tiles;
+  const uint32_t c = in ? tcnt[t] : 0u;
+  const uint64_t start = (uint64_t)tbpre[blockIdx.x] + block_exclusive_scan_1024(c, lds);
+  if (in) {
+    uint32_t s0 = (uint32_t)min(start, cap), s1 = (uint32_t)min(start + c, cap);
+    if (s0 == s1) s0 = s1 = 0u;   // an empty list is (0, 0)
+    ranges[2 * (size_t)t] = s0;
+    ranges[2 * (size_t)t + 1] = s1;
+    tcnt[t] = (uint32_t)min(start, (uint64_t)0xffffffffu);   // the emit kernel's cursor
+    atomicAdd(&hb[len_bucket(s1 - s0)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < TILE_BUCKETS && hb[threadIdx.x]) atomicAdd(&hist[threadIdx.x], hb[threadIdx.x]);
+}
+
+hipError_t launch_count_scan(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  int twl = __builtin_ctz((unsigned)p.tile_w), thl = __builtin_ctz((unsigned)p.tile_h);
   unsigned nb = (unsigned)L.scan_blocks_rec;
   // per-record offsets are finished inside the emit kernel
-  k_scan_reduce<<<nb, 256, 0, st>>>(ws, L);
+  k_scan_reduce<<<nb, 256, 0, st>>>(ws, L, twl, thl);
+  if (L.total_tiles > 0) k_tile_block_sum<<<(unsigned)L.tile_blocks, 1024, 0, st>>>(ws, L);
   k_scan_spine<<<1, 1024, 0, st>>>(ws, L);
+  if (L.total_tiles > 0) k_tile_lists<<<(unsigned)L.tile_blocks, 1024, 0, st>>>(ws, L);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// a4: duplicate each record once per overlapped tile, in record order (per
-// view, ascending kept slot, i.e. ascending tet id); key = global tile id,
-// value = record
+// a4: duplicate each record once per overlapped tile into the tile's list:
+// per SCAN_TILE records, each record's first entry into its box, then the
+// block's entries placed through the per-tile cursors (key = global tile id,
+// value = record); places past the entry capacity are dropped (the overflow
+// is flagged)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, int th_log2) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   uint4* rbox = at<uint4>(ws, L.o_rbox);
-  uint32_t* key2 = at<uint32_t>(ws, L.o_key2a);
-  uint32_t* val2 = at<uint32_t>(ws, L.o_val2a);
-  // the tile ranges and the tile-length histogram (adjacent) start cleared
-  // for the range and dispatch-order kernels after the tile sort
-  {
-    uint32_t* clr = at<uint32_t>(ws, L.o_ranges);
-    const uint64_t nclr = (L.o_tile_hist - L.o_ranges) / 4 + 2 * (uint64_t)TILE_BUCKETS;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nclr; i += (uint64_t)gridDim.x * blockDim.x)
-      clr[i] = 0u;
-    // and the backward-order histogram the forward compositing kernel fills
-    uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (uint32_t)TILE_BUCKETS; i += gridDim.x * blockDim.x)
-      bh[i] = 0u;
-  }
-  // one SCAN_TILE block of records at a time: its records' entry offsets
-  // (the block's exclusive prefix from the spine plus a block scan of the
-  // tile counts), each record's first entry into its box, then the block's
-  // entries with consecutive threads on consecutive entries (the record of an
-  // entry by binary search over the offsets)
+  uint32_t* cursor = at<uint32_t>(ws, L.o_tile_cnt);
+  uint32_t* key2 = at<uint32_t>(ws, sorted_tile_keys(L));
+  uint32_t* val2 = at<uint32_t>(ws, sorted_entry_records(L));
   constexpr int PER = SCAN_TILE / 256;
   __shared__ uint32_t loff[SCAN_TILE];
   __shared__ uint32_t lds[8];
@@ -513,42 +683,27 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const uint32_t q0 = blk * SCAN_TILE;
     const uint32_t m = min((uint32_t)SCAN_TILE, n - q0);
-    uint32_t c[PER], rr[PER], sum = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const uint32_t k = (uint32_t)(t * PER + i);
-      rr[i] = q0 + k;
-      c[i] = k < m ? count1[rr[i]] : 0u;
-      sum += c[i];
-    }
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan_256(sum, lds, &tot);
+    uint32_t c[PER];
+    const uint32_t tot = block_record_offsets(count1, q0, m, loff, lds, c);
     const uint32_t base = part[blk];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      loff[t * PER + i] = run;
-      if (c[i] != 0u) rbox[rr[i]].w = base + run;
-      run += c[i];
-    }
-    __syncthreads();
-    const uint32_t ne = (uint64_t)base + tot <= cap ? tot : (base < cap ? (uint32_t)(cap - base) : 0u);
-    for (uint32_t e = (uint32_t)t; e < ne; e += 256u) {
-      int k = 0;
-#pragma unroll
-      for (int step = SCAN_TILE / 2; step > 0; step >>= 1) {
-        const int k2 = k + step;
-        k = (k2 < (int)m && loff[k2] <= e) ? k2 : k;
+    for (int i = 0; i < PER; ++i)
+      if (c[i] != 0u) rbox[q0 + (uint32_t)(t * PER + i)].w = base + loff[t * PER + i];
+    for (uint32_t e0 = 0; e0 < tot; e0 += 256u) {
+      const uint32_t e = e0 + (uint32_t)t;
+      const bool active = e < tot;
+      uint32_t r = 0, tile = 0;
+      if (active) block_entry(loff, m, q0, e, rbox, vw, tw_log2, th_log2, r, tile);
+      int lead;
+      uint32_t cnt;
+      const uint32_t off = wave_group_by_tile(tile, active, &lead, &cnt);
+      uint32_t gb = cnt ? atomicAdd(&cursor[tile], cnt) : 0u;
+      gb = (uint32_t)__shfl((int)gb, lead, 64);
+      const uint64_t pos = (uint64_t)gb + off;
+      if (active && pos < cap) {
+        key2[pos] = tile;
+        val2[pos] = r;
       }
-      const uint32_t r = q0 + (uint32_t)k;
-      const uint4 bx = rbox[r];   // rectangle and view (the first entry is not read here)
-      const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu);
-      const DevView& V = vw[bx.z];
-      const int tx0 = i0 >> tw_log2, tx1 = i1 >> tw_log2, ty0 = j0 >> th_log2;
-      const int nx = tx1 - tx0 + 1;
-      const uint32_t j = e - loff[k];
-      const int ty = ty0 + (int)(j / (uint32_t)nx), tx = tx0 + (int)(j % (uint32_t)nx);
-      key2[base + e] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
-      val2[base + e] = r;
     }
     __syncthreads();
   }
@@ -561,32 +716,6 @@ hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// a6: tile ranges, record of each sorted entry, inverse permutation
-// ---------------------------------------------------------------------------
-__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-__global__ __launch_bounds__(256) void k_finalize(void* ws, Layout L) {
-  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
-  const uint32_t* keys = at<const uint32_t>(ws, sorted_tile_keys(L));
-  uint32_t* ranges = at<uint32_t>(ws, L.o_ranges);
-  const uint32_t n = hdr->entries_total;
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    const uint32_t t = keys[p];
-    if (p == 0 || keys[p - 1] != t) ranges[2 * (size_t)t] = p;
-    if (p + 1 == n || keys[p + 1] != t) ranges[2 * (size_t)t + 1] = p + 1;
-  }
-}
-
-hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
-  // ranges and the tile-length histogram were cleared by the emit kernel
-  k_finalize<<<2048, 256, 0, st>>>(ws, L);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // dispatch order of the compositing workgroups: tiles with the longest lists
 // first (bucketed by the list length: four buckets per power of two), so the
 // longest sequential walks start in the first scheduling round.  The forward
@@ -594,18 +723,6 @@ hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st) {
 // walked before every pixel of the tile stopped.  The order inside a bucket is
 // whatever the atomics give; results do not depend on it.
 // ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_tile_hist(void* ws, Layout L) {
-  const uint32_t* ranges = at<const uint32_t>(ws, L.o_ranges);
-  uint32_t* hist = at<uint32_t>(ws, L.o_tile_hist);
-  __shared__ uint32_t h[TILE_BUCKETS];
-  if (threadIdx.x < TILE_BUCKETS) h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  if (t < (uint32_t)L.total_tiles) atomicAdd(&h[len_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
-  __syncthreads();
-  if (threadIdx.x < TILE_BUCKETS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
-}
 
 // Every scatter block: first[b] = the number of tiles in buckets above b
 // (longest first), from the complete histogram; the block's tiles of bucket
@@ -653,7 +770,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
 hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
-  k_tile_hist<<<nb, 256, 0, st>>>(ws, L);
+  // the length histogram was counted by k_tile_lists
   k_tile_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }
@@ -820,15 +937,6 @@ hipError_t launch_tile_depth_sort(void* ws, const Layout& L, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st) {
-  uint32_t *ko, *vo;
-  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
-  // the entries are the larger sort: 8 keys per thread (longer digit runs
-  // per block, half the blocks for the spine)
-  return radix_sort_pairs(at<uint32_t>(ws, L.o_key2a), at<uint32_t>(ws, L.o_val2a), at<uint32_t>(ws, L.o_key2b),
-                          at<uint32_t>(ws, L.o_val2b), false, &hdr->entries_total, L.entry_cap, L.key2_bits,
-                          at<uint32_t>(ws, L.o_hist), L.sort_blocks_max, st, &ko, &vo, 8);
-}
 
 // ---------------------------------------------------------------------------
 // gradient buffers are overwritten: clear them first

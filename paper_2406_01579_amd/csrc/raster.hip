@@ -380,6 +380,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
       unpack_rect(R, i0, i1, j0, j1);
       const int tx0 = i0 / TW, ty0 = j0 / TH, nx = i1 / TW - tx0 + 1;
       const size_t d = (size_t)R.entry0 + (size_t)((c.ty - ty0) * nx + (c.tx - tx0));
+      if (d >= (size_t)L.entry_cap) continue;   // an overflowed forward's entry
       tgrad[d * TGRAD_STRIDE + k] = gacc[e][k];
       if (k == 0) eflag[d] = 1;
     }

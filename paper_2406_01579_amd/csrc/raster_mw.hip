@@ -455,7 +455,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       }
       __syncthreads();
     }
-    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, record_grads(L) ? srec + base : nullptr);
+    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, (uint64_t)L.entry_cap,
+                      record_grads(L) ? srec + base : nullptr);
   }
 }
 

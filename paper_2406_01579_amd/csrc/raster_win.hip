@@ -414,7 +414,8 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))
       if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
     }
     __syncthreads();
-    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, record_grads(L) ? srec + base : nullptr);
+    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, (uint64_t)L.entry_cap,
+                      record_grads(L) ? srec + base : nullptr);
   }
 }
 

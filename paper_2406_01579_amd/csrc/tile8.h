@@ -61,9 +61,11 @@ __device__ __forceinline__ Tile8 tile8(const DevView* vw, const TileSlot* slots)
 // tile's row-major index inside the record's tile rectangle; the slot is
 // flagged as reached.  With chunk_rec (the chunk's record indices) it is
 // added into its record's accumulator instead.
+// (A slot past the entry capacity belongs to an overflowed forward, whose
+// outputs are invalid anyway: it is skipped.)
 __device__ __forceinline__ void store_entry_grads(const ViewRec* recs, const float (*gacc)[TGRAD_STRIDE], int n,
                                                   const Tile8& c, float* __restrict__ tgrad,
-                                                  uint8_t* __restrict__ eflag, int nthreads,
+                                                  uint8_t* __restrict__ eflag, int nthreads, uint64_t cap,
                                                   const uint32_t* __restrict__ chunk_rec = nullptr) {
   if (chunk_rec) {
     for (int q = threadIdx.x; q < n * (TGRAD_STRIDE - 1); q += nthreads) {
@@ -80,6 +82,7 @@ __device__ __forceinline__ void store_entry_grads(const ViewRec* recs, const flo
     unpack_rect(R, i0, i1, j0, j1);
     const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
     const size_t d = (size_t)R.entry0 + (size_t)((c.ty - ty0) * nx + (c.tx - tx0));
+    if (d >= cap) continue;
     tgrad[d * TGRAD_STRIDE + k] = gacc[e][k];
     if (k == 0) eflag[d] = 1;
   }

@@ -118,7 +118,7 @@ struct Layout {
   int flags;            // render_params.flags of the call
   int64_t kept_cap, rec_cap, entry_cap;
   int64_t pf_blocks, scan_blocks_rec, sort_blocks_max, total_tiles, total_pixels;
-  int key2_bits;
+  int64_t tile_blocks;   // blocks of 1024 tiles (the tile-list scan)
   int max_scene_views;  // largest number of views of one scene
   size_t o_hdr, o_scene, o_view, o_scene_views, o_view_rec_base, o_scene_kept_base, o_scene_kept_count;
   size_t o_pf_cnt, o_kept_tet, o_trec;
@@ -128,6 +128,7 @@ struct Layout {
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
   size_t o_ranges, o_tile_hist, o_tile_order, o_tgrad, o_last, o_tlast;
+  size_t o_tile_cnt, o_tile_bsum;   // entries per tile (then the emit cursor); per 1024-tile block, its start
   size_t o_tile_pend;    // per dispatch slot: end of the entries the forward blended (backward walk)
   size_t o_bwd_hist, o_bwd_order, o_bwd_pend;  // backward dispatch order (by walked length)
   size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
@@ -141,14 +142,11 @@ struct Layout {
 bool plan_layout(const render_scene* scenes, int ns, const render_view* views, int nv, const render_params* p,
                  int64_t kept_cap, int64_t entry_cap, Layout& L, const char** why);
 
-// after the tile sort (ceil(key2_bits / 8) passes, ping-pong a -> b -> a ...)
-// the sorted tile keys and their records live in one of the two buffers
-inline __host__ __device__ size_t sorted_tile_keys(const Layout& L) {
-  return (((L.key2_bits + SORT_BITS - 1) / SORT_BITS) & 1) ? L.o_key2b : L.o_key2a;
-}
-inline __host__ __device__ size_t sorted_entry_records(const Layout& L) {
-  return (((L.key2_bits + SORT_BITS - 1) / SORT_BITS) & 1) ? L.o_val2b : L.o_val2a;
-}
+// the tile lists: entries placed per tile by the emit kernel (tile keys and
+// records), then put in depth order inside each tile; the other buffer pair
+// is the depth sort's scratch
+inline __host__ __device__ size_t sorted_tile_keys(const Layout& L) { return L.o_key2a; }
+inline __host__ __device__ size_t sorted_entry_records(const Layout& L) { return L.o_val2a; }
 
 template <class T>
 __host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
@@ -161,10 +159,8 @@ hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int 
 hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_tile_depth_sort(void* ws, const Layout& L, hipStream_t st);
-hipError_t launch_count_scan(void* ws, const Layout& L, hipStream_t st);
+hipError_t launch_count_scan(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st);
-hipError_t launch_sort_entries(void* ws, const Layout& L, hipStream_t st);
-hipError_t launch_finalize(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st);
 constexpr int TILE_BUCKETS = 129;  // tiles bucketed by list length, four buckets per power of two
 hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st);
