@@ -27,17 +27,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd Mpixels/s (64³ grid, 512², 4 views) + p99 latency vs plain path"
 HBM_PEAK_GBS = 8000.0
-REC_BYTES = 128          # one ViewRec per tile entry
-ENTRY_LIST_BYTES = 4     # sorted record index per entry
-TGRAD_BYTES = 96         # per-entry screen-space gradient written by the backward
-FIRST_ENTRY_BYTES = 4    # the record's first-entry offset, read per walked entry by the backward
+CU_NUM, CLOCK_GHZ = 256, 2.4
+LDS_PEAK_GBS = 128 * CU_NUM * CLOCK_GHZ   # 128 B per clock per CU
+# Algorithmic bytes of the compositing kernels in the per-unit terms of the
+# hot-path measurement plan: a record of R_B bytes plus its 4-byte list
+# index per entry walked, 40 B per pixel (8 output channels + 8 B of state),
+# and for the backward 2 x 92 B per (view, kept tet) for the per-tet gradient
+# written and read back.
+R_B = 96
+ENTRY_INDEX_B = 4
+PIXEL_B = 40
+TET_GRAD_RW_B = 2 * 92
 # HBM bytes per launch of the compositing kernels at the default workload and
 # launch shape (8x8 tiles, 4 waves), from the rocprofv3 FETCH_SIZE /
 # WRITE_SIZE passes summarised under profiles/ (FETCH_SIZE scaled by 2.0,
-# WRITE_SIZE by 1.0 against a 256 MiB copy), and their VALU issue share: wave
-# instructions (SQ_INSTS_VALU) x 4 cycles over 1024 SIMDs x 2.4 GHz x the
-# kernel's mean duration.  Valid only for the kernel sources with these
-# digests; reported as null once they change.
+# WRITE_SIZE by 1.0 against a 256 MiB copy); their VALU issue share (wave
+# instructions SQ_INSTS_VALU x 4 cycles over 1024 SIMDs x 2.4 GHz x the
+# kernel's mean duration); LDS busy share (LdsUtil: SQ_LDS_IDX_ACTIVE over
+# CU cycles), the LDS bandwidth that busy time carries at 128 B per clock
+# (bank-conflict cycles excluded) and the mean occupancy (OccupancyPercent:
+# SQ_WAVE_CYCLES over 32 waves per CU).  Valid only for the kernel sources
+# with these digests; reported as null once they change.
 MEASURED = {"sha256": {"paper_2406_01579_amd/csrc/raster_mw.hip":
                        "5a07851a5d59b429a53563e0eb7f25d23bec7267145360d27790e6d4b727ac5c",
                        "paper_2406_01579_amd/csrc/ts_device.h":
@@ -76,6 +86,12 @@ def parse():
     ap.add_argument("--window-bench", type=int, default=5,
                     help="also time the step with the per-pixel resort window of this size (0: skip)")
     ap.add_argument("--cpu-pixels", type=int, default=400000)
+    ap.add_argument("--cpu-pixels-1core", type=int, default=25000,
+                    help="pixels of the oracle timed on one host thread (a sample of the same workload)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving trace of the default run")
+    ap.add_argument("--serve-trace-rate", type=float, default=1000.0,
+                    help="arrival rate of the default run's short serving trace (req/s)")
+    ap.add_argument("--serve-trace-seconds", type=float, default=1.5)
     ap.add_argument("--workload", default="training", choices=["training", "batched", "multiscene"],
                     help="batched: 128^3 band grid, 8 views at 1024^2; multiscene: 32 scenes, 124 mixed views "
                          "(fwd+bwd of every view in one graph-captured launch sequence vs one per view)")
@@ -239,10 +255,12 @@ def main():
     bwd_ms, bwd_n = stages["composite_bwd"]
     fwd_avg = comp_ms / max(comp_n, 1)
     bwd_avg = bwd_ms / max(bwd_n, 1)
-    # algorithmic HBM bytes per launch (one launch covers all 4 views)
-    fwd_bytes = (REC_BYTES + ENTRY_LIST_BYTES) * E + 8 * tiles + (32 + 8) * pixels
-    bwd_bytes = ((REC_BYTES + ENTRY_LIST_BYTES + FIRST_ENTRY_BYTES + TGRAD_BYTES) * e_proc + 8 * tiles + 4 * tiles
-                 + (32 + 8) * pixels)
+    # algorithmic HBM bytes per launch (one launch covers all 4 views): the
+    # per-unit terms of the measurement plan times the entries (walked, for
+    # the backward), pixels and (view, kept tet) records of this launch
+    K_rec = int(stt.records)
+    fwd_bytes = (R_B + ENTRY_INDEX_B) * E + PIXEL_B * pixels
+    bwd_bytes = (R_B + ENTRY_INDEX_B) * e_proc + PIXEL_B * pixels + TET_GRAD_RW_B * K_rec
     kern = {
         "composite": dict(ms=fwd_avg, bytes=fwd_bytes),
         "composite_bwd": dict(ms=bwd_avg, bytes=bwd_bytes),
@@ -250,13 +268,25 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     ach = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
     meas = measured_counters(dom, args)
+
+    def mget(key):
+        return None if meas is None or key not in meas else meas[key]
+    lds = None
+    if mget("lds_util") is not None:
+        lds_gbs = mget("lds_active_bytes") / (kern[dom]["ms"] * 1e-3) / 1e9
+        lds = {"achieved": round(lds_gbs, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
+               "frac": round(lds_gbs / LDS_PEAK_GBS, 4), "busy_frac": mget("lds_util"),
+               "bank_conflict_frac": mget("lds_bank_conflict_frac")}
     roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None if meas is None else int(meas["traffic"]),
                 "kernel": dom, "kernel_ms": round(kern[dom]["ms"], 4), "algorithmic_bytes": int(kern[dom]["bytes"]),
-                "valu_issue_frac": None if meas is None else meas["valu_issue_frac"],
-                "note": "the compositing kernels move about their algorithmic bytes (traffic) but are bound by the "
-                        "per-tile sequential walk and its issue latency, not HBM: valu_issue_frac is the VALU issue "
-                        "share from SQ_INSTS_VALU"}
+                "bytes_per_unit": {"entry_walked": R_B + ENTRY_INDEX_B, "pixel": PIXEL_B,
+                                   "view_kept_tet": TET_GRAD_RW_B if dom == "composite_bwd" else 0},
+                "valu_issue_frac": mget("valu_issue_frac"),
+                "lds": lds,
+                "occupancy_pct": mget("occupancy_pct"),
+                "note": "the compositing kernels are bound by the per-tile sequential walk (dependent chunk phases) "
+                        "and VALU issue, not HBM; traffic is the HBM bytes the counters saw per launch"}
 
     # plain path: one launch sequence per view
     plain = None
@@ -290,9 +320,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_trace(args)
+
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(sc, cams, args.s, args.cpu_pixels)
+        cpu = cpu_baseline(sc, cams, args.s, args.cpu_pixels, args.cpu_pixels_1core)
 
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
@@ -310,6 +344,7 @@ def main():
         "plain_path": plain,
         "window_path": window,
         "roofline": roofline,
+        "serving": serving,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items()},
         "workload_stats": {"entries": E, "entries_walked_bwd": e_proc, "kept_tets": int(stt.kept),
@@ -477,27 +512,86 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(sc, cams, s, npix):
+def serve_trace(args):
+    """A short serving trace of the serving workload (16 resident blob scenes,
+    32^3..128^3 cube grids; requests of 1-4 views at 256/512/1024 square;
+    open-loop Poisson arrivals; forward only): continuous batching over two
+    streams against the plain path (FIFO, one launch sequence per view) on
+    the same trace."""
+    import torch
+
+    import synth
+    from paper_2406_01579_amd import Params
+    from paper_2406_01579_amd.serve import SceneRegistry, Server
+    t0 = time.perf_counter()
+    scenes = synth.serving_scenes(s=args.s)
+    reg = SceneRegistry(Params(waves=args.waves))
+    rng = np.random.default_rng(9)
+    for sc in scenes:
+        reg.add(sc, np.concatenate([synth.random_orbit_cameras(rng, 2, z) for z in (256, 512, 1024)], 0))
+    for batching in (True, False):
+        Server(reg, streams=args.serve_streams if batching else 1, batching=batching, keep_outputs=False).run(
+            synth.serving_requests(200, 1000.0, len(scenes), seed=99))
+    rate = args.serve_trace_rate
+    n = int(max(50, rate * args.serve_trace_seconds))
+    trace = synth.serving_requests(n, rate, len(scenes))
+    out = {"rate_per_s": rate, "requests": n, "streams": args.serve_streams,
+           "workload": "16 resident blob scenes (32^3..128^3), 1-4 views at 256/512/1024 square, Poisson "
+                       "arrivals, forward only"}
+    for name, batching in (("batched", True), ("plain", False)):
+        srv = Server(reg, streams=args.serve_streams if batching else 1, batching=batching, keep_outputs=False)
+        st = srv.run(trace)
+        out[name] = {k: round(st[k], 4) for k in ("p50_ms", "p99_ms", "mpix_per_s")}
+    out["setup_s"] = round(time.perf_counter() - t0, 1)
+    del reg
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sc, cams, s, npix, npix1):
     """The oracle as it stands, float32, forward + backward on a bounded
-    sample of pixels of the same workload (every k-th pixel of every view)."""
+    sample of pixels of the same workload (every k-th pixel of every view),
+    on all host threads and on one."""
     import oracle
     g = oracle.Geometry.of(sc)
     P = oracle.params_array(s)
     pix = oracle.all_pixels(cams)
-    step = max(1, pix.shape[0] // npix)
-    sample = np.ascontiguousarray(pix[::step][:npix])
-    rng = np.random.default_rng(0)
-    dout = rng.normal(size=(sample.shape[0], 8))
-    t0 = time.perf_counter()
-    oracle.render(g, cams, P, sample, prec=32)
-    t1 = time.perf_counter()
-    oracle.backward(g, cams, P, sample, dout, prec=32)
-    t2 = time.perf_counter()
-    secs = t2 - t0
-    return {"value": round(sample.shape[0] / secs / 1e6, 6), "unit": "Mpixels/s", "cores": oracle.num_threads(),
+
+    def run(n):
+        step = max(1, pix.shape[0] // n)
+        sample = np.ascontiguousarray(pix[::step][:n])
+        dout = np.random.default_rng(0).normal(size=(sample.shape[0], 8))
+        t0 = time.perf_counter()
+        oracle.render(g, cams, P, sample, prec=32)
+        t1 = time.perf_counter()
+        oracle.backward(g, cams, P, sample, dout, prec=32)
+        t2 = time.perf_counter()
+        return sample.shape[0], step, t1 - t0, t2 - t1
+
+    threads = oracle.num_threads()
+    n, step, tf, tb = run(npix)
+    oracle.set_threads(1)
+    n1, step1, tf1, tb1 = run(npix1)
+    oracle.set_threads(threads)
+    return {"value": round(n / (tf + tb) / 1e6, 6), "unit": "Mpixels/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{sample.shape[0]} pixels (every {step}th of the 4x512x512 views), float32 forward "
-                      f"({t1 - t0:.2f} s) + backward ({t2 - t1:.2f} s), per-pixel loop over every kept tet"}
+            "sample": f"{n} pixels (every {step}th of the 4x512x512 views), float32 forward ({tf:.2f} s) + "
+                      f"backward ({tb:.2f} s), per-pixel loop over every kept tet",
+            "single_core": {"value": round(n1 / (tf1 + tb1) / 1e6, 6), "unit": "Mpixels/s", "cores": 1,
+                            "sample": f"{n1} pixels (every {step1}th), forward {tf1:.2f} s + backward {tb1:.2f} s"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 if __name__ == "__main__":

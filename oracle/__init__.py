@@ -44,6 +44,7 @@ def lib():
             build(force=False)
         L = C.CDLL(_LIB)
         P = C.c_void_p
+        L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_render.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, P, C.c_long, P, P, P]
         L.oracle_render_dual.argtypes = [P, P, P, P, C.c_int, C.c_int, P, P, P, P, C.c_int, P, P, C.c_long, P, P]
         L.oracle_backward.argtypes = [C.c_int, P, P, P, P, C.c_int, C.c_int, P, C.c_int, P, P, C.c_long, P, P, P, P]
@@ -70,6 +71,11 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the count in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def _p(a):

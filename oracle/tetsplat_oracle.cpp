@@ -993,6 +993,17 @@ int oracle_num_threads(void) {
 #endif
 }
 
+// Threads of the oracle's parallel loops from now on (n >= 1).
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 int oracle_render(int prec, const double* verts, const int* tets, const double* sdf, const double* colors,
                   int V, int K, const float* cams, int nv, const float* params, const int* pix, long npix,
                   double* out, int* nblend, double* tfinal) {
