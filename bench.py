@@ -78,6 +78,11 @@ def parse():
     ap.add_argument("--tile", default="8x8")
     ap.add_argument("--waves", type=int, default=4, help="waves sharing one 8x8 tile")
     ap.add_argument("--check", default="lazy", choices=["sync", "lazy"])
+    ap.add_argument("--record-grads", action="store_true",
+                    help="backward with one gradient accumulator per record (RENDER_RECORD_GRADS)")
+    ap.add_argument("--recompute-state", action="store_true",
+                    help="no per-pixel state in the workspace; the backward recomputes it (RENDER_RECOMPUTE_STATE)")
+    ap.add_argument("--deterministic", action="store_true", help="fixed-order sums (RENDER_DETERMINISTIC)")
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"],
                     help="headline path: the whole fwd+bwd step captured once in a HIP graph and replayed, or "
                          "eager launches through the autograd Function")
@@ -146,7 +151,8 @@ def main():
     gen = torch.Generator(device=dev)
     gen.manual_seed(0)
     dout = torch.randn((nv, 8, H, W), device=dev, generator=gen)
-    params = Params(tile_w=tw, tile_h=th, waves=args.waves)
+    params = Params(tile_w=tw, tile_h=th, waves=args.waves, record_grads=args.record_grads,
+                    recompute_state=args.recompute_state, deterministic=args.deterministic)
     renderer = Renderer(params, device=dev, check=args.check)
 
     def step(cam_subset=None):
@@ -227,9 +233,13 @@ def main():
         del wstep
 
     # workload facts of the last forward (for the roofline)
-    plan = renderer.forward([SceneT(verts.detach(), st.tets, sdf.detach(), colors.detach(), args.s)], cams)
-    stt = renderer.read_status(plan)
-    dbg = renderer.debug(plan)
+    # (the per-pixel state comes from a forward that keeps it)
+    import dataclasses
+    stats_r = renderer if not args.recompute_state else Renderer(
+        dataclasses.replace(params, recompute_state=False), device=dev, check="sync")
+    plan = stats_r.forward([SceneT(verts.detach(), st.tets, sdf.detach(), colors.detach(), args.s)], cams)
+    stt = stats_r.read_status(plan)
+    dbg = stats_r.debug(plan)
     E = int(stt.entries)
     tiles = dbg["ranges"].shape[0]
     last = dbg["last"]
@@ -253,8 +263,12 @@ def main():
 
     comp_ms, comp_n = stages["composite"]
     bwd_ms, bwd_n = stages["composite_bwd"]
+    pg_ms, pg_n = stages["pair_grads"]
     fwd_avg = comp_ms / max(comp_n, 1)
-    bwd_avg = bwd_ms / max(bwd_n, 1)
+    # the backward compositing step runs as two kernels on the 8x8 multi-wave
+    # path (the walk with its recurrence, then the per-pair gradients): its
+    # duration is their sum per step
+    bwd_avg = bwd_ms / max(bwd_n, 1) + (pg_ms / pg_n if pg_n else 0.0)
     # algorithmic HBM bytes per launch (one launch covers all 4 views): the
     # per-unit terms of the measurement plan times the entries (walked, for
     # the backward), pixels and (view, kept tet) records of this launch
@@ -280,6 +294,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None if meas is None else int(meas["traffic"]),
                 "kernel": dom, "kernel_ms": round(kern[dom]["ms"], 4), "algorithmic_bytes": int(kern[dom]["bytes"]),
+                "kernels": ({"k_composite_bwd_mw": round(bwd_ms / max(bwd_n, 1), 4),
+                             "k_pair_grads": round(pg_ms / max(pg_n, 1), 4)}
+                            if dom == "composite_bwd" and pg_n else None),
                 "bytes_per_unit": {"entry_walked": R_B + ENTRY_INDEX_B, "pixel": PIXEL_B,
                                    "view_kept_tet": TET_GRAD_RW_B if dom == "composite_bwd" else 0},
                 "valu_issue_frac": mget("valu_issue_frac"),
@@ -337,7 +354,8 @@ def main():
                    "views": nv, "width": W, "height": H, "tile": args.tile, "waves": args.waves, "s": args.s,
                    "path": ("whole fwd+bwd step through the autograd Function captured in one HIP graph"
                             if args.mode == "graph" else "eager launches through the autograd Function"),
-                   "status_check": args.check},
+                   "status_check": args.check,
+                   "flags": [k for k in ("record_grads", "recompute_state", "deterministic") if getattr(args, k)]},
         "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
         "eager_path": eager,
         "graph": graph,
@@ -346,7 +364,7 @@ def main():
         "roofline": roofline,
         "serving": serving,
         "cpu_baseline": cpu,
-        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items()},
+        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
         "workload_stats": {"entries": E, "entries_walked_bwd": e_proc, "kept_tets": int(stt.kept),
                            "records": int(stt.records), "tiles": tiles},
     }

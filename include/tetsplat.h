@@ -254,14 +254,14 @@ enum {
   RENDER_STAGE_UPLOAD = 0,      /* descriptor upload (and header reset) */
   RENDER_STAGE_PREFILTER = 1,   /* alpha_max pre-filter, compaction, normals */
   RENDER_STAGE_PROJECT = 2,     /* per-view projection and tile counts */
-  RENDER_STAGE_DEPTH_SORT = 3,  /* radix sort of records by depth */
-  RENDER_STAGE_SCAN = 4,        /* scan of tile counts */
-  RENDER_STAGE_EMIT = 5,        /* tile-duplicated keys */
-  RENDER_STAGE_TILE_SORT = 6,   /* radix sort of entries by tile */
-  RENDER_STAGE_RANGES = 7,      /* tile ranges, entry records, dispatch orders (forward and backward) */
+  RENDER_STAGE_DEPTH_SORT = 3,  /* depth order inside every tile's list */
+  RENDER_STAGE_SCAN = 4,        /* entry counts per record and per tile, their scans, tile lists */
+  RENDER_STAGE_EMIT = 5,        /* entries placed into the tile lists */
+  RENDER_STAGE_PAIR_GRADS = 6,  /* backward: per-(entry, pixel) gradients summed per (tile, entry) */
+  RENDER_STAGE_RANGES = 7,      /* dispatch orders (forward and backward) */
   RENDER_STAGE_COMPOSITE = 8,   /* forward compositing */
   RENDER_STAGE_ZERO_GRADS = 9,  /* gradient buffer clear */
-  RENDER_STAGE_COMPOSITE_BWD = 10, /* reverse-order compositing backward */
+  RENDER_STAGE_COMPOSITE_BWD = 10, /* reverse-order compositing backward (walk and recurrence) */
   RENDER_STAGE_VERTEX_BWD = 11, /* per-record chain to vertices */
   RENDER_NSTAGES = 12
 };

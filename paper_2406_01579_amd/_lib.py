@@ -65,7 +65,7 @@ EXPORTS = ("render_workspace_size", "render_forward", "render_backward", "render
 STATIC_WORKSPACE_BYTES = 64 << 20
 STATUS_BYTES = 256
 
-STAGES = ("upload", "prefilter", "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "composite",
+STAGES = ("upload", "prefilter", "project", "depth_sort", "scan", "emit", "pair_grads", "ranges", "composite",
           "zero_grads", "composite_bwd", "vertex_bwd")
 
 

@@ -230,7 +230,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_tile_hist = take(4 * 2 * (size_t)TILE_BUCKETS);  // right after the ranges: cleared together
   L.o_tile_order = take(sizeof(TileSlot) * (size_t)tiles);
   L.o_tile_pend = take(4 * (size_t)tiles);
-  L.o_bwd_hist = take(4 * 2 * (size_t)TILE_BUCKETS);
+  L.o_bwd_hist = take(4 * (size_t)BWD_HIST_WORDS);
   L.o_bwd_order = take(sizeof(TileSlot) * (size_t)tiles);
   L.o_bwd_pend = take(4 * (size_t)tiles);
   // screen-space gradients: one per entry, or one accumulator per record
@@ -240,6 +240,17 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_last = keep_state ? take(4 * (size_t)pixels) : 0;
   L.o_tlast = keep_state ? take(4 * (size_t)pixels) : 0;
   L.o_wpair = p->window > 0 ? take(16 * 64 * (size_t)entry_cap) : 0;
+  const bool pairs_path = p->window == 0 && p->tile_w == 8 && p->tile_h == 8 && p->waves != 1;
+  if (pairs_path) {
+    if (tiles >= ((int64_t)1 << 25)) {   // a segment holds its backward slot in 25 bits
+      *why = "the multi-wave 8x8 path takes at most 2^25 tiles";
+      return false;
+    }
+    L.o_slot_pairs = take(8 * (size_t)tiles);
+    L.o_bwd_base = take(16 * (size_t)tiles);
+    L.o_pairs = take(16 * (size_t)entry_cap);   // at most entry_capacity blended pairs
+    L.o_segs = take(16 * (size_t)entry_cap);
+  }
   if (det) {
     const size_t nc = 4 * (size_t)kept_cap;
     L.o_vkey_a = take(4 * nc);
@@ -487,6 +498,9 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
            : multiwave(*params) ? launch_composite_mw(workspace, L, with_waves(*params), st)
                                 : launch_composite(workspace, L, *params, st),
            "composite");
+  // the backward's dispatch order, and the places of its per-pair terms
+  if (params->window == 0 && multiwave(*params))
+    TS_STAGE(RENDER_STAGE_RANGES, launch_bwd_order(workspace, L, st), "backward tile order");
   return RENDER_OK;
 }
 
@@ -517,13 +531,13 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
   TS_STAGE(RENDER_STAGE_ZERO_GRADS,
            launch_desc_zero_grads(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, st),
            "upload descriptors and zero gradients");
-  if (params->window == 0 && multiwave(*params))
-    TS_STAGE(RENDER_STAGE_RANGES, launch_bwd_order(workspace, L, st), "backward tile order");
   TS_STAGE(RENDER_STAGE_COMPOSITE_BWD,
            params->window > 0 ? launch_composite_backward_win(workspace, L, with_waves(*params), st)
            : multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)
                                 : launch_composite_backward(workspace, L, *params, st),
            "composite backward");
+  if (params->window == 0 && multiwave(*params))
+    TS_STAGE(RENDER_STAGE_PAIR_GRADS, launch_pair_grads(workspace, L, st), "pair gradients");
   TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
   if (deterministic(L)) TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_gather(workspace, L, st), "vertex gather");
   return RENDER_OK;

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2
       uint32_t* th = at<uint32_t>(ws, L.o_tile_hist);
       for (int i = threadIdx.x; i < 2 * TILE_BUCKETS; i += 256) th[i] = 0u;
       uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
-      for (int i = threadIdx.x; i < TILE_BUCKETS; i += 256) bh[i] = 0u;
+      for (int i = threadIdx.x; i < BWD_HIST_WORDS; i += 256) bh[i] = 0u;
     }
   }
   const int v = blockIdx.y;
@@ -778,7 +778,11 @@ hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
 // backward order: forward slots re-bucketed by the walked length pend - start
 // (the forward compositing kernel counted every slot with pend > start; the
 // tiles with nothing walked form bucket 0, placed last, whose own count the
-// offsets never need)
+// offsets never need).  On the multi-wave 8x8 path every slot also gets the
+// bases of its blended pairs and of its segments (the (tile, entry) pairs
+// with a blended pixel) in the backward's pair buffers, by the same bucket
+// scheme (the forward counted them per slot and per bucket), and the totals
+// are checked against the entry capacity, which bounds the pairs.
 __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
   const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
@@ -786,30 +790,69 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   uint32_t* cursor = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
   TileSlot* bslots = at<TileSlot>(ws, L.o_bwd_order);
   uint32_t* bpend = at<uint32_t>(ws, L.o_bwd_pend);
+  const bool pairs = L.o_pairs != 0;
   __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS], first[TILE_BUCKETS], lds[8];
-  if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
+  __shared__ uint32_t pcnt[TILE_BUCKETS], pbase[TILE_BUCKETS], pfirst[TILE_BUCKETS];
+  __shared__ uint32_t scnt[TILE_BUCKETS], sbase[TILE_BUCKETS], sfirst[TILE_BUCKETS];
+  if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = pcnt[threadIdx.x] = scnt[threadIdx.x] = 0;
   bucket_first(hist, first, lds);
   __syncthreads();
+  if (pairs) {
+    bucket_first(hist + 2 * TILE_BUCKETS, pfirst, lds);
+    __syncthreads();
+    bucket_first(hist + 4 * TILE_BUCKETS, sfirst, lds);
+    __syncthreads();
+  }
   // the slots before bucket 0 are the tiles with something walked
-  if (blockIdx.x == 0 && threadIdx.x == 0) at<DevHeader>(ws, L.o_hdr)->bwd_work = first[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+    hdr->bwd_work = first[0];
+    if (pairs) {
+      uint64_t np = 0, nsg = 0;
+      for (int b = 0; b < TILE_BUCKETS; ++b) {
+        np += hist[2 * TILE_BUCKETS + b];
+        nsg += hist[4 * TILE_BUCKETS + b];
+      }
+      hdr->pairs_total = (uint32_t)min(np, (uint64_t)0xffffffffu);
+      hdr->segs_total = (uint32_t)min(nsg, (uint64_t)0xffffffffu);
+      if (np > (uint64_t)L.entry_cap) {
+        hdr->overflow |= 2u;
+        if (np > hdr->entries_needed) hdr->entries_needed = np;
+      }
+    }
+  }
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   int b = 0;
-  uint32_t rank = 0;
+  uint32_t rank = 0, prank = 0, srank = 0;
   TileSlot sl{};
   uint32_t pe = 0;
+  uint2 ps = make_uint2(0u, 0u);
   if (t < (uint32_t)L.total_tiles) {
     sl = slots[t];
     pe = pend[t];
     b = len_bucket(pe - sl.start);
     rank = atomicAdd(&cnt[b], 1u);
+    if (pairs && pe > sl.start) {
+      ps = at<const uint2>(ws, L.o_slot_pairs)[t];
+      prank = atomicAdd(&pcnt[b], ps.x);
+      srank = atomicAdd(&scnt[b], ps.y);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x])
+  if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) {
     base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    if (pairs) {
+      pbase[threadIdx.x] = pfirst[threadIdx.x] +
+                           atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + 3 * TILE_BUCKETS + threadIdx.x, pcnt[threadIdx.x]);
+      sbase[threadIdx.x] = sfirst[threadIdx.x] +
+                           atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + 5 * TILE_BUCKETS + threadIdx.x, scnt[threadIdx.x]);
+    }
+  }
   __syncthreads();
   if (t < (uint32_t)L.total_tiles) {
     bslots[base[b] + rank] = sl;
     bpend[base[b] + rank] = pe;
+    if (pairs) at<uint4>(ws, L.o_bwd_base)[base[b] + rank] = make_uint4(pbase[b] + prank, sbase[b] + srank, ps.x, ps.y);
   }
 }
 
@@ -957,8 +1000,6 @@ __device__ __forceinline__ void zero_grads_body(const DevScene& S, void* ws, con
   uint32_t* f = at<uint32_t>(ws, L.o_eflag);
   const uint32_t words = (hdr->entries_total + 3u) / 4u;
   for (size_t i = i0; i < words; i += stride) f[i] = 0u;
-  uint32_t* bcur = at<uint32_t>(ws, L.o_bwd_hist) + TILE_BUCKETS;
-  for (size_t i = i0; i < (size_t)TILE_BUCKETS; i += stride) bcur[i] = 0u;
   if (record_grads(L)) {
     // the records' gradient accumulators
     float4* acc = at<float4>(ws, L.o_tgrad);

@@ -4,15 +4,17 @@
 // (backward) by one pixel per lane, and the per-pixel state along the list
 // (transmittance, the colour behind) is a short sequential recurrence.  The
 // expensive part of every (pixel, entry) pair -- coverage of the projected
-// hull, entry/exit SDF values and Eq. 1, and in the backward the chain to the
-// record's screen-space parameters and the wave reduction -- does not depend
-// on that state.  So NWV waves share one 8x8 tile: for each LDS chunk of
-// entries they evaluate interleaved entries in parallel into LDS, one wave
-// runs the recurrence over the chunk, and (backward) the waves then build and
-// reduce the per-entry gradients in parallel.  Images are bit-identical to
-// the one-wave kernels (the same per-pair arithmetic in the same order);
-// gradients agree to rounding (an entry's pixel groups are added in LDS in
-// arrival order), bitwise with the deterministic variant.
+// hull, entry/exit SDF values and Eq. 1 -- does not depend on that state.
+// So NWV waves share one 8x8 tile: for each LDS chunk of entries they
+// evaluate the (entry, pixel) pairs that can hit in parallel into LDS, and one
+// wave runs the recurrence over the chunk.  The backward's recurrence leaves,
+// per blended pair, dL/df_prev, dL/df_next and the blend weight in a pair
+// buffer, grouped per (tile, entry) segment; a second, flat kernel chains
+// every pair to its record's 23 screen-space parameters and sums each
+// segment, with no per-tile sequence and no atomics.  The forward counts
+// each tile's blended pairs and segments so that every backward workgroup
+// knows where its pairs go.  Images are bit-identical to the one-wave kernels
+// (the same per-pair arithmetic in the same order).
 #include "tile8.h"
 
 namespace ts {
@@ -29,7 +31,8 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
                                               uint64_t* pmask, uint32_t* poff, uint64_t* hm, float (*feat)[CHN],
                                               unsigned long long* done_mask,
                                               float& T, float& Tb, float& O, float (&acc)[7], int& last,
-                                              bool want_acc) {
+                                              bool want_acc, uint32_t* nblend = nullptr,
+                                              uint32_t* nseg = nullptr) {
   constexpr int NT = 64 * NWV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool done = !c.inside;
@@ -74,6 +77,7 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
     if (wave == 0) {
       // each pixel visits only its candidate entries, front to back
       uint64_t cand = hm[lane];
+      uint64_t blended = 0ull;   // this lane's blended entries of the chunk
       while (__ballot(cand != 0ull && !done) != 0ull) {
         if (cand != 0ull && !done) {
           const int e = __ffsll((unsigned long long)cand) - 1;
@@ -97,9 +101,22 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
             Tb = T;
             T = Tn;
             last = (int)(base + e);
+            blended |= 1ull << e;
             if (T == 0.0f) done = true;
           }
         }
+      }
+      if (nblend) {
+        // the chunk's blended pairs (per lane) and its entries with a blended
+        // pixel (the same in every lane)
+        *nblend += (uint32_t)__popcll(blended);
+        uint32_t lo = (uint32_t)blended, hi = (uint32_t)(blended >> 32);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          lo |= (uint32_t)__shfl_xor((int)lo, o, 64);
+          hi |= (uint32_t)__shfl_xor((int)hi, o, 64);
+        }
+        *nseg += (uint32_t)(__popc(lo) + __popc(hi));
       }
       const unsigned long long m = __ballot(done);
       if (lane == 0) *done_mask = m;
@@ -184,19 +201,34 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int last = -1;
+  uint32_t nblend = 0, nseg = 0;
+  const bool count = L.o_pairs != 0;
   forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff, hm,
-                          feat, &done_mask, T, Tb, O, acc, last, true);
+                          feat, &done_mask, T, Tb, O, acc, last, true, count ? &nblend : nullptr,
+                          count ? &nseg : nullptr);
   if ((threadIdx.x >> 6) == 0) {
     // end of the tile's blended prefix: where the backward starts its walk
     int wmax = last;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+    for (int o = 32; o > 0; o >>= 1) {
+      wmax = max(wmax, __shfl_xor(wmax, o, 64));
+      nblend += (uint32_t)__shfl_xor((int)nblend, o, 64);
+    }
     if ((threadIdx.x & 63) == 0) {
       const uint32_t pend = wmax >= (int)start ? (uint32_t)wmax + 1u : start;
       at<uint32_t>(ws, L.o_tile_pend)[blockIdx.x] = pend;
-      // the backward dispatch order's histogram of walked lengths (bucket 0,
-      // nothing walked, is not counted)
-      if (pend > start) atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + len_bucket(pend - start), 1u);
+      if (count) at<uint2>(ws, L.o_slot_pairs)[blockIdx.x] = make_uint2(nblend, nseg);
+      // the backward dispatch order's histograms of walked lengths, blended
+      // pairs and segments (bucket 0, nothing walked, is not counted)
+      if (pend > start) {
+        uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
+        const int b = len_bucket(pend - start);
+        atomicAdd(bh + b, 1u);
+        if (count) {
+          atomicAdd(bh + 2 * TILE_BUCKETS + b, nblend);
+          atomicAdd(bh + 4 * TILE_BUCKETS + b, nseg);
+        }
+      }
     }
   }
   if ((threadIdx.x >> 6) == 0 && c.inside) {
@@ -219,35 +251,36 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   }
 }
 
-// DET: every entry's gradient is the sum of its 8-pixel groups in group
-// order (group sums staged in LDS), not LDS float atomics in arrival order;
-// the chunk is halved (16 entries) to make room.
-template <int NWV, bool DET>
+// Backward, walk and recurrence: per chunk, coverage and Eq. 1 of every
+// (entry, pixel) the pixel's walk reached, packed, then the reverse
+// recurrence of Eq. 2 (one wave).  Every blended pair's dL/df_prev,
+// dL/df_next and blend weight go to the pair buffer, entry-major inside the
+// chunk, and every entry with a blended pixel gets a segment (its record, its
+// per-(record, tile) gradient slot, its first pair and pair count); the
+// tile's pairs and segments start at the bases the forward's counts gave
+// this backward slot.
+template <int NWV>
 __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout L, float alpha_min,
                                                                float alpha_clamp, float t_min, int recompute) {
   constexpr int NT = 64 * NWV;
-  constexpr int CHB = DET ? 16 : 32;
+  constexpr int CHB = 32;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const int32_t* last_in = at<const int32_t>(ws, L.o_last);
   const float* tlast_in = at<const float>(ws, L.o_tlast);
-  float* tgrad = at<float>(ws, L.o_tgrad);
-  uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
+  float4* pairs = at<float4>(ws, L.o_pairs);
+  uint4* segs = at<uint4>(ws, L.o_segs);
   __shared__ ViewRec recs[CHB];
-  __shared__ float abuf[CHB][64];    // raw alpha (-1: no hit / not reached); phase B: dL/df_prev
-  __shared__ float e2buf[CHB][64];   // exp(s f_next); phase B: dL/df_next
+  __shared__ float abuf[CHB][64];    // raw alpha
+  __shared__ float e2buf[CHB][64];   // exp(s f_next)
   __shared__ uint8_t sel[CHB][64];   // entry face | exit face << 2
-  __shared__ float wbuf[CHB][64];    // blend weight T alpha
-  __shared__ float gacc[CHB][TGRAD_STRIDE];
-  __shared__ float grs[8][64];       // upstream gradient of each pixel
   __shared__ uint64_t pmask[CHB];
   __shared__ uint32_t poff[CHB + 1];
-  __shared__ uint64_t hmask[64];     // per pixel: chunk entries it blended (bit e)
+  __shared__ uint64_t hmask[64];     // per pixel: chunk entries it may have blended (bit e)
   __shared__ float feat[7][CHB];     // per entry: c[3], zt, n[3] (conflict-free gathers)
   __shared__ unsigned long long done_mask;
   __shared__ int smax;
-  __shared__ __align__(16) float gsum[DET ? CHB * 8 : 1][TGRAD_STRIDE];  // DET: per 8-pixel group
 
   // dispatch order by the length the forward walked (longest first); the
   // tiles where nothing was blended come last and leave at once
@@ -258,11 +291,11 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const DevView& V = vw[c.view];
   const float s = V.s;
   const uint32_t start = c.start, end = c.end;
-  const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   const size_t plane = (size_t)V.W * V.H;
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
   const unsigned lane = threadIdx.x & 63u;
   const int wave = threadIdx.x >> 6;
+  const uint64_t cap = (uint64_t)L.entry_cap;
 
   // per-pixel state (wave 0): last blended entry, T before it, upstream gradient;
   // pend: end of the tile's blended prefix (from the forward, or the replay)
@@ -290,16 +323,16 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       Tb = tlast_in[gi];
     }
   }
+  float gr[8];
   float Rbehind = 0.0f;
   if (wave == 0) {
-    float gr[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
-      grs[q][lane] = gr[q];
-    }
+    for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
     Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
   }
+  // this tile's pairs and segments
+  const uint4 pb = at<const uint4>(ws, L.o_bwd_base)[blockIdx.x];
+  uint32_t pair_run = pb.x, seg_run = pb.y;
 
   bool first = true;
   float Tnext = 1.0f;
@@ -361,15 +394,41 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       }
     });
     __syncthreads();
-    // phase B: reverse recurrence (one wave); the others clear the chunk's sums
-    for (int q = threadIdx.x; q < n * TGRAD_STRIDE; q += NT) (&gacc[0][0])[q] = 0.0f;
+    // phase B (wave 0): the chunk's pairs are the bits of hmask (every
+    // candidate at or before the pixel's last blend was blended); their
+    // places first, then the reverse recurrence writes each pair
     if (wave == 0) {
-      // each pixel visits only the entries it blended, nearest-last first
       const uint32_t m0 = (uint32_t)hmask[lane];   // CHB = 32 entries
-      uint32_t m = m0;
-      float gr[8];
+      const uint64_t lt = (1ull << lane) - 1ull;
+      // lane e: the pixels that blended entry e
+      uint32_t any = m0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) gr[q] = grs[q][lane];
+      for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+      any = __builtin_amdgcn_readfirstlane(any);
+      uint64_t cmask_e = 0ull;
+      for (uint32_t t = any; t != 0u; t &= t - 1u) {
+        const int e = __ffs(t) - 1;
+        const uint64_t b = __ballot((m0 >> e) & 1u);
+        cmask_e = ((int)lane == e) ? b : cmask_e;
+      }
+      pair_offsets<CHB, 1>(n, cmask_e, pmask, poff);
+      // segments: the entries with a blended pixel, in entry order
+      const bool has = (int)lane < n && cmask_e != 0ull;
+      const uint64_t sm = __ballot(has);
+      if (has) {
+        const uint32_t si = seg_run + (uint32_t)__popcll(sm & lt);
+        const ViewRec& R = recs[lane];
+        int i0, i1, j0, j1;
+        unpack_rect(R, i0, i1, j0, j1);
+        const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
+        const uint32_t d = R.entry0 + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
+        if ((uint64_t)si < cap)
+          segs[si] = make_uint4(srec[base + lane], d, pair_run + poff[lane],
+                                (uint32_t)__popcll(cmask_e) | (blockIdx.x << 7));
+      }
+      seg_run += (uint32_t)__popcll(sm);
+      // each pixel visits only the entries it blended, nearest-last first
+      uint32_t m = m0;
       while (__ballot(m != 0u) != 0ull) {
         if (m != 0u) {
           const int e = 31 - __clz(m);
@@ -384,80 +443,106 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
                              gr[4] * feat[3][e] + gr[5] * feat[4][e] + gr[6] * feat[5][e] + gr[7] * feat[6][e];
           const float da = araw > alpha_clamp ? 0.0f : T * (sdot - Rbehind);
           Rbehind = a * sdot + (1.0f - a) * Rbehind;
-          // chain dL/dalpha through Eq. 1 here, so phase C needs neither alpha nor e2
+          // dL/dalpha chained through Eq. 1 to the entry and exit SDF values
           float dd, dfn;
           eq1_chain(da, araw, e2, s, dd, dfn);
-          abuf[e][lane] = dd;
-          e2buf[e][lane] = dfn;
-          wbuf[e][lane] = T * a;
+          const uint32_t pi = pair_run + poff[e] + (uint32_t)__popcll(pmask[e] & lt);
+          if ((uint64_t)pi < cap)
+            pairs[pi] = make_float4(dd, dfn, T * a, __uint_as_float(lane | ((uint32_t)sel[e][lane] << 6)));
         }
       }
-      // lane e: the pixels that blended entry e (the pairs of phase C)
-      uint32_t any = m0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
-      any = __builtin_amdgcn_readfirstlane(any);
-      uint64_t cmask_e = 0ull;
-      for (uint32_t t = any; t != 0u; t &= t - 1u) {
-        const int e = __ffs(t) - 1;
-        const uint64_t b = __ballot((m0 >> e) & 1u);
-        cmask_e = ((int)lane == e) ? b : cmask_e;
-      }
-      pair_offsets<CHB, 8>(n, cmask_e, pmask, poff);
+      pair_run += poff[n];
     }
-    __syncthreads();
-    // phase C: the gradient of every contributing (entry, pixel) pair.  Each
-    // entry's pairs fill 8-lane groups (eight per wave); a group is summed
-    // with DPP inside its half-row and added to the entry's sum (LDS float
-    // add: an entry with more than 8 contributing pixels spans several
-    // groups).
-    {
-      const uint32_t ngroups = poff[n];
-      const int l8 = (int)(lane & 7u);
-      for (uint32_t g0 = (uint32_t)wave * 8u; g0 < ngroups; g0 += 8u * NWV) {
-        const uint32_t grp = g0 + (lane >> 3);
-        // branch-free: a lane past the last group or the entry's last pair
-        // chains zero weights
-        const bool gv = grp < ngroups;
-        const int e = entry_of<CHB>(n, poff, gv ? grp : ngroups - 1u);
-        const uint64_t m = pmask[e];
-        const uint32_t k = (grp - poff[e]) * 8u + (uint32_t)l8;
-        const bool valid = gv && k < (uint32_t)__popcll(m);
-        const int pix = valid ? select_bit(m, k) : 0;
-        const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
-        float grp8[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) grp8[q] = grs[q][pix];
-        const float dd = valid ? abuf[e][pix] : 0.0f, dfn = valid ? e2buf[e][pix] : 0.0f;
-        const float w = valid ? wbuf[e][pix] : 0.0f;
-        float g[32];
-        pair_grad_all(recs[e], px_, py_, grp8, dd, dfn, w, sel[e][pix], g);
-        const float4 r = row8_transpose_sum32(g);
-        static_assert(TGRAD_STRIDE - 1 == 23, "23 gradient slots: lane 5 holds the last three");
-        if constexpr (DET) {
-          if (gv && 4 * l8 < TGRAD_STRIDE) *reinterpret_cast<float4*>(&gsum[grp][4 * l8]) = r;
-        } else if (gv && 4 * l8 < TGRAD_STRIDE - 1) {
-          atomicAdd(&gacc[e][4 * l8], r.x);
-          atomicAdd(&gacc[e][4 * l8 + 1], r.y);
-          atomicAdd(&gacc[e][4 * l8 + 2], r.z);
-          if (4 * l8 + 3 < TGRAD_STRIDE - 1) atomicAdd(&gacc[e][4 * l8 + 3], r.w);
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (DET) {
-      // each entry: its groups' sums in group order
-      for (int q = threadIdx.x; q < n * (TGRAD_STRIDE - 1); q += NT) {
-        const int e = q / (TGRAD_STRIDE - 1), k = q - e * (TGRAD_STRIDE - 1);
-        float acc = 0.0f;
-        for (uint32_t gi = poff[e]; gi < poff[e + 1]; ++gi) acc += gsum[gi][k];
-        gacc[e][k] = acc;
-      }
-      __syncthreads();
-    }
-    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, (uint64_t)L.entry_cap,
-                      record_grads(L) ? srec + base : nullptr);
   }
+}
+
+// Backward, per-pair gradients: one 4-lane group per segment (a (tile,
+// entry) pair with blended pixels) chains each of its pairs to the record's
+// 23 screen-space parameters (colour, depth and normal enter linearly with
+// the blend weight; the entry and exit faces through App. A.1-A.2) and sums
+// them -- in registers over the group's pairs in order, then over the group
+// in a fixed DPP pattern -- into the segment's gradient slot (flagged as
+// reached), or, with per-record gradients, adds the sum to the record's
+// accumulator.  Fixed order throughout: reproducible bitwise.  (A layout
+// with one workgroup per tile, one pair per thread and the segments summed
+// through LDS took 68 us against 49 us for this one at the training shape:
+// its rounds are dependent load chains and its summation diverges.)
+__global__ __launch_bounds__(256) void k_pair_grads(void* ws, Layout L) {
+  const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
+  const DevView* vw = at<const DevView>(ws, L.o_view);
+  const TileSlot* bslots = at<const TileSlot>(ws, L.o_bwd_order);
+  const float4* vrec4 = at<const float4>(ws, L.o_vrec);
+  const float4* pairs = at<const float4>(ws, L.o_pairs);
+  const uint4* segs = at<const uint4>(ws, L.o_segs);
+  float* tgrad = at<float>(ws, L.o_tgrad);
+  uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
+  const uint64_t cap = (uint64_t)L.entry_cap;
+  const uint32_t nseg = (uint32_t)min((uint64_t)hdr->segs_total, cap);
+  const bool per_record = record_grads(L);
+  const uint32_t lg = threadIdx.x & 3u;
+  const uint32_t groups = gridDim.x * (blockDim.x / 4);
+  // the loop runs the same number of times in every lane of a wave (the
+  // group sum needs them all)
+  const uint32_t wave0 = (blockIdx.x * blockDim.x + (threadIdx.x & ~63u)) / 4;
+  for (uint32_t sbase = wave0; sbase < nseg; sbase += groups) {
+    const uint32_t si = sbase + ((threadIdx.x & 63u) >> 2);
+    const bool sv = si < nseg;
+    const uint4 sg = sv ? segs[si] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t cnt = sg.w & 127u;
+    float g[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) g[q] = 0.0f;
+    if (sv && cnt > 0u) {
+      const TileSlot sl = bslots[sg.w >> 7];
+      const DevView& V = vw[sl.view];
+      const int lt = (int)sl.tile - V.tile_base;
+      const int x0 = (lt % V.tiles_x) * 8, y0 = (lt / V.tiles_x) * 8;
+      const size_t plane = (size_t)V.W * V.H;
+      // the record's projected vertices, inverse depths and SDF values (its first 64 bytes)
+      ViewRec R;
+      const float4* src = vrec4 + (size_t)sg.x * 8;
+      reinterpret_cast<float4*>(&R)[0] = src[0];
+      reinterpret_cast<float4*>(&R)[1] = src[1];
+      reinterpret_cast<float4*>(&R)[2] = src[2];
+      reinterpret_cast<float4*>(&R)[3] = src[3];
+      for (uint32_t k = lg; k < cnt; k += 4u) {
+        const uint64_t pi = (uint64_t)sg.z + k;
+        if (pi >= cap) break;
+        const float4 pr = pairs[pi];
+        const uint32_t pw = __float_as_uint(pr.w);
+        const int pix = (int)(pw & 63u);
+        const int i = x0 + (pix & 7), j = y0 + (pix >> 3);
+        const size_t p = (size_t)j * V.W + i;
+        float gr[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) gr[q] = V.dout[q * plane + p];
+        pair_grad_all<true>(R, (float)i + 0.5f, (float)j + 0.5f, gr, pr.x, pr.y, pr.z, (int)((pw >> 6) & 15u), g);
+      }
+    }
+    float r[8];
+    quad_transpose_sum32(g, r);   // lane lg: the segment's sums of g[8 lg .. 8 lg + 7]
+    if (sv && cnt > 0u && lg < 3u) {
+      if (per_record) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (8 * lg + q < TGRAD_STRIDE - 1 && r[q] != 0.0f)
+            unsafeAtomicAdd(&tgrad[(size_t)sg.x * TGRAD_STRIDE + 8 * lg + q], r[q]);
+      } else if ((uint64_t)sg.y < cap) {
+        float4* dst = reinterpret_cast<float4*>(tgrad + (size_t)sg.y * TGRAD_STRIDE + 8 * lg);
+        dst[0] = make_float4(r[0], r[1], r[2], r[3]);
+        dst[1] = make_float4(r[4], r[5], r[6], r[7]);
+        if (lg == 0u) eflag[sg.y] = 1;
+      }
+    }
+  }
+}
+
+hipError_t launch_pair_grads(void* ws, const Layout& L, hipStream_t st) {
+  if (L.o_pairs == 0) return hipErrorInvalidValue;
+  const int64_t b = (L.entry_cap + 63) / 64;   // 64 segments per block and pass
+  const unsigned blocks = (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+  k_pair_grads<<<blocks, 256, 0, st>>>(ws, L);
+  return hipGetLastError();
 }
 
 template <int NWV>
@@ -466,13 +551,8 @@ static void launch_fwd_mw(void* ws, const Layout& L, const render_params& p, hip
 }
 template <int NWV>
 static void launch_bwd_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  const int rc = (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0;
-  if (deterministic(L))
-    k_composite_bwd_mw<NWV, true><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
-                                                                                p.t_min, rc);
-  else
-    k_composite_bwd_mw<NWV, false><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
-                                                                                 p.t_min, rc);
+  k_composite_bwd_mw<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(
+      ws, L, p.alpha_min, p.alpha_clamp, p.t_min, (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0);
 }
 
 hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {

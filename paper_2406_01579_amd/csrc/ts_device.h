@@ -209,17 +209,21 @@ __device__ __forceinline__ void eq1_chain(float da, float alpha, float e2, float
 // faces fs = fe | fx << 2.  Without branches: all four faces are chained, a
 // face whose weight is zero contributes exactly zero (its 1/S is taken as 0),
 // so g is updated in place and a lane with w = dd = dfn = 0 returns zeros.
+// With ACC the pair's gradient is added to g instead.
+template <bool ACC = false>
 __device__ __forceinline__ void pair_grad_all(const ViewRec& R, float qx, float qy, const float (&gr)[8], float dd,
                                               float dfn, float w, int fs, float (&g)[32]) {
+  if (!ACC) {
 #pragma unroll
-  for (int q = 0; q < 32; ++q) g[q] = 0.0f;
-  g[G_C + 0] = w * gr[0];
-  g[G_C + 1] = w * gr[1];
-  g[G_C + 2] = w * gr[2];
-  g[G_ZT] = w * gr[4];
-  g[G_N + 0] = w * gr[5];
-  g[G_N + 1] = w * gr[6];
-  g[G_N + 2] = w * gr[7];
+    for (int q = 0; q < 32; ++q) g[q] = 0.0f;
+  }
+  g[G_C + 0] = fmaf(w, gr[0], g[G_C + 0]);
+  g[G_C + 1] = fmaf(w, gr[1], g[G_C + 1]);
+  g[G_C + 2] = fmaf(w, gr[2], g[G_C + 2]);
+  g[G_ZT] = fmaf(w, gr[4], g[G_ZT]);
+  g[G_N + 0] = fmaf(w, gr[5], g[G_N + 0]);
+  g[G_N + 1] = fmaf(w, gr[6], g[G_N + 1]);
+  g[G_N + 2] = fmaf(w, gr[7], g[G_N + 2]);
   const int fe = fs & 3, fx = fs >> 2;
   float ax[4], ay[4];
 #pragma unroll
@@ -321,6 +325,28 @@ __device__ __forceinline__ float4 row8_transpose_sum32(const float (&v)[32]) {
     z[k] = keep + dpp<0xB1>(send);    // quad_perm [1,0,3,2] (j <-> j ^ 1)
   }
   return make_float4(z[0], z[1], z[2], z[3]);
+}
+
+// Per 4-lane group (a quad): afterwards lane L of a group holds in r[0..7]
+// the sums over the quad's lanes of v[8 (L & 3)] .. v[8 (L & 3) + 7].  Each
+// step halves the values per lane while pairing lanes 2 apart, then 1 apart.
+// Every lane must be active.
+__device__ __forceinline__ void quad_transpose_sum32(const float (&v)[32], float (&r)[8]) {
+  const unsigned lane = __lane_id();
+  const bool b1 = lane & 2u, b0 = lane & 1u;
+  float x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float send = b1 ? v[k] : v[k + 16];
+    const float keep = b1 ? v[k + 16] : v[k];
+    x[k] = keep + dpp<0x4E>(send);    // quad_perm [2,3,0,1] (j <-> j ^ 2)
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float send = b0 ? x[k] : x[k + 8];
+    const float keep = b0 ? x[k + 8] : x[k];
+    r[k] = keep + dpp<0xB1>(send);    // quad_perm [1,0,3,2] (j <-> j ^ 1)
+  }
 }
 
 }  // namespace ts
