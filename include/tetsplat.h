@@ -127,10 +127,14 @@ typedef struct {
   int64_t entries;      /* tile-duplicated (tet, tile) entries of the last forward */
   int64_t kept;         /* tets kept by the pre-filter, summed over scenes */
   int64_t records;      /* (view, kept tet) records */
-  int32_t overflow;     /* bit 0: kept capacity, bit 1: entry capacity exceeded */
+  int32_t overflow;     /* bit 0: kept capacity, bit 1: entry capacity exceeded (the forward's
+                           outputs are invalid); bit 2: the (entry, pixel) pairs the forward
+                           blended exceed the entry capacity (multi-wave 8x8 path): the outputs
+                           stand, a backward of this forward would not */
   int32_t invalid_index;/* nonzero if some tet had a vertex index outside [0, V) */
   int64_t entry_capacity, kept_capacity;
-  int64_t entries_needed; /* entries the forward wanted (exact even on overflow) */
+  int64_t entries_needed; /* entry capacity the forward and its backward want (exact even on
+                             overflow): its entries, or its blended pairs if more */
 } render_status;
 
 /*

@@ -242,14 +242,9 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_wpair = p->window > 0 ? take(16 * 64 * (size_t)entry_cap) : 0;
   const bool pairs_path = p->window == 0 && p->tile_w == 8 && p->tile_h == 8 && p->waves != 1;
   if (pairs_path) {
-    if (tiles >= ((int64_t)1 << 25)) {   // a segment holds its backward slot in 25 bits
-      *why = "the multi-wave 8x8 path takes at most 2^25 tiles";
-      return false;
-    }
     L.o_slot_pairs = take(8 * (size_t)tiles);
     L.o_bwd_base = take(16 * (size_t)tiles);
-    L.o_pairs = take(16 * (size_t)entry_cap);   // at most entry_capacity blended pairs
-    L.o_segs = take(16 * (size_t)entry_cap);
+    L.o_pairs = take(32 * (size_t)entry_cap);   // at most entry_capacity blended pairs
   }
   if (det) {
     const size_t nc = 4 * (size_t)kept_cap;

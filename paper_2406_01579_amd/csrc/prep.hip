@@ -815,8 +815,8 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
       }
       hdr->pairs_total = (uint32_t)min(np, (uint64_t)0xffffffffu);
       hdr->segs_total = (uint32_t)min(nsg, (uint64_t)0xffffffffu);
-      if (np > (uint64_t)L.entry_cap) {
-        hdr->overflow |= 2u;
+      if (np > (uint64_t)L.entry_cap) {   // the forward's outputs stand; its backward would not
+        hdr->overflow |= 4u;
         if (np > hdr->entries_needed) hdr->entries_needed = np;
       }
     }

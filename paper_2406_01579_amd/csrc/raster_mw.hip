@@ -21,6 +21,14 @@ namespace ts {
 
 namespace {
 
+// A blended (entry, pixel) pair of the backward, 32 bytes: dL/df_prev,
+// dL/df_next, the blend weight T alpha and a word (pixel | entry and exit
+// faces << 6 | PAIR_HEAD on the first pair of its segment, which also holds
+// the segment's pair count << 11); then the entry's record, view, tile
+// (x | y << 16) and gradient slot.  A segment is a (tile, entry) with blended
+// pixels: its pairs are consecutive, at most 64 (one per tile pixel).
+constexpr uint32_t PAIR_HEAD = 1u << 10;
+
 // Forward sweep over [start, end) with NWV waves; wave 0 ends with the
 // pixel's blend state.  Used by the forward kernel and by the backward's
 // state replay.
@@ -269,9 +277,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const int32_t* last_in = at<const int32_t>(ws, L.o_last);
   const float* tlast_in = at<const float>(ws, L.o_tlast);
-  float4* pairs = at<float4>(ws, L.o_pairs);
-  uint4* segs = at<uint4>(ws, L.o_segs);
+  uint4* pairs = at<uint4>(ws, L.o_pairs);
   __shared__ ViewRec recs[CHB];
+  __shared__ uint4 eseg[CHB];        // per entry with a blended pixel: record, view, tile, gradient slot
   __shared__ float abuf[CHB][64];    // raw alpha
   __shared__ float e2buf[CHB][64];   // exp(s f_next)
   __shared__ uint8_t sel[CHB][64];   // entry face | exit face << 2
@@ -332,7 +340,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   }
   // this tile's pairs and segments
   const uint4 pb = at<const uint4>(ws, L.o_bwd_base)[blockIdx.x];
-  uint32_t pair_run = pb.x, seg_run = pb.y;
+  uint32_t pair_run = pb.x;
+  const uint32_t tile_xy = (uint32_t)c.tx | ((uint32_t)c.ty << 16);
 
   bool first = true;
   float Tnext = 1.0f;
@@ -412,21 +421,15 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         cmask_e = ((int)lane == e) ? b : cmask_e;
       }
       pair_offsets<CHB, 1>(n, cmask_e, pmask, poff);
-      // segments: the entries with a blended pixel, in entry order
-      const bool has = (int)lane < n && cmask_e != 0ull;
-      const uint64_t sm = __ballot(has);
-      if (has) {
-        const uint32_t si = seg_run + (uint32_t)__popcll(sm & lt);
+      // the entries with a blended pixel: what every one of their pairs carries
+      if ((int)lane < n && cmask_e != 0ull) {
         const ViewRec& R = recs[lane];
         int i0, i1, j0, j1;
         unpack_rect(R, i0, i1, j0, j1);
         const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
         const uint32_t d = R.entry0 + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
-        if ((uint64_t)si < cap)
-          segs[si] = make_uint4(srec[base + lane], d, pair_run + poff[lane],
-                                (uint32_t)__popcll(cmask_e) | (blockIdx.x << 7));
+        eseg[lane] = make_uint4(srec[base + lane], (uint32_t)c.view, tile_xy, d);
       }
-      seg_run += (uint32_t)__popcll(sm);
       // each pixel visits only the entries it blended, nearest-last first
       uint32_t m = m0;
       while (__ballot(m != 0u) != 0ull) {
@@ -446,9 +449,15 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
           // dL/dalpha chained through Eq. 1 to the entry and exit SDF values
           float dd, dfn;
           eq1_chain(da, araw, e2, s, dd, dfn);
-          const uint32_t pi = pair_run + poff[e] + (uint32_t)__popcll(pmask[e] & lt);
-          if ((uint64_t)pi < cap)
-            pairs[pi] = make_float4(dd, dfn, T * a, __uint_as_float(lane | ((uint32_t)sel[e][lane] << 6)));
+          const uint64_t below = pmask[e] & lt;
+          const uint32_t pi = pair_run + poff[e] + (uint32_t)__popcll(below);
+          if ((uint64_t)pi < cap) {
+            // the segment's first pair carries its pair count
+            const uint32_t hw = below == 0ull ? PAIR_HEAD | ((uint32_t)__popcll(pmask[e]) << 11) : 0u;
+            pairs[2 * (size_t)pi] = make_uint4(__float_as_uint(dd), __float_as_uint(dfn), __float_as_uint(T * a),
+                                               lane | ((uint32_t)sel[e][lane] << 6) | hw);
+            pairs[2 * (size_t)pi + 1] = eseg[e];
+          }
         }
       }
       pair_run += poff[n];
@@ -456,90 +465,151 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   }
 }
 
-// Backward, per-pair gradients: one 4-lane group per segment (a (tile,
-// entry) pair with blended pixels) chains each of its pairs to the record's
-// 23 screen-space parameters (colour, depth and normal enter linearly with
-// the blend weight; the entry and exit faces through App. A.1-A.2) and sums
-// them -- in registers over the group's pairs in order, then over the group
-// in a fixed DPP pattern -- into the segment's gradient slot (flagged as
-// reached), or, with per-record gradients, adds the sum to the record's
-// accumulator.  Fixed order throughout: reproducible bitwise.  (A layout
-// with one workgroup per tile, one pair per thread and the segments summed
-// through LDS took 68 us against 49 us for this one at the training shape:
-// its rounds are dependent load chains and its summation diverges.)
+// Backward, per-pair gradients, flat over the pair buffer: each workgroup
+// pass takes a window of PG_W consecutive pairs, one per lane.  A lane chains
+// its pair to the record's 23 screen-space parameters (colour, depth and
+// normal enter linearly with the blend weight; the entry and exit faces
+// through App. A.1-A.2) and leaves them in an LDS row; everything it needs
+// comes with the pair (one load) and then the record and the view's
+// upstream gradient (a second).  The segments whose first pair lies in the
+// window are then summed there in a fixed order, one (segment, parameter)
+// per thread, into the segment's gradient slot (flagged as reached) or, with
+// per-record gradients, added to the record's accumulator.  Only the
+// window's last segment runs past it, by at most 63 pairs: the first wave
+// also takes the pairs after the window up to the next segment's first pair
+// (their loads in flight beside its own pair's), and skips the pairs before
+// the window's first segment, which the previous window takes.  Fixed order
+// throughout: reproducible bitwise.  (Earlier layouts: a 4-lane group per
+// segment left most lanes idle behind a wave's longest segment, 47 us at the
+// training shape; one workgroup per tile summing its segments through LDS in
+// rounds, 68 us; pairs that reached their record and tile through a segment
+// table, 55 us.)
+constexpr int PG_W = 256;          // pairs per window (one per thread)
+constexpr int PG_TAIL = 64;        // rows for the last segment's pairs past the window
+constexpr int PG_G = TGRAD_STRIDE - 1;    // the 23 parameters (the slot's last float is padding)
+constexpr int PG_LD = PG_G;               // LDS row stride (floats), odd: conflict-free column writes
+
+struct PairIn {
+  uint4 a, b;   // the pair's two halves
+  bool ok;
+};
+
+// Loads of pair pidx; ok = in range (the buffers of an overflowed forward
+// may be stale: the reads then stay in bounds and the result is discarded).
+__device__ __forceinline__ PairIn pair_load(const uint4* __restrict__ pairs, uint32_t pidx, const Layout& L) {
+  PairIn q;
+  q.a = pairs[2 * (size_t)pidx];
+  q.b = pairs[2 * (size_t)pidx + 1];
+  q.ok = q.b.y < (uint32_t)L.nv && (int64_t)q.b.x < L.rec_cap;
+  return q;
+}
+
+__device__ __forceinline__ void pair_row(const PairIn& q, const DevView* __restrict__ vw,
+                                         const float4* __restrict__ vrec4, float* row) {
+  // the record's projected vertices, inverse depths and SDF values (its first 64 bytes)
+  ViewRec R;
+  const float4* src = vrec4 + (size_t)q.b.x * 8;
+  reinterpret_cast<float4*>(&R)[0] = src[0];
+  reinterpret_cast<float4*>(&R)[1] = src[1];
+  reinterpret_cast<float4*>(&R)[2] = src[2];
+  reinterpret_cast<float4*>(&R)[3] = src[3];
+  const DevView& V = vw[q.b.y];
+  const float* dout = V.dout;
+  const int W = V.W, H = V.H;
+  const int pix = (int)(q.a.w & 63u);
+  const int i = (int)(q.b.z & 0xffffu) * 8 + (pix & 7), j = (int)(q.b.z >> 16) * 8 + (pix >> 3);
+  // (clamped: a stale pair of an overflowed forward stays in bounds)
+  const size_t plane = (size_t)W * H, p = (size_t)min(j, H - 1) * W + min(i, W - 1);
+  float gr[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) gr[k] = dout[k * plane + p];
+  float g[32];
+  pair_grad_all(R, (float)i + 0.5f, (float)j + 0.5f, gr, __uint_as_float(q.a.x), __uint_as_float(q.a.y),
+                __uint_as_float(q.a.z), (int)((q.a.w >> 6) & 15u), g);
+#pragma unroll
+  for (int k = 0; k < PG_G; ++k) row[k] = g[k];
+}
+
 __global__ __launch_bounds__(256) void k_pair_grads(void* ws, Layout L) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  const TileSlot* bslots = at<const TileSlot>(ws, L.o_bwd_order);
   const float4* vrec4 = at<const float4>(ws, L.o_vrec);
-  const float4* pairs = at<const float4>(ws, L.o_pairs);
-  const uint4* segs = at<const uint4>(ws, L.o_segs);
+  const uint4* pairs = at<const uint4>(ws, L.o_pairs);
   float* tgrad = at<float>(ws, L.o_tgrad);
   uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
   const uint64_t cap = (uint64_t)L.entry_cap;
-  const uint32_t nseg = (uint32_t)min((uint64_t)hdr->segs_total, cap);
+  const uint32_t npair = (uint32_t)min((uint64_t)hdr->pairs_total, cap);
   const bool per_record = record_grads(L);
-  const uint32_t lg = threadIdx.x & 3u;
-  const uint32_t groups = gridDim.x * (blockDim.x / 4);
-  // the loop runs the same number of times in every lane of a wave (the
-  // group sum needs them all)
-  const uint32_t wave0 = (blockIdx.x * blockDim.x + (threadIdx.x & ~63u)) / 4;
-  for (uint32_t sbase = wave0; sbase < nseg; sbase += groups) {
-    const uint32_t si = sbase + ((threadIdx.x & 63u) >> 2);
-    const bool sv = si < nseg;
-    const uint4 sg = sv ? segs[si] : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t cnt = sg.w & 127u;
-    float g[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) g[q] = 0.0f;
-    if (sv && cnt > 0u) {
-      const TileSlot sl = bslots[sg.w >> 7];
-      const DevView& V = vw[sl.view];
-      const int lt = (int)sl.tile - V.tile_base;
-      const int x0 = (lt % V.tiles_x) * 8, y0 = (lt / V.tiles_x) * 8;
-      const size_t plane = (size_t)V.W * V.H;
-      // the record's projected vertices, inverse depths and SDF values (its first 64 bytes)
-      ViewRec R;
-      const float4* src = vrec4 + (size_t)sg.x * 8;
-      reinterpret_cast<float4*>(&R)[0] = src[0];
-      reinterpret_cast<float4*>(&R)[1] = src[1];
-      reinterpret_cast<float4*>(&R)[2] = src[2];
-      reinterpret_cast<float4*>(&R)[3] = src[3];
-      for (uint32_t k = lg; k < cnt; k += 4u) {
-        const uint64_t pi = (uint64_t)sg.z + k;
-        if (pi >= cap) break;
-        const float4 pr = pairs[pi];
-        const uint32_t pw = __float_as_uint(pr.w);
-        const int pix = (int)(pw & 63u);
-        const int i = x0 + (pix & 7), j = y0 + (pix >> 3);
-        const size_t p = (size_t)j * V.W + i;
-        float gr[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) gr[q] = V.dout[q * plane + p];
-        pair_grad_all<true>(R, (float)i + 0.5f, (float)j + 0.5f, gr, pr.x, pr.y, pr.z, (int)((pw >> 6) & 15u), g);
-      }
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  // (32 KB of LDS in all: five workgroups per CU)
+  __shared__ float gs[PG_W + PG_TAIL][PG_LD];
+  __shared__ uint32_t hrow[PG_W];   // the window's segments: their first row | pair count << 16
+  __shared__ uint2 hseg[PG_W];      // ... record, gradient slot
+  __shared__ uint32_t wheads[PG_W / 64];
+
+  for (uint32_t w0 = blockIdx.x * PG_W; w0 < npair; w0 += gridDim.x * PG_W) {
+    const uint32_t pidx = w0 + threadIdx.x;
+    const bool have = pidx < npair;
+    PairIn q;
+    q.ok = false;
+    if (have) q = pair_load(pairs, pidx, L);
+    const bool head = q.ok && (q.a.w & PAIR_HEAD) != 0u;
+    const uint64_t hb = __ballot(head);
+    // the first wave: the pairs after the window up to the next first pair
+    // (or the end) belong to the window's last segment
+    PairIn t;
+    t.ok = false;
+    bool skip = false;
+    if (wave == 0u) {
+      const uint32_t tp = pidx + PG_W;
+      if (tp < npair) t = pair_load(pairs, tp, L);
+      const uint64_t tb = __ballot(tp >= npair || (t.a.w & PAIR_HEAD) != 0u);
+      const uint32_t tn = tb ? (uint32_t)__ffsll((unsigned long long)tb) - 1u : 64u;
+      t.ok = t.ok && lane < tn;
+      // pairs before the window's first segment start belong to the previous window
+      const uint32_t h0 = hb ? (uint32_t)__ffsll((unsigned long long)hb) - 1u : 64u;
+      skip = lane < h0 && w0 > 0u;
     }
-    float r[8];
-    quad_transpose_sum32(g, r);   // lane lg: the segment's sums of g[8 lg .. 8 lg + 7]
-    if (sv && cnt > 0u && lg < 3u) {
+    if (q.ok && !skip) pair_row(q, vw, vrec4, gs[threadIdx.x]);
+    if (t.ok) pair_row(t, vw, vrec4, gs[PG_W + threadIdx.x]);
+    if (lane == 0u) wheads[wave] = (uint32_t)__popcll(hb);
+    __syncthreads();
+    if (head) {
+      uint32_t h = (uint32_t)__popcll(hb & ((1ull << lane) - 1ull));
+      for (uint32_t w = 0; w < wave; ++w) h += wheads[w];
+      hrow[h] = threadIdx.x | (min((q.a.w >> 11) & 127u, 64u) << 16);
+      hseg[h] = make_uint2(q.b.x, q.b.w);
+    }
+    uint32_t nh = 0u;
+#pragma unroll
+    for (int w = 0; w < PG_W / 64; ++w) nh += wheads[w];
+    __syncthreads();
+    for (uint32_t it = threadIdx.x; it < nh * TGRAD_STRIDE; it += PG_W) {
+      const uint32_t h = it / TGRAD_STRIDE, k = it - h * TGRAD_STRIDE;
+      const uint32_t r0 = hrow[h] & 0xffffu, cnt = k < (uint32_t)PG_G ? hrow[h] >> 16 : 0u;
+      const uint2 hs = hseg[h];
+      // eight rows per step, their reads in flight together (a fixed order)
+      float sum = 0.0f;
+      for (uint32_t m0 = 0; m0 < cnt; m0 += 8u) {
+        float v[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8u; ++u) v[u] = m0 + u < cnt ? gs[r0 + m0 + u][k] : 0.0f;
+        sum += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+      }
       if (per_record) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (8 * lg + q < TGRAD_STRIDE - 1 && r[q] != 0.0f)
-            unsafeAtomicAdd(&tgrad[(size_t)sg.x * TGRAD_STRIDE + 8 * lg + q], r[q]);
-      } else if ((uint64_t)sg.y < cap) {
-        float4* dst = reinterpret_cast<float4*>(tgrad + (size_t)sg.y * TGRAD_STRIDE + 8 * lg);
-        dst[0] = make_float4(r[0], r[1], r[2], r[3]);
-        dst[1] = make_float4(r[4], r[5], r[6], r[7]);
-        if (lg == 0u) eflag[sg.y] = 1;
+        if (k < TGRAD_STRIDE - 1 && sum != 0.0f) unsafeAtomicAdd(&tgrad[(size_t)hs.x * TGRAD_STRIDE + k], sum);
+      } else if ((uint64_t)hs.y < cap) {
+        tgrad[(size_t)hs.y * TGRAD_STRIDE + k] = sum;
+        if (k == 0u) eflag[hs.y] = 1;
       }
     }
+    __syncthreads();
   }
 }
 
 hipError_t launch_pair_grads(void* ws, const Layout& L, hipStream_t st) {
   if (L.o_pairs == 0) return hipErrorInvalidValue;
-  const int64_t b = (L.entry_cap + 63) / 64;   // 64 segments per block and pass
+  const int64_t b = (L.entry_cap + PG_W - 1) / PG_W;   // one window of pairs per block and pass
   const unsigned blocks = (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
   k_pair_grads<<<blocks, 256, 0, st>>>(ws, L);
   return hipGetLastError();

@@ -135,10 +135,8 @@ struct Layout {
   size_t o_bwd_hist, o_bwd_order, o_bwd_pend;  // backward dispatch order (by walked length)
   // multi-wave 8x8 backward (0 otherwise): per forward slot (blended pairs,
   // entries with a blended pixel); per backward slot the bases and counts of
-  // its pairs and segments; the pairs (dL/df_prev, dL/df_next, T alpha,
-  // pixel | faces << 6) and segments (record, gradient slot, first pair,
-  // pair count | backward slot << 7)
-  size_t o_slot_pairs, o_bwd_base, o_pairs, o_segs;
+  // its pairs and segments; 32 bytes per blended (entry, pixel) pair
+  size_t o_slot_pairs, o_bwd_base, o_pairs;
   size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
   // deterministic backward (0 otherwise): per kept-tet corner a vertex key and
   // corner id (double-buffered for the sort) and its 7 gradient terms (8 floats)

@@ -236,7 +236,7 @@ class Renderer:
                     self._caps[sig] = (kept_cap, entry_cap)
                 return plan
             kept_cap = int(need_kept * 1.25) if (stt.overflow & 1) else kept_cap
-            entry_cap = int(need_ent * 1.3) + 4096 if (stt.overflow & 2) else entry_cap
+            entry_cap = int(need_ent * 1.3) + 4096 if (stt.overflow & 6) else entry_cap
             if stt.overflow & 1:
                 entry_cap = max(entry_cap, 2 * entry_cap)
         raise RuntimeError("could not size the workspace")
@@ -252,7 +252,7 @@ class Renderer:
         if s.overflow:
             k, e = self._caps.get(plan.sig, (0, 0))
             self._caps[plan.sig] = (int(s.kept * 1.25) + 1024 if s.overflow & 1 else k,
-                                    int(s.entries_needed * 1.3) + 4096 if s.overflow & 2 else e)
+                                    int(s.entries_needed * 1.3) + 4096 if s.overflow & 6 else e)
             raise CapacityError("workspace capacity exceeded in a forward pass; its outputs are invalid "
                                 "(capacities enlarged for the next call)")
         if s.invalid_index:

@@ -304,7 +304,7 @@ class Server:
             if s.invalid_index:
                 for r in L.requests:
                     r.error = "a tet of the scene has a vertex index outside [0, V)"
-            if s.overflow:
+            if s.overflow & 3:   # (bit 2 concerns a backward only: a served forward stands)
                 # outgrown capacities: re-run this launch with the exact sizes and
                 # remember larger estimates for the scene/size pairs it holds
                 sids, cams, vs, caps = L.args[i]

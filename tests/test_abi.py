@@ -243,10 +243,10 @@ def test_resort_window_arguments(L):
     assert rc == 0
     p.window = 5
     rc, with_win = _size(L, scenes, views, p, ent=10000)
-    # (the window path keeps no pair buffers: 32 bytes per entry and 16 per
+    # (the window path keeps no pair buffers: 32 bytes per entry and 24 per
     # tile of the plain 8x8 path, 256-byte aligned)
     tiles = 8 * 8
-    assert rc == 0 and with_win >= base - 32 * 10000 - 16 * tiles - 4 * 256 + 16 * 64 * 10000
+    assert rc == 0 and with_win >= base - 32 * 10000 - 24 * tiles - 3 * 256 + 16 * 64 * 10000
     for bad in (-1, L.RENDER_WINDOW_MAX + 1):
         p.window = bad
         assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL

@@ -302,6 +302,42 @@ def test_capacity_overflow_is_detected_and_replanned():
     assert np.array_equal(plan3.outs[0].cpu().numpy(), ref[0])
 
 
+def test_pair_overflow_keeps_the_forward_and_replans_the_backward():
+    """Entries that fit while the (entry, pixel) pairs the forward blended do
+    not (the multi-wave 8x8 backward keeps them in entry-capacity buffers):
+    status bit 2 alone, the images stand, the backward is refused until the
+    forward is re-planned, and the re-planned gradients equal those of a
+    workspace sized from the start."""
+    import torch
+    from paper_2406_01579_amd import Renderer, SceneT
+    from paper_2406_01579_amd.frontend import CapacityError
+    w = synth.tiny(s=20.0)
+    sc = w.scenes[0]
+    P = _params("exact", (8, 8), deterministic=True)   # every covered pixel blends: many pairs per entry
+    st = SceneT.from_numpy(sc)
+    r0, plan0, ref = gpu_forward(sc, w.cams, P)
+    E = int(plan0.status.entries)
+    dout = torch.from_numpy(np.random.default_rng(3).normal(size=(8, 64, 64)).astype(np.float32)).cuda()
+    (g0,) = r0.backward(plan0, [dout])
+    g0 = [t.cpu().numpy() for t in g0]
+    r = Renderer(P, check="lazy")
+    sig = r._signature([st], w.cams, np.zeros(1, np.int32))
+    r._caps[sig] = (sc.K, E + 16)
+    plan = r.forward([st], w.cams)
+    torch.cuda.synchronize()
+    s1 = r.read_status(plan)
+    assert s1.overflow == 4 and s1.entries == E and s1.entries_needed > E + 16
+    assert np.array_equal(plan.outs[0].cpu().numpy(), ref[0])
+    with pytest.raises(CapacityError):
+        r.backward(plan, [dout])
+    plan2 = r.forward([st], w.cams)            # enlarged to the pairs it needs
+    torch.cuda.synchronize()
+    assert r.read_status(plan2).overflow == 0 and plan2.entry_cap >= s1.entries_needed
+    (g2,) = r.backward(plan2, [dout])
+    for a, b in zip(g2, g0):
+        assert np.array_equal(a.cpu().numpy(), b)
+
+
 # ---------------------------------------------------------------------------
 # training-shaped workload at full size (64^3 grid, 4 views 512^2, s = 320):
 # tiling in full, sampled pixels, gradients of a sparse upstream gradient
