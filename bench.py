@@ -60,7 +60,8 @@ MEASURED = {"sha256": {"paper_2406_01579_amd/csrc/raster_mw.hip":
 
 def measured_counters(kernel, args):
     import hashlib
-    if (args.tile, args.waves, args.s) != ("8x8", 4, 320.0):
+    if (args.tile, args.waves, args.s, args.chunk_fwd in (0, 64), args.chunk_bwd in (0, 32)) != \
+            ("8x8", 4, 320.0, True, True):
         return None
     for path, digest in MEASURED["sha256"].items():
         with open(os.path.join(ROOT, path), "rb") as f:
@@ -77,6 +78,8 @@ def parse():
     ap.add_argument("--s", type=float, default=320.0)
     ap.add_argument("--tile", default="8x8")
     ap.add_argument("--waves", type=int, default=4, help="waves sharing one 8x8 tile")
+    ap.add_argument("--chunk-fwd", type=int, default=0, help="forward LDS chunk length (32, 64; 0: 64)")
+    ap.add_argument("--chunk-bwd", type=int, default=0, help="backward LDS chunk length (16, 32; 0: 32)")
     ap.add_argument("--check", default="lazy", choices=["sync", "lazy"])
     ap.add_argument("--record-grads", action="store_true",
                     help="backward with one gradient accumulator per record (RENDER_RECORD_GRADS)")
@@ -152,7 +155,8 @@ def main():
     gen.manual_seed(0)
     dout = torch.randn((nv, 8, H, W), device=dev, generator=gen)
     params = Params(tile_w=tw, tile_h=th, waves=args.waves, record_grads=args.record_grads,
-                    recompute_state=args.recompute_state, deterministic=args.deterministic)
+                    recompute_state=args.recompute_state, deterministic=args.deterministic,
+                    chunk_fwd=args.chunk_fwd, chunk_bwd=args.chunk_bwd)
     renderer = Renderer(params, device=dev, check=args.check)
 
     def step(cam_subset=None):
@@ -351,7 +355,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "training-shaped: 64^3-cube Kuhn grid (1,572,864 tets), sphere+torus smooth-union "
                                "SDF + N(0,0.005), per-vertex RGB, 4 orbit views 512x512, s=320, fwd+bwd",
-                   "views": nv, "width": W, "height": H, "tile": args.tile, "waves": args.waves, "s": args.s,
+                   "views": nv, "width": W, "height": H, "tile": args.tile, "waves": args.waves,
+                   "chunks": [args.chunk_fwd or 64, args.chunk_bwd or 32], "s": args.s,
                    "path": ("whole fwd+bwd step through the autograd Function captured in one HIP graph"
                             if args.mode == "graph" else "eager launches through the autograd Function"),
                    "status_check": args.check,
@@ -399,7 +404,8 @@ def workload_bench(args):
     tuner = Autotuner(reps=2, base=Params())
     params = tuner.best(scenes, cams, vs, dout=douts)
     tuned = next(iter(tuner.cache.values()))
-    print(f"[{args.workload}] autotuned {params.tile_w}x{params.tile_h} waves {params.waves}: {tuned['ms']}",
+    print(f"[{args.workload}] autotuned {params.tile_w}x{params.tile_h} waves {params.waves} chunks "
+          f"{params.chunk_fwd}/{params.chunk_bwd}: {tuned['ms']}",
           file=sys.stderr, flush=True)
 
     # exact sizes from one synchronous forward, then capture with headroom
@@ -469,6 +475,7 @@ def workload_bench(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "views": nv, "scenes": len(scenes), "pixels": pixels,
                    "tile": f"{params.tile_w}x{params.tile_h}", "waves": params.waves,
+                   "chunks": [params.chunk_fwd, params.chunk_bwd],
                    "path": "fwd+bwd of all views and scenes in one launch sequence, captured in one HIP graph"},
         "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
         "autotune_ms": tuned["ms"],

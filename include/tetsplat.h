@@ -113,6 +113,11 @@ typedef struct {
                              nearest first (equal depths: arrival order); only candidates with
                              alpha >= alpha_min enter.  Needs 8x8 tiles; the workspace then holds
                              16 B per (entry, pixel of its tile) for the backward. */
+  int32_t chunk_fwd;      /* entries staged in LDS per step of the forward's walk of a tile list:
+                             32 or 64 (0: 64).  With chunk_bwd, only on the multi-wave 8x8 path
+                             (8x8 tiles, waves > 1, no resort window).  A speed knob: images and
+                             gradients do not depend on it. */
+  int32_t chunk_bwd;      /* the same for the backward's walk: 16 or 32 (0: 32) */
 } render_params;
 
 #define RENDER_WINDOW_MAX 8

@@ -28,7 +28,7 @@ class render_params(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("flags", C.c_int32), ("waves", C.c_int32),
                 ("alpha_min", C.c_float),
                 ("alpha_clamp", C.c_float), ("t_min", C.c_float), ("prefilter_tf", C.c_float),
-                ("window", C.c_int32)]
+                ("window", C.c_int32), ("chunk_fwd", C.c_int32), ("chunk_bwd", C.c_int32)]
 
 
 class render_grads(C.Structure):

@@ -75,6 +75,14 @@ int check_args(const render_scene* scenes, int ns, const render_view* views, int
     return fail(RENDER_EINVAL, "window must be in [0, %d] (got %d)", RENDER_WINDOW_MAX, p->window);
   if (p->window > 0 && (p->tile_w != 8 || p->tile_h != 8))
     return fail(RENDER_EINVAL, "the resort window needs 8x8 tiles (got %dx%d)", p->tile_w, p->tile_h);
+  if (!(p->chunk_fwd == 0 || p->chunk_fwd == 32 || p->chunk_fwd == 64))
+    return fail(RENDER_EINVAL, "chunk_fwd must be 0, 32 or 64 (got %d)", p->chunk_fwd);
+  if (!(p->chunk_bwd == 0 || p->chunk_bwd == 16 || p->chunk_bwd == 32))
+    return fail(RENDER_EINVAL, "chunk_bwd must be 0, 16 or 32 (got %d)", p->chunk_bwd);
+  if ((p->chunk_fwd | p->chunk_bwd) != 0 &&
+      (p->tile_w != 8 || p->tile_h != 8 || p->waves == 1 || p->window > 0))
+    return fail(RENDER_EINVAL, "chunk lengths apply to the multi-wave 8x8 path only (8x8 tiles, waves > 1, "
+                "no resort window)");
   for (int s = 0; s < ns; ++s) {
     const render_scene& S = scenes[s];
     if (S.V < 0 || S.K < 0) return fail(RENDER_EINVAL, "scene %d: negative V or K", s);
@@ -242,8 +250,8 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_wpair = p->window > 0 ? take(16 * 64 * (size_t)entry_cap) : 0;
   const bool pairs_path = p->window == 0 && p->tile_w == 8 && p->tile_h == 8 && p->waves != 1;
   if (pairs_path) {
-    L.o_slot_pairs = take(8 * (size_t)tiles);
-    L.o_bwd_base = take(16 * (size_t)tiles);
+    L.o_slot_pairs = take(4 * (size_t)tiles);
+    L.o_bwd_base = take(4 * (size_t)tiles);
     L.o_pairs = take(32 * (size_t)entry_cap);   // at most entry_capacity blended pairs
   }
   if (det) {
@@ -278,6 +286,8 @@ int effective_waves(const render_params& p) { return p.waves == 0 ? 4 : p.waves;
 bool multiwave(const render_params& p) { return p.tile_w == 8 && p.tile_h == 8 && effective_waves(p) > 1; }
 render_params with_waves(render_params p) {
   p.waves = effective_waves(p);
+  if (p.chunk_fwd == 0) p.chunk_fwd = 64;
+  if (p.chunk_bwd == 0) p.chunk_bwd = 32;
   return p;
 }
 

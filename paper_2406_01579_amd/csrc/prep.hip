@@ -779,10 +779,9 @@ hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
 // (the forward compositing kernel counted every slot with pend > start; the
 // tiles with nothing walked form bucket 0, placed last, whose own count the
 // offsets never need).  On the multi-wave 8x8 path every slot also gets the
-// bases of its blended pairs and of its segments (the (tile, entry) pairs
-// with a blended pixel) in the backward's pair buffers, by the same bucket
-// scheme (the forward counted them per slot and per bucket), and the totals
-// are checked against the entry capacity, which bounds the pairs.
+// base of its blended pairs in the backward's pair buffer, by the same
+// bucket scheme (the forward counted them per slot and per bucket), and the
+// total is checked against the entry capacity, which bounds the pairs.
 __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   const TileSlot* slots = at<const TileSlot>(ws, L.o_tile_order);
   const uint32_t* pend = at<const uint32_t>(ws, L.o_tile_pend);
@@ -793,14 +792,11 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   const bool pairs = L.o_pairs != 0;
   __shared__ uint32_t cnt[TILE_BUCKETS], base[TILE_BUCKETS], first[TILE_BUCKETS], lds[8];
   __shared__ uint32_t pcnt[TILE_BUCKETS], pbase[TILE_BUCKETS], pfirst[TILE_BUCKETS];
-  __shared__ uint32_t scnt[TILE_BUCKETS], sbase[TILE_BUCKETS], sfirst[TILE_BUCKETS];
-  if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = pcnt[threadIdx.x] = scnt[threadIdx.x] = 0;
+  if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = pcnt[threadIdx.x] = 0;
   bucket_first(hist, first, lds);
   __syncthreads();
   if (pairs) {
     bucket_first(hist + 2 * TILE_BUCKETS, pfirst, lds);
-    __syncthreads();
-    bucket_first(hist + 4 * TILE_BUCKETS, sfirst, lds);
     __syncthreads();
   }
   // the slots before bucket 0 are the tiles with something walked
@@ -808,13 +804,9 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
     DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
     hdr->bwd_work = first[0];
     if (pairs) {
-      uint64_t np = 0, nsg = 0;
-      for (int b = 0; b < TILE_BUCKETS; ++b) {
-        np += hist[2 * TILE_BUCKETS + b];
-        nsg += hist[4 * TILE_BUCKETS + b];
-      }
+      uint64_t np = 0;
+      for (int b = 0; b < TILE_BUCKETS; ++b) np += hist[2 * TILE_BUCKETS + b];
       hdr->pairs_total = (uint32_t)min(np, (uint64_t)0xffffffffu);
-      hdr->segs_total = (uint32_t)min(nsg, (uint64_t)0xffffffffu);
       if (np > (uint64_t)L.entry_cap) {   // the forward's outputs stand; its backward would not
         hdr->overflow |= 4u;
         if (np > hdr->entries_needed) hdr->entries_needed = np;
@@ -823,36 +815,28 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
   }
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   int b = 0;
-  uint32_t rank = 0, prank = 0, srank = 0;
+  uint32_t rank = 0, prank = 0;
   TileSlot sl{};
   uint32_t pe = 0;
-  uint2 ps = make_uint2(0u, 0u);
   if (t < (uint32_t)L.total_tiles) {
     sl = slots[t];
     pe = pend[t];
     b = len_bucket(pe - sl.start);
     rank = atomicAdd(&cnt[b], 1u);
-    if (pairs && pe > sl.start) {
-      ps = at<const uint2>(ws, L.o_slot_pairs)[t];
-      prank = atomicAdd(&pcnt[b], ps.x);
-      srank = atomicAdd(&scnt[b], ps.y);
-    }
+    if (pairs && pe > sl.start) prank = atomicAdd(&pcnt[b], at<const uint32_t>(ws, L.o_slot_pairs)[t]);
   }
   __syncthreads();
   if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) {
     base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
-    if (pairs) {
+    if (pairs)
       pbase[threadIdx.x] = pfirst[threadIdx.x] +
                            atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + 3 * TILE_BUCKETS + threadIdx.x, pcnt[threadIdx.x]);
-      sbase[threadIdx.x] = sfirst[threadIdx.x] +
-                           atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + 5 * TILE_BUCKETS + threadIdx.x, scnt[threadIdx.x]);
-    }
   }
   __syncthreads();
   if (t < (uint32_t)L.total_tiles) {
     bslots[base[b] + rank] = sl;
     bpend[base[b] + rank] = pe;
-    if (pairs) at<uint4>(ws, L.o_bwd_base)[base[b] + rank] = make_uint4(pbase[b] + prank, sbase[b] + srank, ps.x, ps.y);
+    if (pairs) at<uint32_t>(ws, L.o_bwd_base)[base[b] + rank] = pbase[b] + prank;
   }
 }
 

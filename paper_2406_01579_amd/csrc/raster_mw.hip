@@ -39,8 +39,7 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
                                               uint64_t* pmask, uint32_t* poff, uint64_t* hm, float (*feat)[CHN],
                                               unsigned long long* done_mask,
                                               float& T, float& Tb, float& O, float (&acc)[7], int& last,
-                                              bool want_acc, uint32_t* nblend = nullptr,
-                                              uint32_t* nseg = nullptr) {
+                                              bool want_acc, uint32_t* nblend = nullptr) {
   constexpr int NT = 64 * NWV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool done = !c.inside;
@@ -114,18 +113,7 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
           }
         }
       }
-      if (nblend) {
-        // the chunk's blended pairs (per lane) and its entries with a blended
-        // pixel (the same in every lane)
-        *nblend += (uint32_t)__popcll(blended);
-        uint32_t lo = (uint32_t)blended, hi = (uint32_t)(blended >> 32);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          lo |= (uint32_t)__shfl_xor((int)lo, o, 64);
-          hi |= (uint32_t)__shfl_xor((int)hi, o, 64);
-        }
-        *nseg += (uint32_t)(__popc(lo) + __popc(hi));
-      }
+      if (nblend) *nblend += (uint32_t)__popcll(blended);   // the chunk's blended pairs (per lane)
       const unsigned long long m = __ballot(done);
       if (lane == 0) *done_mask = m;
     }
@@ -172,10 +160,9 @@ __device__ __forceinline__ void background_tiles(void* ws, const Layout& L, cons
 
 }  // namespace
 
-template <int NWV>
+template <int NWV, int CHN>
 __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, float alpha_min, float alpha_clamp,
                                                            float t_min) {
-  constexpr int CHN = 64;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
@@ -209,11 +196,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int last = -1;
-  uint32_t nblend = 0, nseg = 0;
+  uint32_t nblend = 0;
   const bool count = L.o_pairs != 0;
   forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff, hm,
-                          feat, &done_mask, T, Tb, O, acc, last, true, count ? &nblend : nullptr,
-                          count ? &nseg : nullptr);
+                          feat, &done_mask, T, Tb, O, acc, last, true, count ? &nblend : nullptr);
   if ((threadIdx.x >> 6) == 0) {
     // end of the tile's blended prefix: where the backward starts its walk
     int wmax = last;
@@ -225,17 +211,14 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
     if ((threadIdx.x & 63) == 0) {
       const uint32_t pend = wmax >= (int)start ? (uint32_t)wmax + 1u : start;
       at<uint32_t>(ws, L.o_tile_pend)[blockIdx.x] = pend;
-      if (count) at<uint2>(ws, L.o_slot_pairs)[blockIdx.x] = make_uint2(nblend, nseg);
-      // the backward dispatch order's histograms of walked lengths, blended
-      // pairs and segments (bucket 0, nothing walked, is not counted)
+      if (count) at<uint32_t>(ws, L.o_slot_pairs)[blockIdx.x] = nblend;
+      // the backward dispatch order's histograms of walked lengths and of
+      // blended pairs (bucket 0, nothing walked, is not counted)
       if (pend > start) {
         uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
         const int b = len_bucket(pend - start);
         atomicAdd(bh + b, 1u);
-        if (count) {
-          atomicAdd(bh + 2 * TILE_BUCKETS + b, nblend);
-          atomicAdd(bh + 4 * TILE_BUCKETS + b, nseg);
-        }
+        if (count) atomicAdd(bh + 2 * TILE_BUCKETS + b, nblend);
       }
     }
   }
@@ -267,11 +250,11 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
 // per-(record, tile) gradient slot, its first pair and pair count); the
 // tile's pairs and segments start at the bases the forward's counts gave
 // this backward slot.
-template <int NWV>
+template <int NWV, int CHB>
 __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout L, float alpha_min,
                                                                float alpha_clamp, float t_min, int recompute) {
+  static_assert(CHB <= 32, "a pixel's chunk candidates are a 32-bit mask");
   constexpr int NT = 64 * NWV;
-  constexpr int CHB = 32;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
@@ -338,9 +321,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
     Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
   }
-  // this tile's pairs and segments
-  const uint4 pb = at<const uint4>(ws, L.o_bwd_base)[blockIdx.x];
-  uint32_t pair_run = pb.x;
+  // where this tile's pairs go
+  uint32_t pair_run = at<const uint32_t>(ws, L.o_bwd_base)[blockIdx.x];
   const uint32_t tile_xy = (uint32_t)c.tx | ((uint32_t)c.ty << 16);
 
   bool first = true;
@@ -617,12 +599,20 @@ hipError_t launch_pair_grads(void* ws, const Layout& L, hipStream_t st) {
 
 template <int NWV>
 static void launch_fwd_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  k_composite_mw<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp, p.t_min);
+  if (p.chunk_fwd == 32)
+    k_composite_mw<NWV, 32><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp, p.t_min);
+  else
+    k_composite_mw<NWV, 64><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp, p.t_min);
 }
 template <int NWV>
 static void launch_bwd_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  k_composite_bwd_mw<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(
-      ws, L, p.alpha_min, p.alpha_clamp, p.t_min, (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0);
+  const int rc = (p.flags & RENDER_RECOMPUTE_STATE) ? 1 : 0;
+  if (p.chunk_bwd == 16)
+    k_composite_bwd_mw<NWV, 16><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                               p.t_min, rc);
+  else
+    k_composite_bwd_mw<NWV, 32><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                               p.t_min, rc);
 }
 
 hipError_t launch_composite_mw(void* ws, const Layout& L, const render_params& p, hipStream_t st) {

@@ -65,8 +65,7 @@ struct DevHeader {
   int64_t entry_capacity, kept_capacity;
   uint64_t entries_needed;  // entries the last forward wanted (exact, also on overflow)
   uint32_t pairs_total;     // (entry, pixel) pairs the forward blended (multi-wave 8x8 path)
-  uint32_t segs_total;      // (tile, entry) pairs with at least one blended pixel
-  uint32_t pad1[48];
+  uint32_t pad1[49];
 };
 static_assert(sizeof(DevHeader) == 256, "header is 256 bytes");
 
@@ -133,9 +132,9 @@ struct Layout {
   size_t o_tile_cnt, o_tile_bsum;   // entries per tile (then the emit cursor); per 1024-tile block, its start
   size_t o_tile_pend;    // per dispatch slot: end of the entries the forward blended (backward walk)
   size_t o_bwd_hist, o_bwd_order, o_bwd_pend;  // backward dispatch order (by walked length)
-  // multi-wave 8x8 backward (0 otherwise): per forward slot (blended pairs,
-  // entries with a blended pixel); per backward slot the bases and counts of
-  // its pairs and segments; 32 bytes per blended (entry, pixel) pair
+  // multi-wave 8x8 backward (0 otherwise): per forward slot its blended
+  // pairs; per backward slot the base of its pairs; 32 bytes per blended
+  // (entry, pixel) pair
   size_t o_slot_pairs, o_bwd_base, o_pairs;
   size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
   // deterministic backward (0 otherwise): per kept-tet corner a vertex key and
@@ -169,9 +168,9 @@ hipError_t launch_count_scan(void* ws, const Layout& L, const render_params& p, 
 hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st);
 constexpr int TILE_BUCKETS = 129;  // tiles bucketed by list length, four buckets per power of two
-// the backward-order histogram region: slot counts, slot cursors, pair totals,
-// pair cursors, segment totals, segment cursors (TILE_BUCKETS each)
-constexpr int BWD_HIST_WORDS = 6 * TILE_BUCKETS;
+// the backward-order histogram region: slot counts, slot cursors, pair totals
+// and pair cursors (TILE_BUCKETS each)
+constexpr int BWD_HIST_WORDS = 4 * TILE_BUCKETS;
 hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_composite(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_composite_backward(void* ws, const Layout& L, const render_params& p, hipStream_t st);

@@ -36,6 +36,8 @@ class Params:
     window: int = 0  # per-pixel resort window N_w (Sec. 3.3); 0: per-tile order
     deterministic: bool = False     # bitwise-reproducible gradients (fixed-order sums)
     record_grads: bool = False      # one gradient accumulator per record instead of per entry
+    chunk_fwd: int = 0   # entries per LDS step of the forward's tile walk (32, 64; 0: 64), multi-wave 8x8 only
+    chunk_bwd: int = 0   # the same for the backward (16, 32; 0: 32)
 
     def flags(self) -> int:
         return ((_lib.RENDER_RECOMPUTE_STATE if self.recompute_state else 0) |
@@ -44,7 +46,8 @@ class Params:
 
     def c(self) -> _lib.render_params:
         return _lib.render_params(self.tile_w, self.tile_h, self.flags(), self.waves,
-                                  self.alpha_min, self.alpha_clamp, self.t_min, self.prefilter_tf, self.window)
+                                  self.alpha_min, self.alpha_clamp, self.t_min, self.prefilter_tf, self.window,
+                                  self.chunk_fwd, self.chunk_bwd)
 
     @classmethod
     def exact(cls, **kw):

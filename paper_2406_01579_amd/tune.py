@@ -1,9 +1,15 @@
 """Autotuner for the compositing launch shape.
 
 The knobs are the screen tile (8x8, 16x8, 8x16, 16x16, 32x8) and, for 8x8
-tiles, the number of 64-lane waves that share a tile (1, 2, 4, 8).  Every
-candidate produces the same images (the per-pixel arithmetic and blend order
-do not depend on the tiling), so the choice is purely a speed decision.
+tiles, the per-lane work and the LDS chunk lengths.  The per-lane work is set
+by the number of 64-lane waves that share a tile (1, 2, 4, 8): the waves
+split a chunk's (entry, pixel) pairs between them, so one wave evaluates
+eight times the pairs per lane of eight waves.  With several waves, the
+entries staged in LDS per step of a tile's walk are 32 or 64 (forward) and
+16 or 32 (backward): shorter chunks mean less LDS per workgroup (more of them
+per CU) but more steps, each a round of barriers.  Every candidate produces
+the same images and gradients (the per-pixel arithmetic and blend order do
+not depend on the launch shape), so the choice is purely a speed decision.
 
 The tuner times forward + backward of each candidate on the caller's actual
 scenes and views (median of a few repetitions, HIP events on the rendering
@@ -23,16 +29,29 @@ from .frontend import Params
 
 TILES = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8)]
 WAVES = [1, 2, 4, 8]
+CHUNKS_FWD = [32, 64]
+CHUNKS_BWD = [16, 32]
 
 
 def candidates():
+    """(tile_w, tile_h, waves, chunk_fwd, chunk_bwd); chunk 0: the kernel's
+    fixed length (the one-wave and larger-tile kernels have no chunk knob)."""
     out = []
     for tw, th in TILES:
         if (tw, th) == (8, 8):
-            out += [(tw, th, w) for w in WAVES]
+            for w in WAVES:
+                if w == 1:
+                    out.append((tw, th, w, 0, 0))
+                else:
+                    out += [(tw, th, w, cf, cb) for cf in CHUNKS_FWD for cb in CHUNKS_BWD]
         else:
-            out.append((tw, th, 1))
+            out.append((tw, th, 1, 0, 0))
     return out
+
+
+def label(cand) -> str:
+    tw, th, w, cf, cb = cand
+    return f"{tw}x{th}w{w}" + (f"f{cf}b{cb}" if cf else "")
 
 
 def _bits(x: int) -> int:
@@ -68,20 +87,19 @@ class Autotuner:
 
     def params_for(self, cand) -> Params:
         d = asdict(self.base)
-        d.update(tile_w=cand[0], tile_h=cand[1], waves=cand[2])
+        d.update(tile_w=cand[0], tile_h=cand[1], waves=cand[2], chunk_fwd=cand[3], chunk_bwd=cand[4])
         return Params(**d)
 
     def tune(self, key: str, measure) -> Params:
         """measure(params) -> seconds.  Returns (and caches) the fastest."""
-        if key in self.cache:
+        if key in self.cache and len(self.cache[key].get("best", ())) == 5:   # (older entries: re-tuned)
             return self.params_for(tuple(self.cache[key]["best"]))
         times = {}
         for cand in candidates():
             t = measure(self.params_for(cand))
             times[cand] = t
         best = min(times, key=times.get)
-        self.cache[key] = {"best": list(best), "ms": {f"{c[0]}x{c[1]}w{c[2]}": round(1e3 * t, 4)
-                                                      for c, t in times.items()}}
+        self.cache[key] = {"best": list(best), "ms": {label(c): round(1e3 * t, 4) for c, t in times.items()}}
         self._save()
         return self.params_for(best)
 

@@ -243,10 +243,10 @@ def test_resort_window_arguments(L):
     assert rc == 0
     p.window = 5
     rc, with_win = _size(L, scenes, views, p, ent=10000)
-    # (the window path keeps no pair buffers: 32 bytes per entry and 24 per
+    # (the window path keeps no pair buffers: 32 bytes per entry and 8 per
     # tile of the plain 8x8 path, 256-byte aligned)
     tiles = 8 * 8
-    assert rc == 0 and with_win >= base - 32 * 10000 - 24 * tiles - 3 * 256 + 16 * 64 * 10000
+    assert rc == 0 and with_win >= base - 32 * 10000 - 8 * tiles - 3 * 256 + 16 * 64 * 10000
     for bad in (-1, L.RENDER_WINDOW_MAX + 1):
         p.window = bad
         assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL
@@ -255,6 +255,31 @@ def test_resort_window_arguments(L):
     p2.window = 3
     assert _size(L, s2, v2, p2)[0] == L.RENDER_EINVAL
     assert b"8x8" in L.lib().render_last_error()
+
+
+def test_chunk_length_arguments(L):
+    """LDS chunk lengths: forward 32/64, backward 16/32 (0: the defaults), on
+    the multi-wave 8x8 path only; they do not change the workspace."""
+    w = synth.tiny()
+    scenes, views, p = _args(L, w, (8, 8))
+    rc, base = _size(L, scenes, views, p)
+    assert rc == 0
+    for cf, cb in ((32, 16), (64, 32), (32, 0), (0, 16)):
+        p.chunk_fwd, p.chunk_bwd = cf, cb
+        rc, n = _size(L, scenes, views, p)
+        assert rc == 0 and n == base
+    for cf, cb in ((16, 0), (128, 0), (0, 8), (0, 64), (-32, 0)):
+        p.chunk_fwd, p.chunk_bwd = cf, cb
+        assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL
+        assert b"chunk" in L.lib().render_last_error()
+    p.chunk_fwd, p.chunk_bwd = 32, 16
+    for waves, window in ((1, 0), (4, 3)):
+        p.waves, p.window = waves, window
+        assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL
+    p.waves, p.window = 4, 0
+    s2, v2, p2 = _args(L, w, (16, 16))
+    p2.chunk_fwd = 32
+    assert _size(L, s2, v2, p2)[0] == L.RENDER_EINVAL
 
 
 def test_coarse_grid_entry_points_validate_on_the_host(L):

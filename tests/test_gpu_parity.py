@@ -102,6 +102,42 @@ def test_tiny_gradients(tile, mode, s, recompute):
     check_gradients((dv, ds, dc), refs, f"tiny {tile} {mode} s={s} recompute={recompute}")
 
 
+def _tuner_candidates():
+    from paper_2406_01579_amd import tune
+    return tune.candidates(), [tune.label(c) for c in tune.candidates()]
+
+
+@pytest.mark.parametrize("cand", _tuner_candidates()[0], ids=_tuner_candidates()[1])
+def test_every_tuner_candidate_against_the_oracle(cand):
+    """Every launch shape the autotuner may pick (tile, waves per 8x8 tile,
+    forward and backward LDS chunk lengths): images of the tiny grid against
+    the oracle, and the gradients of a dense upstream gradient on it and on a
+    ragged image, with stored and with recomputed per-pixel state."""
+    import torch
+    tw, th, wv, cf, cb = cand
+    s = 100.0
+    w = synth.tiny(s=s, bg=(0.3, 0.1, 0.2))
+    sc = w.scenes[0]
+    g = oracle.Geometry.of(sc)
+    Wd, Hd = 130, 9
+    rag = synth.orbit_camera(0.7, 0.35, 2.5, 50.0, Wd, Hd, bg=(0.2, 0.5, 0.1))[None]
+    rag[0, 17] = Hd / 2.0
+    for cams, seed, rc in ((w.cams, 5, False), (rag, 21, True)):
+        P = _params("default", (tw, th), waves=wv, chunk_fwd=cf, chunk_bwd=cb, recompute_state=rc)
+        op = oracle_params(P, s)
+        r, plan, imgs = gpu_forward(sc, cams, P)
+        err32, n_ex, n = compare_images(imgs, g, cams, op, s)
+        assert err32 <= IMG_TOL and n_ex <= max(1, int(1e-4 * n)), (cand, err32, n_ex)
+        H, W = int(cams[0][1]), int(cams[0][0])
+        dout = np.random.default_rng(seed).normal(size=(8, H, W)).astype(np.float32)
+        (dv, ds, dc), = r.backward(plan, [torch.from_numpy(dout).cuda()])
+        torch.cuda.synchronize()
+        pix = oracle.all_pixels(cams)
+        dflat = np.stack([dout[:, j, i] for (_, i, j) in pix], 0).astype(np.float32)
+        refs = oracle_gradients(g, cams, op, pix, dflat)
+        check_gradients((dv, ds, dc), refs, f"candidate {cand} {W}x{H} recompute={rc}")
+
+
 def test_recompute_state_matches_stored_state():
     import torch
     w = synth.tiny(s=100.0)

@@ -30,7 +30,7 @@ def test_autotuner_measures_caches_and_keeps_images(tmp_path):
     (key, entry), = cache.items()
     assert len(entry["ms"]) == len(candidates())
     assert all(v > 0 for v in entry["ms"].values())
-    assert tuple(entry["best"]) == (best.tile_w, best.tile_h, best.waves)
+    assert tuple(entry["best"]) == (best.tile_w, best.tile_h, best.waves, best.chunk_fwd, best.chunk_bwd)
     _, _, a = gpu_forward(w.scenes[0], w.cams, Params())
     _, _, b = gpu_forward(w.scenes[0], w.cams, best)
     for x, y in zip(a, b):
