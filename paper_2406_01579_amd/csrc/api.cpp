@@ -247,8 +247,14 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   const bool keep_state = (p->flags & RENDER_RECOMPUTE_STATE) == 0;
   L.o_last = keep_state ? take(4 * (size_t)pixels) : 0;
   L.o_tlast = keep_state ? take(4 * (size_t)pixels) : 0;
-  L.o_wpair = p->window > 0 ? take(16 * 64 * (size_t)entry_cap) : 0;
-  const bool pairs_path = p->window == 0 && p->tile_w == 8 && p->tile_h == 8 && p->waves != 1;
+  if (p->window > 0) {
+    L.o_wblend = take(32 * (size_t)entry_cap);   // at most entry_capacity blends
+    L.o_wmask = take(8 * (size_t)entry_cap);
+    L.o_wbase = take(4 * (size_t)entry_cap);
+  }
+  // the 8x8 backwards that go through per-pair terms: multi-wave, and every
+  // resort-window launch
+  const bool pairs_path = p->tile_w == 8 && p->tile_h == 8 && (p->waves != 1 || p->window > 0);
   if (pairs_path) {
     L.o_slot_pairs = take(4 * (size_t)tiles);
     L.o_bwd_base = take(4 * (size_t)tiles);
@@ -504,8 +510,7 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
                                 : launch_composite(workspace, L, *params, st),
            "composite");
   // the backward's dispatch order, and the places of its per-pair terms
-  if (params->window == 0 && multiwave(*params))
-    TS_STAGE(RENDER_STAGE_RANGES, launch_bwd_order(workspace, L, st), "backward tile order");
+  if (L.o_pairs != 0) TS_STAGE(RENDER_STAGE_RANGES, launch_bwd_order(workspace, L, st), "backward tile order");
   return RENDER_OK;
 }
 
@@ -541,8 +546,7 @@ int render_backward(const render_scene* scenes, int n_scenes, const render_view*
            : multiwave(*params) ? launch_composite_backward_mw(workspace, L, with_waves(*params), st)
                                 : launch_composite_backward(workspace, L, *params, st),
            "composite backward");
-  if (params->window == 0 && multiwave(*params))
-    TS_STAGE(RENDER_STAGE_PAIR_GRADS, launch_pair_grads(workspace, L, st), "pair gradients");
+  if (L.o_pairs != 0) TS_STAGE(RENDER_STAGE_PAIR_GRADS, launch_pair_grads(workspace, L, st), "pair gradients");
   TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_backward(workspace, L, *params, st), "vertex backward");
   if (deterministic(L)) TS_STAGE(RENDER_STAGE_VERTEX_BWD, launch_vertex_gather(workspace, L, st), "vertex gather");
   return RENDER_OK;

@@ -843,8 +843,8 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
 hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
-  // histogram: counted by the forward compositing kernel; cursors: cleared
-  // with the gradients
+  // histograms: counted by the forward compositing kernel; cursors: cleared
+  // by the project kernel
   k_bwd_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
 }

@@ -21,13 +21,6 @@ namespace ts {
 
 namespace {
 
-// A blended (entry, pixel) pair of the backward, 32 bytes: dL/df_prev,
-// dL/df_next, the blend weight T alpha and a word (pixel | entry and exit
-// faces << 6 | PAIR_HEAD on the first pair of its segment, which also holds
-// the segment's pair count << 11); then the entry's record, view, tile
-// (x | y << 16) and gradient slot.  A segment is a (tile, entry) with blended
-// pixels: its pairs are consecutive, at most 64 (one per tile pixel).
-constexpr uint32_t PAIR_HEAD = 1u << 10;
 
 // Forward sweep over [start, end) with NWV waves; wave 0 ends with the
 // pixel's blend state.  Used by the forward kernel and by the backward's

@@ -19,16 +19,16 @@
 //
 // Backward: a pixel's blend order is no longer the tile order, so the
 // reverse-order walk of the plain backward does not apply.  Sweep 1 replays
-// the window front to back and records, for every blended (entry, pixel)
-// pair, the transmittance before the blend, the raw alpha, the dot product of
-// the pixel's upstream gradient with the entry's features, and the pixel's
-// previously blended entry: a per-pixel list in blend order, kept in a
-// workspace array indexed by (entry, lane).  Sweep 2 walks every pixel's list
-// from its last blend back (the reverse mode of Eq. 2) and leaves
-// (dL/dalpha, T alpha) in place.  Sweep 3 goes over the chunks again in tile
-// order and chains every pair to the record's parameters, reduced over the
-// tile into the per-entry gradient.  The backward keeps the dense per-entry
-// evaluation (every wave owns interleaved entries for all 64 pixels).
+// the window front to back and writes every blend, in the order the blends
+// happen, to the tile's part of a blend buffer (a per-pixel list through
+// each record's link to the pixel's previous blend), and marks the pixel in
+// the entry's blend mask; the masks then give each entry's pairs their
+// places, entry by entry in tile order and pixel by pixel inside an entry.
+// Sweep 2 walks every pixel's list from its last blend back (the reverse mode
+// of Eq. 2) and writes each pair, chained through Eq. 1, to its place; the
+// flat pair-gradient kernel of the multi-wave path then sums each entry over
+// the tile.  The forward counts each tile's blends so that the backward
+// knows where its records and pairs go.
 #include "tile8.h"
 
 namespace ts {
@@ -90,25 +90,10 @@ __device__ __forceinline__ int win_pop(Window& w, int* idx) {
   return m;
 }
 
-// Phase A of a chunk: every wave evaluates its interleaved entries for its
-// lane's pixel; alpha (-1: no hit or pixel finished) and entry key to LDS.
-template <int NWV>
-__device__ __forceinline__ void eval_chunk(const ViewRec* recs, int n, const Tile8& c, float qx, float qy, float s,
-                                           bool mydone, float (*alds)[64], float (*zlds)[64]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int e = wave; e < n; e += NWV) {
-    float a = -1.0f, z = 0.0f;
-    const ViewRec& R = recs[e];
-    if (!mydone && has_pixel(R, c.i, c.j)) {
-      PixEval h;
-      if (pixel_eval(R, qx, qy, s, h)) {
-        a = h.alpha;
-        z = h.zin_inv;
-      }
-    }
-    alds[e][lane] = a;
-    zlds[e][lane] = z;
-  }
+// A blend mask, set by atomics (done in L2): read from L2 as well, past any
+// copy of its line in this CU's L1 (one brought in by a neighbouring slot).
+__device__ __forceinline__ unsigned long long mask_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per chunk: the entries' blended features as a conflict-free table
@@ -155,6 +140,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int last = -1;
   bool done = !c.inside;
+  uint32_t nblend = 0;    // this pixel's blends
+  uint32_t walked = start;  // end of the chunks walked
   Window win;
   win_init(win);
 
@@ -178,6 +165,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
     Tb = T;
     T = Tn;
     last = idx;
+    ++nblend;
     if (T == 0.0f) done = true;
   };
 
@@ -197,6 +185,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
     __syncthreads();
     if (done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHW, end - base);
+    walked = base + (uint32_t)n;
     rp.store(recs, n);
     if (end - base > (uint32_t)CHW) rp.fetch_rec(vrec);
     if (end - base > 2u * CHW) rp.fetch_idx(srec, base + 2 * CHW, (int)min((uint32_t)CHW, end - base - 2 * CHW));
@@ -246,6 +235,23 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
         blend(m, idx);
       }
     }
+    // the tile's blends and walked length: where the backward puts its
+    // records and pairs, and its dispatch order (a tile with no blend has
+    // nothing to walk back)
+    uint32_t nb = nblend;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nb += (uint32_t)__shfl_xor((int)nb, o, 64);
+    if (lane == 0) {
+      const uint32_t pend = nb > 0u ? walked : start;
+      at<uint32_t>(ws, L.o_tile_pend)[blockIdx.x] = pend;
+      at<uint32_t>(ws, L.o_slot_pairs)[blockIdx.x] = nb;
+      if (pend > start) {
+        uint32_t* bh = at<uint32_t>(ws, L.o_bwd_hist);
+        const int b = len_bucket(pend - start);
+        atomicAdd(bh + b, 1u);
+        atomicAdd(bh + 2 * TILE_BUCKETS + b, nb);
+      }
+    }
     if (c.inside) {
       const size_t plane = (size_t)V.W * V.H;
       const size_t px = (size_t)c.j * V.W + c.i;
@@ -267,57 +273,100 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   }
 }
 
-// A 5-waves-per-SIMD target fits the backward in 96 VGPRs without spills:
-// one more resident workgroup per CU.
+// Backward, with NWV waves per 8x8 tile, dispatched longest walk first (the
+// tiles with no blend leave at once).
+// Sweep 1 replays the window front to back exactly as the forward runs it
+// (packed evaluation of the live (entry, pixel) pairs, then each pixel's
+// candidates through its window, in wave 0) and writes every blend, in the
+// order the blends happen, to the tile's part of the blend buffer: T before
+// the blend, raw alpha, the upstream gradient dotted with the entry's
+// features, exp(s f_next), the pixel's previous blend (a per-pixel list),
+// faces and pixel, record and gradient slot; and sets the pixel's bit in the
+// entry's blend mask.  Then the tile's walked entries, in tile order, get the
+// places of their pairs: the exclusive sum of their masks' pixel counts.
+// Sweep 2 (wave 0) walks every pixel's list from its last blend back (the
+// reverse mode of Eq. 2), chains dL/dalpha through Eq. 1 and writes the pair
+// to its place, in the pair format of the multi-wave backward: an entry's
+// pairs consecutive in pixel order, so the flat pair-gradient kernel sums
+// each entry over the tile in a fixed order.
 template <int NWV>
-__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_composite_bwd_win(void* ws, Layout L, float alpha_min,
+__global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout L, float alpha_min,
                                                                 float alpha_clamp, float t_min, int nw) {
   constexpr int NT = 64 * NWV;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
-  float* tgrad = at<float>(ws, L.o_tgrad);
-  uint8_t* eflag = at<uint8_t>(ws, L.o_eflag);
-  // per (entry, lane): {T before the blend, raw alpha, g . features, previous
-  // blended entry}; sweep 2 turns the first two into {dL/dalpha, T alpha}
-  float4* pairs = at<float4>(ws, L.o_wpair);
+  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
+  uint4* blends = at<uint4>(ws, L.o_wblend);
+  unsigned long long* emask = at<unsigned long long>(ws, L.o_wmask);
+  uint32_t* ebase = at<uint32_t>(ws, L.o_wbase);
+  uint4* pairs = at<uint4>(ws, L.o_pairs);
+  const uint64_t cap = (uint64_t)L.entry_cap;
   __shared__ ViewRec recs[CHW];
-  __shared__ float alds[CHW][64];
-  __shared__ float zlds[CHW][64];
-  __shared__ float pay[WSLOTS][2][64];  // per slot: raw alpha, g . features
-  __shared__ float gacc[CHW][TGRAD_STRIDE];
+  __shared__ float alds[CHW][64];       // raw alpha
+  __shared__ float zlds[CHW][64];       // window key: 1 / entry depth
+  __shared__ float e2lds[CHW][64];      // exp(s f_next)
+  __shared__ uint8_t sel[CHW][64];      // entry face | exit face << 2
+  __shared__ float feat[7][CHW];        // per entry: c[3], zt, n[3]
+  __shared__ uint32_t erec[CHW], eslot[CHW];   // per entry: record, gradient slot
+  __shared__ uint64_t pmask[CHW];
+  __shared__ uint32_t poff[CHW + 1];
+  __shared__ uint32_t hm[64];           // per pixel: the chunk's candidates (bit e)
+  __shared__ uint32_t pay[WSLOTS][6][64];  // per slot: raw alpha, g . features, e2, faces, record, slot
+  __shared__ uint32_t wsum[NWV];
   __shared__ unsigned long long done_mask;
 
-  const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
+  const TileSlot* bslots = at<const TileSlot>(ws, L.o_bwd_order);
+  if (blockIdx.x >= at<const DevHeader>(ws, L.o_hdr)->bwd_work) return;
+  const uint32_t pend = at<const uint32_t>(ws, L.o_bwd_pend)[blockIdx.x];
+  if (pend == bslots[blockIdx.x].start) return;
+  const Tile8 c = tile8(vw, bslots);
   const DevView& V = vw[c.view];
   const float s = V.s;
-  const uint32_t start = c.start, end = c.end;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
+  const uint32_t start = c.start, end = pend;   // the forward walked [start, pend)
+  const unsigned lane = threadIdx.x & 63u;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t pair0 = at<const uint32_t>(ws, L.o_bwd_base)[blockIdx.x];   // the tile's first blend / pair
+  const uint32_t tile_xy = (uint32_t)c.tx | ((uint32_t)c.ty << 16);
   const size_t plane = (size_t)V.W * V.H;
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
   float gr[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
 
-  // ---- sweep 1: the window front to back, recording every blend
+  // ---- sweep 1 (window and blend records in wave 0)
   float T = 1.0f;
-  int prev = -1;  // this pixel's last blended entry
+  int prev = -1;          // this pixel's last blend (index into the blend buffer)
+  uint32_t run = pair0;   // next blend's place (wave-uniform)
   bool done = !c.inside;
   Window win;
   win_init(win);
-  auto record = [&](int m, int idx) {
-    const float araw = pay[m][0][lane], sdot = pay[m][1][lane];
-    const float a = fminf(araw, alpha_clamp);
-    const float Tn = T * (1.0f - a);
-    if (Tn < t_min) {
-      done = true;
-      return;
+  // one step of every lane that pops slot m (pop set): blend or stop; the
+  // blends of the step take consecutive places in lane order
+  auto step = [&](bool pop, int m) {
+    bool bl = false;
+    float a = 0.0f, Tn = 0.0f;
+    if (pop) {
+      a = fminf(__uint_as_float(pay[m][0][lane]), alpha_clamp);
+      Tn = T * (1.0f - a);
+      if (Tn < t_min) done = true;
+      else bl = true;
     }
-    pairs[(size_t)idx * 64 + lane] = make_float4(T, araw, sdot, __int_as_float(prev));
-    prev = idx;
-    T = Tn;
-    if (T == 0.0f) done = true;
+    const uint64_t bm = __ballot(bl);
+    if (bl) {
+      const uint32_t k = run + (uint32_t)__popcll(bm & lt);
+      const uint32_t d = pay[m][5][lane];
+      if ((uint64_t)k < cap) {
+        blends[2 * (size_t)k] = make_uint4(__float_as_uint(T), pay[m][0][lane], pay[m][1][lane], pay[m][2][lane]);
+        blends[2 * (size_t)k + 1] = make_uint4((uint32_t)prev, pay[m][3][lane] | (lane << 8), pay[m][4][lane], d);
+      }
+      if ((uint64_t)d < cap) atomicOr(&emask[d], 1ull << lane);
+      prev = (uint64_t)k < cap ? (int)k : -1;   // (past the capacity: an overflowed forward)
+      T = Tn;
+      if (T == 0.0f) done = true;
+    }
+    run += (uint32_t)__popcll(bm);
   };
 
   if (threadIdx.x == 0) done_mask = 0ull;
@@ -326,96 +375,151 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))
     const unsigned long long m = __ballot(done);
     if (lane == 0) done_mask = m;
   }
-  uint32_t pend = start;  // end of the walked part of the list
+  RecPipe<CHW, NT, true> rp;
+  rp.fetch_idx(srec, start, (int)min((uint32_t)CHW, end - start));
+  rp.fetch_rec(vrec, rbox);
+  if (end - start > (uint32_t)CHW) rp.fetch_idx(srec, start + CHW, (int)min((uint32_t)CHW, end - start - CHW));
   for (uint32_t base = start; base < end; base += CHW) {
     __syncthreads();
     if (done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHW, end - base);
-    pend = base + (uint32_t)n;
-    load_recs(recs, vrec, srec, base, n, NT);
+    rp.store(recs, n);
+    if (end - base > (uint32_t)CHW) rp.fetch_rec(vrec, rbox);
+    if (end - base > 2u * CHW) rp.fetch_idx(srec, base + 2 * CHW, (int)min((uint32_t)CHW, end - base - 2 * CHW));
     __syncthreads();
-    eval_chunk<NWV>(recs, n, c, qx, qy, s, (done_mask >> lane) & 1ull, alds, zlds);
-    // every walked pair starts as "not blended"
-    for (int e = wave; e < n; e += NWV) pairs[(size_t)(base + e) * 64 + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    load_chunk_tables(recs, n, feat, hm, NT);
+    if (threadIdx.x < (unsigned)n) {
+      // the entry's record and gradient slot; its blend mask starts empty
+      const ViewRec& R = recs[threadIdx.x];
+      int i0, i1, j0, j1;
+      unpack_rect(R, i0, i1, j0, j1);
+      const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
+      const uint32_t d = R.entry0 + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
+      erec[threadIdx.x] = srec[base + threadIdx.x];
+      eslot[threadIdx.x] = d;
+      if ((uint64_t)d < cap) emask[d] = 0ull;
+    }
+    if (wave == 0) chunk_pairs<CHW>(recs, n, c, ~done_mask, pmask, poff);
+    __syncthreads();
+    for_each_pair<CHW>(n, pmask, poff, NT, [&](int e, int pix) {
+      const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
+      PixEval h;
+      if (pixel_eval(recs[e], px_, py_, s, h) && h.alpha >= alpha_min) {
+        alds[e][pix] = h.alpha;
+        zlds[e][pix] = h.zin_inv;
+        e2lds[e][pix] = h.e2;
+        sel[e][pix] = (uint8_t)(h.fe | (h.fx << 2));
+        atomicOr(&hm[pix], 1u << e);
+      }
+    });
     __syncthreads();
     if (wave == 0) {
-      for (int e = 0; e < n; ++e) {
-        const float a = alds[e][lane];
-        if (done || a < 0.0f || a < alpha_min) continue;
-        const int slot = win_insert(win, zlds[e][lane], (int)(base + e));
-        const ViewRec& R = recs[e];
-        const float sdot = gr[0] * R.c[0] + gr[1] * R.c[1] + gr[2] * R.c[2] + gr[3] + gr[4] * R.zt +
-                           gr[5] * R.n[0] + gr[6] * R.n[1] + gr[7] * R.n[2];
-        pay[slot][0][lane] = a;
-        pay[slot][1][lane] = sdot;
-        if (win.cnt > nw) {
-          int idx;
-          const int m = win_pop(win, &idx);
-          record(m, idx);
+      // each pixel's candidates in arrival order
+      uint32_t cand = done ? 0u : hm[lane];
+      while (__ballot(cand != 0u) != 0ull) {
+        bool pop = false;
+        int m = 0;
+        if (cand != 0u) {
+          const int e = __ffs(cand) - 1;
+          cand &= cand - 1u;
+          const int slot = win_insert(win, zlds[e][lane], (int)(base + e));
+          const float sdot = gr[0] * feat[0][e] + gr[1] * feat[1][e] + gr[2] * feat[2][e] + gr[3] +
+                             gr[4] * feat[3][e] + gr[5] * feat[4][e] + gr[6] * feat[5][e] + gr[7] * feat[6][e];
+          pay[slot][0][lane] = __float_as_uint(alds[e][lane]);
+          pay[slot][1][lane] = __float_as_uint(sdot);
+          pay[slot][2][lane] = __float_as_uint(e2lds[e][lane]);
+          pay[slot][3][lane] = sel[e][lane];
+          pay[slot][4][lane] = erec[e];
+          pay[slot][5][lane] = eslot[e];
+          if (win.cnt > nw) {
+            int idx;
+            m = win_pop(win, &idx);
+            pop = true;
+          }
         }
+        step(pop, m);
+        if (done) cand = 0u;
       }
-      const unsigned long long m = __ballot(done);
-      if (lane == 0) done_mask = m;
+      const unsigned long long dm = __ballot(done);
+      if (lane == 0) done_mask = dm;
     }
   }
   if (wave == 0) {
+    // end of the list: the rest of the window leaves nearest first
     while (__ballot(!done && win.cnt > 0) != 0ull) {
+      bool pop = false;
+      int m = 0;
       if (!done && win.cnt > 0) {
         int idx;
-        const int m = win_pop(win, &idx);
-        record(m, idx);
+        m = win_pop(win, &idx);
+        pop = true;
       }
+      step(pop, m);
     }
-    // ---- sweep 2: each pixel's blends from the last one back; Rbehind is
-    // the upstream gradient dotted with what lies behind, per unit of T
+  }
+  __syncthreads();
+
+  // ---- the places of the pairs: per walked entry, in tile order, the
+  // exclusive sum of its blend counts (the masks are complete)
+  uint32_t carry = pair0;
+  for (uint32_t b0 = start; b0 < end; b0 += NT) {
+    const uint32_t idx = b0 + threadIdx.x;
+    uint32_t d = 0u, cnt = 0u;
+    if (idx < end) {
+      const uint4 bx = rbox[srec[idx]];   // pixel rectangle, view, first entry
+      const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu),
+                j1 = (int)(bx.y >> 16);
+      const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
+      d = bx.w + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
+      (void)j1;
+      cnt = (uint64_t)d < cap ? (uint32_t)__popcll(mask_load(emask + d)) : 0u;
+    }
+    uint32_t x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      x += lane >= (unsigned)o ? y : 0u;
+    }
+    if (lane == 63u) wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = carry;
+    for (int q = 0; q < wave; ++q) before += wsum[q];
+    if (cnt > 0u && (uint64_t)d < cap) ebase[d] = before + x - cnt;
+    for (int q = 0; q < NWV; ++q) carry += wsum[q];
+    __syncthreads();
+  }
+
+  // ---- sweep 2: each pixel's blends from the last one back; Rbehind is the
+  // upstream gradient dotted with what lies behind, per unit of T
+  if (wave == 0) {
     float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
     int k = prev;
     while (__ballot(k >= 0) != 0ull) {
       if (k >= 0) {
-        float4* p = &pairs[(size_t)k * 64 + lane];
-        const float4 v = *p;
-        const float Tk = v.x, araw = v.y, sdot = v.z;
+        const uint4 b0 = blends[2 * (size_t)k], b1 = blends[2 * (size_t)k + 1];
+        const float Tk = __uint_as_float(b0.x), araw = __uint_as_float(b0.y), sdot = __uint_as_float(b0.z);
+        const float e2 = __uint_as_float(b0.w);
         const float a = fminf(araw, alpha_clamp);
         float da = Tk * (sdot - Rbehind);
         Rbehind = a * sdot + (1.0f - a) * Rbehind;
         if (araw > alpha_clamp) da = 0.0f;
-        *reinterpret_cast<float2*>(p) = make_float2(da, Tk * a);
-        k = __float_as_int(v.w);
-      }
-    }
-  }
-  // ---- sweep 3: per-entry gradients in tile order, reduced over the tile
-  for (uint32_t base = start; base < pend; base += CHW) {
-    const int n = (int)min((uint32_t)CHW, pend - base);
-    __syncthreads();
-    load_recs(recs, vrec, srec, base, n, NT, at<const uint4>(ws, L.o_rbox));
-    __syncthreads();
-    for (int e = wave; e < n; e += NWV) {
-      const float2 dw = *reinterpret_cast<const float2*>(&pairs[(size_t)(base + e) * 64 + lane]);
-      const float da = dw.x, w = dw.y;
-      const bool contrib = (da != 0.0f) || (w != 0.0f);
-      if (__ballot(contrib) == 0ull) {
-        if (lane < (unsigned)TGRAD_STRIDE) gacc[e][lane] = 0.0f;
-        continue;
-      }
-      // branch-free: a lane that did not blend this entry chains zero
-      // weights (zero gradient)
-      float g[32];
-      {
-        const ViewRec& R = recs[e];
-        PixEval h;
-        pixel_eval(R, qx, qy, s, h);
         float dd, dfn;
-        eq1_chain(da, h.alpha, h.e2, s, dd, dfn);
-        pair_grad_all(R, qx, qy, gr, dd, dfn, w, h.fe | (h.fx << 2), g);
+        eq1_chain(da, araw, e2, s, dd, dfn);
+        const uint32_t d = b1.w;
+        if ((uint64_t)d < cap) {
+          const unsigned long long mk = mask_load(emask + d);
+          const unsigned long long below = mk & lt;
+          const uint32_t pos = ebase[d] + (uint32_t)__popcll(below);
+          const uint32_t hw = below == 0ull ? PAIR_HEAD | ((uint32_t)__popcll(mk) << 11) : 0u;
+          if ((uint64_t)pos < cap) {
+            pairs[2 * (size_t)pos] = make_uint4(__float_as_uint(dd), __float_as_uint(dfn), __float_as_uint(Tk * a),
+                                                lane | ((b1.y & 15u) << 6) | hw);
+            pairs[2 * (size_t)pos + 1] = make_uint4(b1.z, (uint32_t)c.view, tile_xy, d);
+          }
+        }
+        k = (int)b1.x;
       }
-      const float tot = wave_transpose_sum32(g);
-      const unsigned q = lane >> 1;
-      if ((lane & 1u) == 0u && q < (unsigned)TGRAD_STRIDE) gacc[e][q] = tot;
     }
-    __syncthreads();
-    store_entry_grads(recs, gacc, n, c, tgrad, eflag, NT, (uint64_t)L.entry_cap,
-                      record_grads(L) ? srec + base : nullptr);
   }
 }
 
@@ -445,7 +549,8 @@ hipError_t launch_composite_win(void* ws, const Layout& L, const render_params& 
 
 hipError_t launch_composite_backward_win(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
-  if (p.window < 1 || p.window > RENDER_WINDOW_MAX || p.tile_w != 8 || p.tile_h != 8 || L.o_wpair == 0)
+  if (p.window < 1 || p.window > RENDER_WINDOW_MAX || p.tile_w != 8 || p.tile_h != 8 || L.o_wblend == 0 ||
+      L.o_pairs == 0)
     return hipErrorInvalidValue;
   switch (p.waves) {
     case 1: launch_bwd_win<1>(ws, L, p, st); break;

@@ -101,6 +101,14 @@ struct ViewRec {
 static_assert(sizeof(ViewRec) == 128, "view record is 128 bytes");
 
 constexpr int TGRAD_STRIDE = 24;  // floats per per-entry gradient
+// A blended (entry, pixel) pair of the 8x8 multi-wave and resort-window
+// backwards, 32 bytes: dL/df_prev, dL/df_next, the blend weight T alpha and a
+// word (pixel | entry and exit faces << 6 | PAIR_HEAD on the first pair of
+// its segment, which also holds the segment's pair count << 11); then the
+// entry's record, view, tile (x | y << 16) and gradient slot.  A segment is a
+// (tile, entry) with blended pixels: its pairs are consecutive, in pixel
+// order, at most 64.
+constexpr uint32_t PAIR_HEAD = 1u << 10;
 // per-entry gradient layout (screen space of one record)
 enum { G_PX = 0, G_PY = 4, G_IZ = 8, G_F = 12, G_C = 16, G_ZT = 19, G_N = 20 };
 
@@ -136,7 +144,12 @@ struct Layout {
   // pairs; per backward slot the base of its pairs; 32 bytes per blended
   // (entry, pixel) pair
   size_t o_slot_pairs, o_bwd_base, o_pairs;
-  size_t o_wpair;        // resort-window backward: per (entry, lane) 16 B; 0 when the window is off
+  // resort-window backward (0 when the window is off): per blend, in each
+  // tile's blend order, 32 B (T before the blend, raw alpha, upstream
+  // gradient . features, exp(s f_next); the pixel's previous blend, faces
+  // and pixel, record, gradient slot); per entry slot the pixels of its tile
+  // that blended it (64-bit mask) and the place of its first pair
+  size_t o_wblend, o_wmask, o_wbase;
   // deterministic backward (0 otherwise): per kept-tet corner a vertex key and
   // corner id (double-buffered for the sort) and its 7 gradient terms (8 floats)
   size_t o_vkey_a, o_vkey_b, o_vval_a, o_vval_b, o_vterm;

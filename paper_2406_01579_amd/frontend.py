@@ -8,7 +8,6 @@ and wraps the forward/backward pair in a torch.autograd.Function.
 from __future__ import annotations
 
 import ctypes as C
-import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -194,13 +193,6 @@ class Renderer:
         st = torch.cuda.current_stream(self.device).cuda_stream if stream is None else stream
         sig = self._signature(scenes, cams, view_scene)
         kept_cap, entry_cap = self._caps.get(sig, (0, 0)) if caps is None else (int(caps[0]), int(caps[1]))
-        if entry_cap == 0 and self.params.window > 0:
-            # the resort window's backward keeps 1 KiB per entry: size it from
-            # a probe without the window (the tiling does not depend on it)
-            probe = Renderer(dataclasses.replace(self.params, window=0), device=self.device, check="sync")
-            probe.forward(scenes, cams, view_scene, stream)
-            kept_cap, entry_cap = probe._caps[sig]
-            del probe
         if entry_cap == 0:
             # first sight of this shape: generous bound, refined after the call
             rec = sum(int(scenes[int(view_scene[v])].tets.shape[0]) for v in range(nv))

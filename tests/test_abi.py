@@ -236,17 +236,15 @@ def test_regularizer_entry_points_validate_on_the_host(L):
 
 def test_resort_window_arguments(L):
     """The resort window is 0..RENDER_WINDOW_MAX on 8x8 tiles; with it on, the
-    workspace holds 16 bytes per (entry, tile pixel) more."""
+    workspace holds 44 bytes per entry more (its backward's blend records,
+    blend masks and pair places)."""
     w = synth.tiny()
     scenes, views, p = _args(L, w, (8, 8))
     rc, base = _size(L, scenes, views, p, ent=10000)
     assert rc == 0
     p.window = 5
     rc, with_win = _size(L, scenes, views, p, ent=10000)
-    # (the window path keeps no pair buffers: 32 bytes per entry and 8 per
-    # tile of the plain 8x8 path, 256-byte aligned)
-    tiles = 8 * 8
-    assert rc == 0 and with_win >= base - 32 * 10000 - 8 * tiles - 3 * 256 + 16 * 64 * 10000
+    assert rc == 0 and 44 * 10000 <= with_win - base <= 44 * 10000 + 3 * 256
     for bad in (-1, L.RENDER_WINDOW_MAX + 1):
         p.window = bad
         assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL
