@@ -660,9 +660,10 @@ hipError_t launch_count_scan(void* ws, const Layout& L, const render_params& p, 
 // ---------------------------------------------------------------------------
 // a4: duplicate each record once per overlapped tile into the tile's list:
 // per SCAN_TILE records, each record's first entry into its box, then the
-// block's entries placed through the per-tile cursors (key = global tile id,
-// value = record); places past the entry capacity are dropped (the overflow
-// is flagged)
+// block's entries (records) placed through the per-tile cursors; places past
+// the entry capacity are dropped (the overflow is flagged).  The lists' tile
+// keys are written by the depth sort, contiguously per tile, not here, where
+// every 4-byte place is a scattered write.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, int th_log2) {
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
@@ -670,7 +671,6 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   uint4* rbox = at<uint4>(ws, L.o_rbox);
   uint32_t* cursor = at<uint32_t>(ws, L.o_tile_cnt);
-  uint32_t* key2 = at<uint32_t>(ws, sorted_tile_keys(L));
   uint32_t* val2 = at<uint32_t>(ws, sorted_entry_records(L));
   constexpr int PER = SCAN_TILE / 256;
   __shared__ uint32_t loff[SCAN_TILE];
@@ -700,10 +700,7 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
       uint32_t gb = cnt ? atomicAdd(&cursor[tile], cnt) : 0u;
       gb = (uint32_t)__shfl((int)gb, lead, 64);
       const uint64_t pos = (uint64_t)gb + off;
-      if (active && pos < cap) {
-        key2[pos] = tile;
-        val2[pos] = r;
-      }
+      if (active && pos < cap) val2[pos] = r;
     }
     __syncthreads();
   }
@@ -910,10 +907,14 @@ __global__ __launch_bounds__(256) void k_tile_depth_sort(void* ws, Layout L) {
   if (blockIdx.x >= (uint32_t)L.total_tiles - n_empty) return;
   const TileSlot sl = at<const TileSlot>(ws, L.o_tile_order)[blockIdx.x];
   const uint32_t s0 = sl.start, n = sl.end - sl.start;
-  if (n < 2) return;
-  const uint32_t* zkey = at<const uint32_t>(ws, L.o_key1a);   // depth bits per record
   uint32_t* rk = at<uint32_t>(ws, sorted_tile_keys(L));       // result pair: tile keys, records
   uint32_t* rv = at<uint32_t>(ws, sorted_entry_records(L));
+  // the list's tile keys (a list past DS_CAP uses them as merge scratch first
+  // and writes them at the end)
+  if (n <= (uint32_t)DS_CAP)
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) rk[s0 + i] = sl.tile;
+  if (n < 2) return;
+  const uint32_t* zkey = at<const uint32_t>(ws, L.o_key1a);   // depth bits per record
   const bool res_a = sorted_entry_records(L) == L.o_val2a;    // scratch pair: the other buffers
   uint32_t* xk = at<uint32_t>(ws, res_a ? L.o_key2b : L.o_key2a);
   uint32_t* xv = at<uint32_t>(ws, res_a ? L.o_val2b : L.o_val2a);
