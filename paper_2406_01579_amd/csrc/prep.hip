@@ -804,10 +804,9 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
       uint64_t np = 0;
       for (int b = 0; b < TILE_BUCKETS; ++b) np += hist[2 * TILE_BUCKETS + b];
       hdr->pairs_total = (uint32_t)min(np, (uint64_t)0xffffffffu);
-      if (np > (uint64_t)L.entry_cap) {   // the forward's outputs stand; its backward would not
-        hdr->overflow |= 4u;
-        if (np > hdr->entries_needed) hdr->entries_needed = np;
-      }
+      // the capacity a backward needs covers the pairs too
+      if (np > hdr->entries_needed) hdr->entries_needed = np;
+      if (np > (uint64_t)L.entry_cap) hdr->overflow |= 4u;   // the forward's outputs stand; its backward would not
     }
   }
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;

@@ -310,8 +310,10 @@ class Server:
                 sids, cams, vs, caps = L.args[i]
                 need = (int(s.kept) + 256, int(int(s.entries_needed) * 1.05) + 1024)
                 factor = max(1.0, need[1] / max(1, caps[1])) * 1.25
-                for v in range(len(cams)):
-                    self.reg.grow(sids[int(vs[v])], int(cams[v][0]), int(cams[v][1]), factor)
+                # once per (scene, image size) of the launch, not once per view
+                for sid, W, H in sorted({(sids[int(vs[v])], int(cams[v][0]), int(cams[v][1]))
+                                         for v in range(len(cams))}):
+                    self.reg.grow(sid, W, H, factor)
                 old_bytes = L.plans[i].workspace.numel()
                 with torch.cuda.stream(st):
                     plan = self.renderer.forward([self.reg.scenes[x] for x in sids], cams, vs, caps=need)

@@ -374,6 +374,28 @@ def test_pair_overflow_keeps_the_forward_and_replans_the_backward():
         assert np.array_equal(a.cpu().numpy(), b)
 
 
+def test_capacities_sized_from_a_forward_cover_its_pairs():
+    """The status's entries_needed covers the blended pairs when they are more
+    than the entries, so capacities sized from a first forward leave the
+    backward room for its pairs: later lazy-checked steps never overflow."""
+    import torch
+    from paper_2406_01579_amd import Renderer, SceneT
+    w = synth.tiny(s=20.0)
+    sc = w.scenes[0]
+    st = SceneT.from_numpy(sc)
+    r = Renderer(_params("exact", (8, 8)), check="lazy")
+    plan = r.forward([st], w.cams)        # first sight of the shape: sized synchronously
+    s = plan.status
+    assert s.overflow == 0 and s.entries_needed > s.entries   # more pairs than entries here
+    dout = torch.zeros(8, 64, 64, device="cuda")
+    r.backward(plan, [dout])
+    for _ in range(3):
+        plan = r.forward([st], w.cams)
+        r.backward(plan, [dout])
+    torch.cuda.synchronize()
+    assert r.read_status(plan).overflow == 0
+
+
 # ---------------------------------------------------------------------------
 # training-shaped workload at full size (64^3 grid, 4 views 512^2, s = 320):
 # tiling in full, sampled pixels, gradients of a sparse upstream gradient
