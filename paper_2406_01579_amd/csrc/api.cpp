@@ -259,6 +259,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
     L.o_slot_pairs = take(4 * (size_t)tiles);
     L.o_bwd_base = take(4 * (size_t)tiles);
     L.o_pairs = take(32 * (size_t)entry_cap);   // at most entry_capacity blended pairs
+    if (p->window == 0) L.o_bmask = take(8 * (size_t)entry_cap);
   }
   if (det) {
     const size_t nc = 4 * (size_t)kept_cap;

@@ -32,7 +32,8 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
                                               uint64_t* pmask, uint32_t* poff, uint64_t* hm, float (*feat)[CHN],
                                               unsigned long long* done_mask,
                                               float& T, float& Tb, float& O, float (&acc)[7], int& last,
-                                              bool want_acc, uint32_t* nblend = nullptr) {
+                                              bool want_acc, uint32_t* nblend = nullptr,
+                                              unsigned long long* bmask = nullptr) {
   constexpr int NT = 64 * NWV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool done = !c.inside;
@@ -107,6 +108,12 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
         }
       }
       if (nblend) *nblend += (uint32_t)__popcll(blended);   // the chunk's blended pairs (per lane)
+      if (bmask) {
+        // per entry of the chunk, the pixels that blended it (what the
+        // backward's pairs are): lane e writes entry e's mask
+        const uint64_t mine = wave_transpose64(blended);
+        if (lane < n) bmask[base + lane] = mine;
+      }
       const unsigned long long m = __ballot(done);
       if (lane == 0) *done_mask = m;
     }
@@ -192,7 +199,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   uint32_t nblend = 0;
   const bool count = L.o_pairs != 0;
   forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff, hm,
-                          feat, &done_mask, T, Tb, O, acc, last, true, count ? &nblend : nullptr);
+                          feat, &done_mask, T, Tb, O, acc, last, true, count ? &nblend : nullptr,
+                          L.o_bmask ? at<unsigned long long>(ws, L.o_bmask) : nullptr);
   if ((threadIdx.x >> 6) == 0) {
     // end of the tile's blended prefix: where the backward starts its walk
     int wmax = last;
@@ -251,8 +259,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
-  const int32_t* last_in = at<const int32_t>(ws, L.o_last);
   const float* tlast_in = at<const float>(ws, L.o_tlast);
+  const unsigned long long* bmask = at<const unsigned long long>(ws, L.o_bmask);
   uint4* pairs = at<uint4>(ws, L.o_pairs);
   __shared__ ViewRec recs[CHB];
   __shared__ uint4 eseg[CHB];        // per entry with a blended pixel: record, view, tile, gradient slot
@@ -281,7 +289,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const int wave = threadIdx.x >> 6;
   const uint64_t cap = (uint64_t)L.entry_cap;
 
-  // per-pixel state (wave 0): last blended entry, T before it, upstream gradient;
+  // per-pixel state (wave 0): T before the last blend, upstream gradient;
   // pend: end of the tile's blended prefix (from the forward, or the replay)
   int last = -1;
   float Tb = 1.0f;
@@ -301,11 +309,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     pend = smax >= (int)start ? (uint32_t)smax + 1u : start;
   } else {
     pend = at<const uint32_t>(ws, L.o_bwd_pend)[blockIdx.x];
-    if (wave == 0 && c.inside) {
-      const size_t gi = (size_t)V.pix_base + px;
-      last = last_in[gi];
-      Tb = tlast_in[gi];
-    }
+    if (wave == 0 && c.inside) Tb = tlast_in[(size_t)V.pix_base + px];
   }
   float gr[8];
   float Rbehind = 0.0f;
@@ -324,10 +328,14 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const int64_t cb0 = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CHB) * CHB;
   const uint4* rbox = at<const uint4>(ws, L.o_rbox);
   RecPipe<CHB, NT, true> rp;
+  // wave 0, lane e: the blend mask of the current chunk's entry e, and of the
+  // next chunk's (its load in flight across the current chunk)
+  uint64_t bm_cur = 0ull, bm_next = 0ull;
   if (pend > start) {
     rp.fetch_idx(srec, (uint32_t)cb0, (int)(pend - (uint32_t)cb0));
     rp.fetch_rec(vrec, rbox);
     if (cb0 - CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb0 - CHB), CHB);
+    if (wave == 0 && lane < pend - (uint32_t)cb0 && lane < (unsigned)CHB) bm_next = bmask[(uint32_t)cb0 + lane];
   }
   for (int64_t cb = cb0; cb >= (int64_t)start && pend > start; cb -= CHB) {
     const uint32_t base = (uint32_t)cb;
@@ -336,34 +344,20 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     rp.store(recs, n);
     if (cb - CHB >= (int64_t)start) rp.fetch_rec(vrec, rbox);
     if (cb - 2 * CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb - 2 * CHB), CHB);
+    bm_cur = bm_next;
+    if (wave == 0 && cb - CHB >= (int64_t)start && lane < (unsigned)CHB) bm_next = bmask[base - CHB + lane];
     __syncthreads();
-    // phase A: coverage, faces and Eq. 1 of every (entry, pixel) the pixel's
-    // walk reached (entry at or before its last blend), packed
+    // phase A: coverage, faces and Eq. 1 of every (entry, pixel) pair the
+    // forward blended, packed
     if (threadIdx.x < 64) hmask[threadIdx.x] = 0ull;
     for (int q = threadIdx.x; q < n * 7; q += NT) {
       const int e = q / 7, k = q - e * 7;
       feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
     }
     if (wave == 0) {
-      // lane e: the pixels whose walk reached entry e (last >= base + e).  A
-      // pixel whose last blend lies past the chunk takes part in all of it;
-      // only the pixels whose last blend lies inside the chunk need a test
-      // per entry.
-      const int rel = c.inside ? last - (int)base : -1;
-      uint64_t live_e = __ballot(rel >= n - 1);
-      uint64_t part = __ballot(rel >= 0 && rel < n - 1);
-      if (__popcll(part) * 2 <= n) {
-        for (; part != 0ull; part &= part - 1ull) {
-          const int p = __ffsll((unsigned long long)part) - 1;
-          const int lp = __shfl(rel, p, 64);
-          live_e |= ((int)lane <= lp) ? (1ull << p) : 0ull;
-        }
-      } else {
-        for (int e = 0; e < n - 1; ++e) {
-          const uint64_t b = __ballot(rel >= e);
-          live_e = ((int)lane == e) ? b : live_e;
-        }
-      }
+      // lane e: the pixels that blended entry e (the forward's masks, loaded
+      // a chunk ahead)
+      const uint64_t live_e = bm_cur;
       chunk_pairs<CHB>(recs, n, c, live_e, pmask, poff);
     }
     __syncthreads();
@@ -382,19 +376,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     // candidate at or before the pixel's last blend was blended); their
     // places first, then the reverse recurrence writes each pair
     if (wave == 0) {
-      const uint32_t m0 = (uint32_t)hmask[lane];   // CHB = 32 entries
+      const uint32_t m0 = (uint32_t)hmask[lane];   // CHB <= 32 entries
       const uint64_t lt = (1ull << lane) - 1ull;
       // lane e: the pixels that blended entry e
-      uint32_t any = m0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
-      any = __builtin_amdgcn_readfirstlane(any);
-      uint64_t cmask_e = 0ull;
-      for (uint32_t t = any; t != 0u; t &= t - 1u) {
-        const int e = __ffs(t) - 1;
-        const uint64_t b = __ballot((m0 >> e) & 1u);
-        cmask_e = ((int)lane == e) ? b : cmask_e;
-      }
+      const uint64_t cmask_e = wave_transpose64((uint64_t)m0);
       pair_offsets<CHB, 1>(n, cmask_e, pmask, poff);
       // the entries with a blended pixel: what every one of their pairs carries
       if ((int)lane < n && cmask_e != 0ull) {

@@ -248,6 +248,26 @@ __device__ __forceinline__ void pair_grad_all(const ViewRec& R, float qx, float 
 }
 
 // ---------------------------------------------------------------------------
+// Transpose of the 64 x 64 bit matrix whose row r is lane r's word: bit c of
+// lane r becomes bit r of lane c.  Six butterfly steps; at step j, lanes r
+// and r ^ j exchange the j-wide column blocks that the transpose swaps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+  constexpr uint64_t M[6] = {0x00000000ffffffffull, 0x0000ffff0000ffffull, 0x00ff00ff00ff00ffull,
+                             0x0f0f0f0f0f0f0f0full, 0x3333333333333333ull, 0x5555555555555555ull};
+  const unsigned lane = __lane_id();
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int j = 32 >> s;
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, j, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), j, 64);
+    const uint64_t y = ((uint64_t)hi << 32) | lo;
+    x = (lane & (unsigned)j) ? (x & ~M[s]) | ((y & ~M[s]) >> j) : (x & M[s]) | ((y & M[s]) << j);
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------------------
 // wave-wide transposed sum of 32 per-lane values (gfx950 permlane swaps and
 // DPP): afterwards lane L holds the sum over all 64 lanes of v[L >> 1].
 // Each step halves the values per lane while pairing lanes across a 32-,

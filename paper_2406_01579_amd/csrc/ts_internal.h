@@ -142,8 +142,9 @@ struct Layout {
   size_t o_bwd_hist, o_bwd_order, o_bwd_pend;  // backward dispatch order (by walked length)
   // multi-wave 8x8 backward (0 otherwise): per forward slot its blended
   // pairs; per backward slot the base of its pairs; 32 bytes per blended
-  // (entry, pixel) pair
-  size_t o_slot_pairs, o_bwd_base, o_pairs;
+  // (entry, pixel) pair; per sorted entry the pixels of its tile that blended
+  // it (64-bit mask, written for the walked entries; per-tile order only)
+  size_t o_slot_pairs, o_bwd_base, o_pairs, o_bmask;
   // resort-window backward (0 when the window is off): per blend, in each
   // tile's blend order, 32 B (T before the blend, raw alpha, upstream
   // gradient . features, exp(s f_next); the pixel's previous blend, faces
