@@ -35,20 +35,29 @@ namespace ts {
 
 namespace {
 
-constexpr int WSLOTS = RENDER_WINDOW_MAX + 1;  // an arrival overflows a full window by one
-constexpr int CHW = 32;                        // entries per LDS chunk
+// A lane's window holds up to N_w entries, plus the arrival that overflows
+// it: WS >= N_w + 1 slots (the kernels are built for WS in {2, 4, 6, 9}, the
+// smallest that fits N_w, so the slot scans stay short).
+constexpr int CHW = 32;       // entries per LDS chunk (forward)
+// The backward's chunks are shorter: its per-(entry, pixel) arrays then fit
+// four workgroups per CU.  Its replay makes the forward's decisions with any
+// chunk length (they are per pixel and per candidate, in tile order), and it
+// walks exactly the forward's walked range.
+constexpr int CHW_BWD = 16;
 
 // One lane's window.  key = 1 / entry depth (larger is nearer), -1 for a free
 // slot (a hit's key is positive); idx = global entry index (arrival order).
+template <int WS>
 struct Window {
-  float key[WSLOTS];
-  int idx[WSLOTS];
+  float key[WS];
+  int idx[WS];
   int cnt;
 };
 
-__device__ __forceinline__ void win_init(Window& w) {
+template <int WS>
+__device__ __forceinline__ void win_init(Window<WS>& w) {
 #pragma unroll
-  for (int k = 0; k < WSLOTS; ++k) {
+  for (int k = 0; k < WS; ++k) {
     w.key[k] = -1.0f;
     w.idx[k] = 0;
   }
@@ -56,12 +65,13 @@ __device__ __forceinline__ void win_init(Window& w) {
 }
 
 // Puts (key, idx) into the lowest free slot and returns that slot.
-__device__ __forceinline__ int win_insert(Window& w, float key, int idx) {
+template <int WS>
+__device__ __forceinline__ int win_insert(Window<WS>& w, float key, int idx) {
   int slot = 0;
 #pragma unroll
-  for (int k = WSLOTS - 1; k >= 0; --k) slot = (w.key[k] < 0.0f) ? k : slot;
+  for (int k = WS - 1; k >= 0; --k) slot = (w.key[k] < 0.0f) ? k : slot;
 #pragma unroll
-  for (int k = 0; k < WSLOTS; ++k) {
+  for (int k = 0; k < WS; ++k) {
     const bool here = k == slot;
     w.key[k] = here ? key : w.key[k];
     w.idx[k] = here ? idx : w.idx[k];
@@ -72,19 +82,20 @@ __device__ __forceinline__ int win_insert(Window& w, float key, int idx) {
 
 // Takes the nearest entry out (largest key; equal keys: earliest arrival) and
 // returns its slot; *idx receives its entry index.  Needs cnt > 0.
-__device__ __forceinline__ int win_pop(Window& w, int* idx) {
+template <int WS>
+__device__ __forceinline__ int win_pop(Window<WS>& w, int* idx) {
   int m = 0;
   float bk = w.key[0];
   int bi = w.idx[0];
 #pragma unroll
-  for (int k = 1; k < WSLOTS; ++k) {
+  for (int k = 1; k < WS; ++k) {
     const bool better = w.key[k] > bk || (w.key[k] == bk && bk >= 0.0f && w.idx[k] < bi);
     m = better ? k : m;
     bk = better ? w.key[k] : bk;
     bi = better ? w.idx[k] : bi;
   }
 #pragma unroll
-  for (int k = 0; k < WSLOTS; ++k) w.key[k] = (k == m) ? -1.0f : w.key[k];
+  for (int k = 0; k < WS; ++k) w.key[k] = (k == m) ? -1.0f : w.key[k];
   --w.cnt;
   *idx = bi;
   return m;
@@ -110,7 +121,7 @@ __device__ __forceinline__ void load_chunk_tables(const ViewRec* recs, int n, fl
 
 }  // namespace
 
-template <int NWV>
+template <int NWV, int WS>
 __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, float alpha_min, float alpha_clamp,
                                                             float t_min, int nw) {
   constexpr int NT = 64 * NWV;
@@ -126,7 +137,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   __shared__ uint64_t pmask[CHW];
   __shared__ uint32_t poff[CHW + 1];
   __shared__ uint32_t hm[64];           // per pixel: the chunk's candidates (bit e)
-  __shared__ float pay[WSLOTS][8][64];  // per slot: alpha, c[3], zt, n[3]
+  __shared__ float pay[WS][8][64];      // per slot: alpha, c[3], zt, n[3]
   __shared__ unsigned long long done_mask;
 
   const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   bool done = !c.inside;
   uint32_t nblend = 0;    // this pixel's blends
   uint32_t walked = start;  // end of the chunks walked
-  Window win;
+  Window<WS> win;
   win_init(win);
 
   // blend the entry that leaves the window from slot m
@@ -289,10 +300,11 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
 // to its place, in the pair format of the multi-wave backward: an entry's
 // pairs consecutive in pixel order, so the flat pair-gradient kernel sums
 // each entry over the tile in a fixed order.
-template <int NWV>
+template <int NWV, int WS>
 __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout L, float alpha_min,
                                                                 float alpha_clamp, float t_min, int nw) {
   constexpr int NT = 64 * NWV;
+  constexpr int CHB = CHW_BWD;
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
@@ -302,17 +314,17 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   uint32_t* ebase = at<uint32_t>(ws, L.o_wbase);
   uint4* pairs = at<uint4>(ws, L.o_pairs);
   const uint64_t cap = (uint64_t)L.entry_cap;
-  __shared__ ViewRec recs[CHW];
-  __shared__ float alds[CHW][64];       // raw alpha
-  __shared__ float zlds[CHW][64];       // window key: 1 / entry depth
-  __shared__ float e2lds[CHW][64];      // exp(s f_next)
-  __shared__ uint8_t sel[CHW][64];      // entry face | exit face << 2
-  __shared__ float feat[7][CHW];        // per entry: c[3], zt, n[3]
-  __shared__ uint32_t erec[CHW], eslot[CHW];   // per entry: record, gradient slot
-  __shared__ uint64_t pmask[CHW];
-  __shared__ uint32_t poff[CHW + 1];
+  __shared__ ViewRec recs[CHB];
+  __shared__ float alds[CHB][64];       // raw alpha
+  __shared__ float zlds[CHB][64];       // window key: 1 / entry depth
+  __shared__ float e2lds[CHB][64];      // exp(s f_next)
+  __shared__ uint8_t sel[CHB][64];      // entry face | exit face << 2
+  __shared__ float feat[7][CHB];        // per entry: c[3], zt, n[3]
+  __shared__ uint32_t erec[CHB], eslot[CHB];   // per entry: record, gradient slot
+  __shared__ uint64_t pmask[CHB];
+  __shared__ uint32_t poff[CHB + 1];
   __shared__ uint32_t hm[64];           // per pixel: the chunk's candidates (bit e)
-  __shared__ uint32_t pay[WSLOTS][6][64];  // per slot: raw alpha, g . features, e2, faces, record, slot
+  __shared__ uint32_t pay[WS][6][64];   // per slot: raw alpha, g . features, e2, faces, record, slot
   __shared__ uint32_t wsum[NWV];
   __shared__ unsigned long long done_mask;
 
@@ -340,7 +352,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   int prev = -1;          // this pixel's last blend (index into the blend buffer)
   uint32_t run = pair0;   // next blend's place (wave-uniform)
   bool done = !c.inside;
-  Window win;
+  Window<WS> win;
   win_init(win);
   // one step of every lane that pops slot m (pop set): blend or stop; the
   // blends of the step take consecutive places in lane order
@@ -375,17 +387,17 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
     const unsigned long long m = __ballot(done);
     if (lane == 0) done_mask = m;
   }
-  RecPipe<CHW, NT, true> rp;
-  rp.fetch_idx(srec, start, (int)min((uint32_t)CHW, end - start));
+  RecPipe<CHB, NT, true> rp;
+  rp.fetch_idx(srec, start, (int)min((uint32_t)CHB, end - start));
   rp.fetch_rec(vrec, rbox);
-  if (end - start > (uint32_t)CHW) rp.fetch_idx(srec, start + CHW, (int)min((uint32_t)CHW, end - start - CHW));
-  for (uint32_t base = start; base < end; base += CHW) {
+  if (end - start > (uint32_t)CHB) rp.fetch_idx(srec, start + CHB, (int)min((uint32_t)CHB, end - start - CHB));
+  for (uint32_t base = start; base < end; base += CHB) {
     __syncthreads();
     if (done_mask == ~0ull) break;
-    const int n = (int)min((uint32_t)CHW, end - base);
+    const int n = (int)min((uint32_t)CHB, end - base);
     rp.store(recs, n);
-    if (end - base > (uint32_t)CHW) rp.fetch_rec(vrec, rbox);
-    if (end - base > 2u * CHW) rp.fetch_idx(srec, base + 2 * CHW, (int)min((uint32_t)CHW, end - base - 2 * CHW));
+    if (end - base > (uint32_t)CHB) rp.fetch_rec(vrec, rbox);
+    if (end - base > 2u * CHB) rp.fetch_idx(srec, base + 2 * CHB, (int)min((uint32_t)CHB, end - base - 2 * CHB));
     __syncthreads();
     load_chunk_tables(recs, n, feat, hm, NT);
     if (threadIdx.x < (unsigned)n) {
@@ -399,9 +411,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
       eslot[threadIdx.x] = d;
       if ((uint64_t)d < cap) emask[d] = 0ull;
     }
-    if (wave == 0) chunk_pairs<CHW>(recs, n, c, ~done_mask, pmask, poff);
+    if (wave == 0) chunk_pairs<CHB>(recs, n, c, ~done_mask, pmask, poff);
     __syncthreads();
-    for_each_pair<CHW>(n, pmask, poff, NT, [&](int e, int pix) {
+    for_each_pair<CHB>(n, pmask, poff, NT, [&](int e, int pix) {
       const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
       PixEval h;
       if (pixel_eval(recs[e], px_, py_, s, h) && h.alpha >= alpha_min) {
@@ -523,15 +535,30 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   }
 }
 
+template <int NWV, int WS>
+static void launch_fwd_win_ws(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  k_composite_win<NWV, WS><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                          p.t_min, p.window);
+}
+template <int NWV, int WS>
+static void launch_bwd_win_ws(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  k_composite_bwd_win<NWV, WS><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
+                                                                              p.t_min, p.window);
+}
+// the smallest slot count that holds N_w entries and one arrival
 template <int NWV>
 static void launch_fwd_win(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  k_composite_win<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp, p.t_min,
-                                                                      p.window);
+  if (p.window <= 1) launch_fwd_win_ws<NWV, 2>(ws, L, p, st);
+  else if (p.window <= 3) launch_fwd_win_ws<NWV, 4>(ws, L, p, st);
+  else if (p.window <= 5) launch_fwd_win_ws<NWV, 6>(ws, L, p, st);
+  else launch_fwd_win_ws<NWV, RENDER_WINDOW_MAX + 1>(ws, L, p, st);
 }
 template <int NWV>
 static void launch_bwd_win(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
-  k_composite_bwd_win<NWV><<<(unsigned)L.total_tiles, 64 * NWV, 0, st>>>(ws, L, p.alpha_min, p.alpha_clamp,
-                                                                          p.t_min, p.window);
+  if (p.window <= 1) launch_bwd_win_ws<NWV, 2>(ws, L, p, st);
+  else if (p.window <= 3) launch_bwd_win_ws<NWV, 4>(ws, L, p, st);
+  else if (p.window <= 5) launch_bwd_win_ws<NWV, 6>(ws, L, p, st);
+  else launch_bwd_win_ws<NWV, RENDER_WINDOW_MAX + 1>(ws, L, p, st);
 }
 
 hipError_t launch_composite_win(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
