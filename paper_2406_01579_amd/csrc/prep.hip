@@ -725,6 +725,9 @@ hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStr
 // (longest first), from the complete histogram; the block's tiles of bucket
 // b then take consecutive places from first[b] + an atomic cursor.
 static_assert(TILE_BUCKETS <= 256, "one thread per bucket");
+// tiles per thread of the scatter kernels: fewer blocks, so fewer of the
+// global cursor atomics, which serialise per bucket
+constexpr int SC_PER = 4;
 __device__ __forceinline__ void bucket_first(const uint32_t* hist, uint32_t* first, uint32_t* lds /*[8]*/) {
   const int t = threadIdx.x;
   const uint32_t v = t < TILE_BUCKETS ? hist[TILE_BUCKETS - 1 - t] : 0u;
@@ -743,30 +746,39 @@ __global__ __launch_bounds__(256) void k_tile_scatter(void* ws, Layout L) {
   if (threadIdx.x < TILE_BUCKETS) cnt[threadIdx.x] = 0;
   bucket_first(hist, first, lds);
   __syncthreads();
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  int b = 0;
-  uint32_t rank = 0;
-  if (t < (uint32_t)L.total_tiles) {
-    b = len_bucket(ranges[2 * t + 1] - ranges[2 * t]);
-    rank = atomicAdd(&cnt[b], 1u);
+  int b[SC_PER];
+  uint32_t rank[SC_PER];
+#pragma unroll
+  for (int i = 0; i < SC_PER; ++i) {
+    const uint32_t t = (blockIdx.x * SC_PER + (uint32_t)i) * 256u + threadIdx.x;
+    b[i] = 0;
+    rank[i] = 0u;
+    if (t < (uint32_t)L.total_tiles) {
+      b[i] = len_bucket(ranges[2 * t + 1] - ranges[2 * t]);
+      rank[i] = atomicAdd(&cnt[b[i]], 1u);
+    }
   }
   __syncthreads();
   if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x])
     base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
   __syncthreads();
-  if (t < (uint32_t)L.total_tiles) {
-    TileSlot sl;
-    sl.tile = t;
-    sl.view = (uint32_t)find_view_by_tile(vw, L.nv, (int)t);
-    sl.start = ranges[2 * t];
-    sl.end = ranges[2 * t + 1];
-    order[base[b] + rank] = sl;
+#pragma unroll
+  for (int i = 0; i < SC_PER; ++i) {
+    const uint32_t t = (blockIdx.x * SC_PER + (uint32_t)i) * 256u + threadIdx.x;
+    if (t < (uint32_t)L.total_tiles) {
+      TileSlot sl;
+      sl.tile = t;
+      sl.view = (uint32_t)find_view_by_tile(vw, L.nv, (int)t);
+      sl.start = ranges[2 * t];
+      sl.end = ranges[2 * t + 1];
+      order[base[b[i]] + rank[i]] = sl;
+    }
   }
 }
 
 hipError_t launch_tile_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
+  const unsigned nb = (unsigned)((L.total_tiles + 256 * SC_PER - 1) / (256 * SC_PER));
   // the length histogram was counted by k_tile_lists
   k_tile_scatter<<<nb, 256, 0, st>>>(ws, L);
   return hipGetLastError();
@@ -809,17 +821,21 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
       if (np > (uint64_t)L.entry_cap) hdr->overflow |= 4u;   // the forward's outputs stand; its backward would not
     }
   }
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  int b = 0;
-  uint32_t rank = 0, prank = 0;
-  TileSlot sl{};
-  uint32_t pe = 0;
-  if (t < (uint32_t)L.total_tiles) {
-    sl = slots[t];
-    pe = pend[t];
-    b = len_bucket(pe - sl.start);
-    rank = atomicAdd(&cnt[b], 1u);
-    if (pairs && pe > sl.start) prank = atomicAdd(&pcnt[b], at<const uint32_t>(ws, L.o_slot_pairs)[t]);
+  int b[SC_PER];
+  uint32_t rank[SC_PER], prank[SC_PER], pe[SC_PER];
+  TileSlot sl[SC_PER];
+#pragma unroll
+  for (int i = 0; i < SC_PER; ++i) {
+    const uint32_t t = (blockIdx.x * SC_PER + (uint32_t)i) * 256u + threadIdx.x;
+    b[i] = 0;
+    rank[i] = prank[i] = pe[i] = 0u;
+    if (t < (uint32_t)L.total_tiles) {
+      sl[i] = slots[t];
+      pe[i] = pend[t];
+      b[i] = len_bucket(pe[i] - sl[i].start);
+      rank[i] = atomicAdd(&cnt[b[i]], 1u);
+      if (pairs && pe[i] > sl[i].start) prank[i] = atomicAdd(&pcnt[b[i]], at<const uint32_t>(ws, L.o_slot_pairs)[t]);
+    }
   }
   __syncthreads();
   if (threadIdx.x < TILE_BUCKETS && cnt[threadIdx.x]) {
@@ -829,16 +845,21 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(void* ws, Layout L) {
                            atomicAdd(at<uint32_t>(ws, L.o_bwd_hist) + 3 * TILE_BUCKETS + threadIdx.x, pcnt[threadIdx.x]);
   }
   __syncthreads();
-  if (t < (uint32_t)L.total_tiles) {
-    bslots[base[b] + rank] = sl;
-    bpend[base[b] + rank] = pe;
-    if (pairs) at<uint32_t>(ws, L.o_bwd_base)[base[b] + rank] = pbase[b] + prank;
+#pragma unroll
+  for (int i = 0; i < SC_PER; ++i) {
+    const uint32_t t = (blockIdx.x * SC_PER + (uint32_t)i) * 256u + threadIdx.x;
+    if (t < (uint32_t)L.total_tiles) {
+      const uint32_t q = base[b[i]] + rank[i];
+      bslots[q] = sl[i];
+      bpend[q] = pe[i];
+      if (pairs) at<uint32_t>(ws, L.o_bwd_base)[q] = pbase[b[i]] + prank[i];
+    }
   }
 }
 
 hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((L.total_tiles + 255) / 256);
+  const unsigned nb = (unsigned)((L.total_tiles + 256 * SC_PER - 1) / (256 * SC_PER));
   // histograms: counted by the forward compositing kernel; cursors: cleared
   // by the project kernel
   k_bwd_scatter<<<nb, 256, 0, st>>>(ws, L);
@@ -859,8 +880,12 @@ hipError_t launch_bwd_order(void* ws, const Layout& L, hipStream_t st) {
 // longer one sorts runs of DS_CAP in LDS and merges them the same way in
 // HBM, ping-ponging between the other tile-sort buffer pair and the tile's
 // own range of the result pair (whose tile keys are rewritten at the end).
+// DS_CAP = 1024 keeps the workgroup at 16 KB of LDS (eight per CU): at the
+// training shape the lists average about 400 entries and reach about 1,100,
+// and the sort took 37 us against 43 us with 2048 (five per CU) and 45 us
+// with 512 (more lists take the HBM merge).
 // ---------------------------------------------------------------------------
-constexpr int DS_CAP = 2048;
+constexpr int DS_CAP = 1024;
 
 // Where element i (key `key`) of a run of length w goes when runs are merged
 // pairwise: `get(j)` reads the key at index j of the current array of length n.
