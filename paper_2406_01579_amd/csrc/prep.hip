@@ -74,7 +74,8 @@ hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int 
 // ---------------------------------------------------------------------------
 // a1: pre-filter.  alpha_max = Eq. 1 at (max f, min f) over the 4 vertices;
 // keep iff alpha_max >= prefilter_tf.  Kept tets are compacted in ascending
-// tet id per scene (block counts, one-block scan, block-local rescan).
+// tet id per scene (block counts; each compaction block sums the counts of
+// the blocks before it and rescans its own tets).
 // ---------------------------------------------------------------------------
 constexpr int PF_THREADS = 256;
 constexpr int PF_PER_THREAD = PF_TILE / PF_THREADS;  // 4 consecutive tets per thread
@@ -155,50 +156,44 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_count(void* ws, Layout L, flo
   if (threadIdx.x == 0) cnt[b] = tot;
 }
 
-// one block: exclusive scan of the block counts, per-scene kept ranges,
-// per-view record bases, totals and capacity checks
-__global__ __launch_bounds__(1024) void k_pf_scan(void* ws, Layout L) {
+// Per-scene kept ranges, per-view record bases, totals and capacity checks
+// from the pre-filter blocks' counts (thread t sums a contiguous range of
+// them; a scan of the range sums gives each range's start, and the scene
+// whose first block lies in a range takes its base from there).  One block.
+__device__ void prefilter_totals(void* ws, const Layout& L, uint32_t* lds /*[8]*/) {
   DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
   const DevView* vw = at<const DevView>(ws, L.o_view);
-  uint32_t* cnt = at<uint32_t>(ws, L.o_pf_cnt);
+  const uint32_t* cnt = at<const uint32_t>(ws, L.o_pf_cnt);
   int32_t* kbase = at<int32_t>(ws, L.o_scene_kept_base);
   int32_t* kcount = at<int32_t>(ws, L.o_scene_kept_count);
   int32_t* rbase = at<int32_t>(ws, L.o_view_rec_base);
-  __shared__ uint32_t part[1024];
   const int n = (int)L.pf_blocks;
-  const int per = (n + 1023) / 1024;
-  const int t = threadIdx.x;
+  const int per = (n + PF_THREADS - 1) / PF_THREADS;
+  const int j0 = min(n, (int)threadIdx.x * per), j1 = min(n, j0 + per);
   uint32_t sum = 0;
-  for (int i = t * per; i < min(n, (t + 1) * per); ++i) sum += cnt[i];
-  part[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t v = (t >= o) ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  for (int j = j0; j < j1; ++j) sum += cnt[j];
+  uint32_t total;
+  const uint32_t start = block_exclusive_scan_256(sum, lds, &total);
+  const uint32_t cap = (uint32_t)L.kept_cap;
+  // scene s starts at block block_base (a scene with no blocks shares the
+  // next one's; past the last block: the total)
+  for (int s = 0; s < L.ns; ++s) {
+    const int bb = sc[s].block_base;
+    const bool mine = (bb >= j0 && bb < j1) || (bb >= n && threadIdx.x == PF_THREADS - 1);
+    if (mine) {
+      uint32_t x = start;
+      for (int j = j0; j < min(bb, j1); ++j) x += cnt[j];
+      kbase[s] = (int32_t)min(x, cap);
+    }
   }
-  uint32_t run = part[t] - sum;
-  for (int i = t * per; i < min(n, (t + 1) * per); ++i) {
-    uint32_t c = cnt[i];
-    cnt[i] = run;
-    run += c;
-  }
   __syncthreads();
-  if (t == 0) {
-    const uint32_t total = part[1023];
-    const uint32_t cap = (uint32_t)L.kept_cap;
+  if (threadIdx.x == 0) {
     hdr->kept_total = total;
-    uint32_t ovf = 0;
-    if (total > cap) ovf |= 1u;
+    uint32_t ovf = total > cap ? 1u : 0u;
     for (int s = 0; s < L.ns; ++s) {
-      const int bb0 = sc[s].block_base, bb1 = sc[s].block_base + sc[s].n_blocks;
-      uint32_t b0 = (bb0 < n) ? cnt[bb0] : total;
-      uint32_t b1 = (bb1 < n) ? cnt[bb1] : total;
-      if (b0 > cap) b0 = cap;
-      if (b1 > cap) b1 = cap;
-      kbase[s] = (int32_t)b0;
+      const uint32_t b0 = (uint32_t)kbase[s];
+      const uint32_t b1 = s + 1 < L.ns ? (uint32_t)kbase[s + 1] : min(total, cap);
       kcount[s] = (int32_t)(b1 - b0);
     }
     uint64_t r = 0;
@@ -214,14 +209,22 @@ __global__ __launch_bounds__(1024) void k_pf_scan(void* ws, Layout L) {
 }
 
 // rescan and write the kept tets' records: vertices, SDF, normal (App. A.3 via
-// the equivalent 3x3 edge system), mean colour
+// the equivalent 3x3 edge system), mean colour.  Each block finds the kept
+// tets before it by summing the counts of the blocks before it (all threads
+// at once); block 0 also writes the per-scene and per-view totals.
 __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, float tf) {
   const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  const uint32_t* off = at<const uint32_t>(ws, L.o_pf_cnt);
+  const uint32_t* cnt = at<const uint32_t>(ws, L.o_pf_cnt);
   TetRec* trec = at<TetRec>(ws, L.o_trec);
   int32_t* kept_tet = at<int32_t>(ws, L.o_kept_tet);
   __shared__ uint32_t lds[8];
   const int b = blockIdx.x;
+  if (b == 0) prefilter_totals(ws, L, lds);
+  if (b >= (int)L.pf_blocks) return;   // (no blocks of tets: block 0 only writes the totals)
+  uint32_t part = 0;
+  for (int j = threadIdx.x; j < b; j += PF_THREADS) part += cnt[j];
+  uint32_t before;
+  block_exclusive_scan_256(part, lds, &before);
   const int s = find_scene_by_block(sc, L.ns, b);
   const DevScene S = sc[s];
   const int k0 = (b - S.block_base) * PF_TILE + threadIdx.x * PF_PER_THREAD;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
     c += kp[q] ? 1u : 0u;
   }
   uint32_t tot;
-  uint32_t slot = off[b] + block_exclusive_scan_256(c, lds, &tot);
+  uint32_t slot = before + block_exclusive_scan_256(c, lds, &tot);
 #pragma unroll
   for (int q = 0; q < PF_PER_THREAD; ++q) {
     if (!kp[q]) continue;
@@ -283,8 +286,7 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
 
 hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
   if (L.pf_blocks > 0) k_pf_count<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
-  k_pf_scan<<<1, 1024, 0, st>>>(ws, L);
-  if (L.pf_blocks > 0) k_pf_scatter<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
+  k_pf_scatter<<<(unsigned)std::max<int64_t>(L.pf_blocks, 1), PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
   return hipGetLastError();
 }
 
