@@ -497,9 +497,10 @@ int render_forward(const render_scene* scenes, int n_scenes, const render_view* 
   std::vector<DevView> hv;
   std::vector<int32_t> sv;
   fill_desc(scenes, n_scenes, views, n_views, params, L, hs, hv, sv);
-  TS_STAGE(RENDER_STAGE_UPLOAD, launch_write_desc(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, true, st),
-           "upload descriptors");
-  TS_STAGE(RENDER_STAGE_PREFILTER, launch_prefilter(workspace, L, *params, st), "pre-filter");
+  // (the descriptor upload rides on the pre-filter's first launch when it fits)
+  TS_STAGE(RENDER_STAGE_PREFILTER,
+           launch_desc_prefilter(hs.data(), n_scenes, hv.data(), n_views, sv.data(), workspace, L, *params, st),
+           "descriptor upload and pre-filter");
   TS_STAGE(RENDER_STAGE_PROJECT, launch_project(workspace, L, *params, st), "project");
   TS_STAGE(RENDER_STAGE_SCAN, launch_count_scan(workspace, L, *params, st), "count scan and tile lists");
   TS_STAGE(RENDER_STAGE_EMIT, launch_emit(workspace, L, *params, st), "emit");

@@ -61,15 +61,6 @@ static hipError_t desc_image(const DevScene* hs, int ns, const DevView* hv, int 
   return hipSuccess;
 }
 
-// in as few launches as the argument size allows
-hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
-                             void* ws, const Layout& L, bool reset_header, hipStream_t st) {
-  std::vector<uint8_t> img;
-  size_t first;
-  const hipError_t e = desc_image(hs, ns, hv, nv, scene_views, L, reset_header, img, first);
-  if (e != hipSuccess) return e;
-  return upload(img.data(), img.size(), at<void>(ws, first), st);
-}
 
 // ---------------------------------------------------------------------------
 // a1: pre-filter.  alpha_max = Eq. 1 at (max f, min f) over the 4 vertices;
@@ -96,7 +87,7 @@ __device__ __forceinline__ bool keep_tet(const DevScene& S, int k, float tf, uin
   if (vi_out) *vi_out = vi;
   if ((unsigned)vi.x >= (unsigned)S.V || (unsigned)vi.y >= (unsigned)S.V || (unsigned)vi.z >= (unsigned)S.V ||
       (unsigned)vi.w >= (unsigned)S.V) {
-    if (invalid) atomicOr(invalid, 1u);
+    if (invalid) *invalid = 1u;
     return false;
   }
   float f0 = S.sdf[vi.x], f1 = S.sdf[vi.y], f2 = S.sdf[vi.z], f3 = S.sdf[vi.w];
@@ -126,24 +117,27 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
   return wbase + x - v;
 }
 
-__global__ __launch_bounds__(PF_THREADS) void k_pf_count(void* ws, Layout L, float tf) {
-  const DevScene* sc = at<const DevScene>(ws, L.o_scene);
-  DevHeader* hdr = at<DevHeader>(ws, L.o_hdr);
+// A block's kept count, with PF_INVALID set when one of its tets had a
+// vertex index out of range (the totals put it into the header).
+constexpr uint32_t PF_INVALID = 1u << 31;
+
+__device__ __forceinline__ void pf_count_body(void* ws, const Layout& L, float tf, const DevScene* sc) {
   uint32_t* cnt = at<uint32_t>(ws, L.o_pf_cnt);
   __shared__ uint32_t lds[8];
   const int b = blockIdx.x;
   const int s = find_scene_by_block(sc, L.ns, b);
   const DevScene S = sc[s];
   const int k0 = (b - S.block_base) * PF_TILE + threadIdx.x * PF_PER_THREAD;
-  uint32_t c = 0, nib = 0;
+  uint32_t c = 0, nib = 0, bad = 0;
   static_assert(PF_PER_THREAD == 4 && PF_THREADS % 8 == 0, "a thread's four decisions are a nibble of a word");
 #pragma unroll
   for (int q = 0; q < PF_PER_THREAD; ++q) {
     int k = k0 + q;
-    const bool kp = k < S.K && keep_tet(S, k, tf, &hdr->invalid_index, nullptr);
+    const bool kp = k < S.K && keep_tet(S, k, tf, &bad, nullptr);
     c += kp ? 1u : 0u;
     nib |= kp ? 1u << q : 0u;
   }
+  const int any_bad = __syncthreads_or((int)bad);
   // the decisions, 4 bits per thread: eight threads fill a word
   const int lane = threadIdx.x & 63;
   uint32_t w = nib << (4 * (lane & 7));
@@ -153,7 +147,23 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_count(void* ws, Layout L, flo
   if ((lane & 7) == 0) at<uint32_t>(ws, L.o_pf_keep)[(size_t)b * (PF_TILE / 32) + (threadIdx.x >> 3)] = w;
   uint32_t tot;
   block_exclusive_scan_256(c, lds, &tot);
-  if (threadIdx.x == 0) cnt[b] = tot;
+  if (threadIdx.x == 0) cnt[b] = tot | (any_bad ? PF_INVALID : 0u);
+}
+
+__global__ __launch_bounds__(PF_THREADS) void k_pf_count(void* ws, Layout L, float tf) {
+  pf_count_body(ws, L, tf, at<const DevScene>(ws, L.o_scene));
+}
+
+// The same, with the forward's descriptor image (header, scenes, views and
+// scene-view lists) as the argument: block 0 writes it to the workspace for
+// the kernels after this one (no block of this one reads the workspace's
+// copy or the header), and every block reads its scene from the argument.
+__global__ __launch_bounds__(PF_THREADS) void k_pf_count_desc(Blob d, int nwords, void* ws, Layout L, float tf) {
+  if (blockIdx.x == 0) {
+    uint32_t* dst = at<uint32_t>(ws, L.o_hdr);
+    for (int i = threadIdx.x; i < nwords; i += PF_THREADS) dst[i] = d.w[i];
+  }
+  pf_count_body(ws, L, tf, reinterpret_cast<const DevScene*>(d.w + (L.o_scene - L.o_hdr) / 4));
 }
 
 // Per-scene kept ranges, per-view record bases, totals and capacity checks
@@ -171,8 +181,12 @@ __device__ void prefilter_totals(void* ws, const Layout& L, uint32_t* lds /*[8]*
   const int n = (int)L.pf_blocks;
   const int per = (n + PF_THREADS - 1) / PF_THREADS;
   const int j0 = min(n, (int)threadIdx.x * per), j1 = min(n, j0 + per);
-  uint32_t sum = 0;
-  for (int j = j0; j < j1; ++j) sum += cnt[j];
+  uint32_t sum = 0, bad = 0;
+  for (int j = j0; j < j1; ++j) {
+    sum += cnt[j] & ~PF_INVALID;
+    bad |= cnt[j] & PF_INVALID;
+  }
+  const int any_bad = __syncthreads_or((int)(bad != 0u));
   uint32_t total;
   const uint32_t start = block_exclusive_scan_256(sum, lds, &total);
   const uint32_t cap = (uint32_t)L.kept_cap;
@@ -183,7 +197,7 @@ __device__ void prefilter_totals(void* ws, const Layout& L, uint32_t* lds /*[8]*
     const bool mine = (bb >= j0 && bb < j1) || (bb >= n && threadIdx.x == PF_THREADS - 1);
     if (mine) {
       uint32_t x = start;
-      for (int j = j0; j < min(bb, j1); ++j) x += cnt[j];
+      for (int j = j0; j < min(bb, j1); ++j) x += cnt[j] & ~PF_INVALID;
       kbase[s] = (int32_t)min(x, cap);
     }
   }
@@ -205,6 +219,7 @@ __device__ void prefilter_totals(void* ws, const Layout& L, uint32_t* lds /*[8]*
     hdr->records_total = (uint32_t)r;
     hdr->overflow = ovf;
     hdr->entries_total = 0;
+    if (any_bad) hdr->invalid_index = 1u;
   }
 }
 
@@ -222,7 +237,7 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
   if (b == 0) prefilter_totals(ws, L, lds);
   if (b >= (int)L.pf_blocks) return;   // (no blocks of tets: block 0 only writes the totals)
   uint32_t part = 0;
-  for (int j = threadIdx.x; j < b; j += PF_THREADS) part += cnt[j];
+  for (int j = threadIdx.x; j < b; j += PF_THREADS) part += cnt[j] & ~PF_INVALID;
   uint32_t before;
   block_exclusive_scan_256(part, lds, &before);
   const int s = find_scene_by_block(sc, L.ns, b);
@@ -287,6 +302,28 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
 hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
   if (L.pf_blocks > 0) k_pf_count<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
   k_pf_scatter<<<(unsigned)std::max<int64_t>(L.pf_blocks, 1), PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
+  return hipGetLastError();
+}
+
+// The forward's descriptor upload and pre-filter: when the descriptor image
+// fits one kernel argument, the pre-filter's counting launch carries it (one
+// launch fewer); otherwise it goes up first.
+hipError_t launch_desc_prefilter(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                                 void* ws, const Layout& L, const render_params& p, hipStream_t st) {
+  std::vector<uint8_t> img;
+  size_t first;
+  hipError_t e = desc_image(hs, ns, hv, nv, scene_views, L, true, img, first);
+  if (e != hipSuccess) return e;
+  const size_t words = img.size() / 4;
+  if (words > (size_t)BLOB_WORDS || L.pf_blocks == 0 || first != L.o_hdr) {
+    e = upload(img.data(), img.size(), at<void>(ws, first), st);
+    if (e != hipSuccess) return e;
+    return launch_prefilter(ws, L, p, st);
+  }
+  Blob b;
+  std::memcpy(b.w, img.data(), img.size());
+  k_pf_count_desc<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(b, (int)words, ws, L, p.prefilter_tf);
+  k_pf_scatter<<<(unsigned)L.pf_blocks, PF_THREADS, 0, st>>>(ws, L, p.prefilter_tf);
   return hipGetLastError();
 }
 

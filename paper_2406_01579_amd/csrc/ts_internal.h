@@ -173,9 +173,9 @@ __host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast
 // ---------------------------------------------------------------------------
 // launchers (each returns hipSuccess or the launch error)
 // ---------------------------------------------------------------------------
-hipError_t launch_write_desc(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
-                             void* ws, const Layout& L, bool reset_header, hipStream_t st);
 hipError_t launch_prefilter(void* ws, const Layout& L, const render_params& p, hipStream_t st);
+hipError_t launch_desc_prefilter(const DevScene* hs, int ns, const DevView* hv, int nv, const int32_t* scene_views,
+                                 void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_project(void* ws, const Layout& L, const render_params& p, hipStream_t st);
 hipError_t launch_tile_depth_sort(void* ws, const Layout& L, hipStream_t st);
 hipError_t launch_count_scan(void* ws, const Layout& L, const render_params& p, hipStream_t st);
