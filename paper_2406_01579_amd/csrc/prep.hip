@@ -764,9 +764,10 @@ hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStr
 // (longest first), from the complete histogram; the block's tiles of bucket
 // b then take consecutive places from first[b] + an atomic cursor.
 static_assert(TILE_BUCKETS <= 256, "one thread per bucket");
-// tiles per thread of the scatter kernels: fewer blocks, so fewer of the
-// global cursor atomics, which serialise per bucket
-constexpr int SC_PER = 4;
+// tiles per thread of the scatter kernels (4 -- a quarter of the blocks and
+// of their per-bucket cursor atomics -- was 5 us slower per step: the
+// per-block work grew more than the atomics shrank)
+constexpr int SC_PER = 1;
 __device__ __forceinline__ void bucket_first(const uint32_t* hist, uint32_t* first, uint32_t* lds /*[8]*/) {
   const int t = threadIdx.x;
   const uint32_t v = t < TILE_BUCKETS ? hist[TILE_BUCKETS - 1 - t] : 0u;

@@ -595,6 +595,31 @@ def test_training_deterministic_gradients_are_bitwise_repeatable(training, tile)
         assert n <= 1e-5
 
 
+@pytest.mark.parametrize("waves,chunks", [(2, (32, 16)), (4, (64, 32)), (8, (64, 32))])
+def test_multiwave_gradients_repeat_bitwise(waves, chunks):
+    """The multi-wave 8x8 backward with 2, 4 and 8 waves per tile, run eight
+    times on one input (deterministic mode: every sum in a fixed order): the
+    gradients are bit for bit equal, so no repeat sees another wave's LDS
+    or global hand-over early (the chunk arrays, candidate masks, pair
+    places and blend masks pass between waves only across barriers or
+    kernel boundaries)."""
+    import torch
+    w = synth.training(s=320.0, R=16, size=96, views=2)
+    sc = w.scenes[0]
+    P = _params("default", (8, 8), waves=waves, chunk_fwd=chunks[0], chunk_bwd=chunks[1], deterministic=True)
+    gen = np.random.default_rng(13)
+    douts = [torch.from_numpy(gen.normal(size=(8, 96, 96)).astype(np.float32)).cuda() for _ in range(2)]
+    r, plan, img0 = gpu_forward(sc, w.cams, P)
+    ref = [t.cpu().numpy() for t in r.backward(plan, douts)[0]]
+    assert max(np.abs(t).max() for t in ref) > 0
+    for _ in range(7):
+        r, plan, img = gpu_forward(sc, w.cams, P)
+        assert all(np.array_equal(a, b) for a, b in zip(img, img0))
+        got = [t.cpu().numpy() for t in r.backward(plan, douts)[0]]
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+
+
 def test_training_record_grads_and_recomputed_state_shrink_the_workspace(training):
     """RENDER_RECORD_GRADS + RENDER_RECOMPUTE_STATE at the training shape:
     a smaller workspace, the same image, gradients of a sparse upstream
