@@ -32,7 +32,7 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
                                               uint64_t* pmask, uint32_t* poff, uint64_t* hm, float (*feat)[CHN],
                                               unsigned long long* done_mask,
                                               float& T, float& Tb, float& O, float (&acc)[7], int& last,
-                                              bool want_acc, uint32_t* nblend = nullptr,
+                                              bool want_acc, uint32_t& nblend,
                                               unsigned long long* bmask = nullptr) {
   constexpr int NT = 64 * NWV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
           }
         }
       }
-      if (nblend) *nblend += (uint32_t)__popcll(blended);   // the chunk's blended pairs (per lane)
+      nblend += (uint32_t)__popcll(blended);   // the chunk's blended pairs (per lane)
       if (bmask) {
         // per entry of the chunk, the pixels that blended it (what the
         // backward's pairs are): lane e writes entry e's mask
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   uint32_t nblend = 0;
   const bool count = L.o_pairs != 0;
   forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff, hm,
-                          feat, &done_mask, T, Tb, O, acc, last, true, count ? &nblend : nullptr,
+                          feat, &done_mask, T, Tb, O, acc, last, true, nblend,
                           L.o_bmask ? at<unsigned long long>(ws, L.o_bmask) : nullptr);
   if ((threadIdx.x >> 6) == 0) {
     // end of the tile's blended prefix: where the backward starts its walk
@@ -297,8 +297,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   if (recompute) {
     float T = 1.0f, O = 0.0f;
     float acc[7];
+    uint32_t nb_unused = 0;
     forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, pmask, poff,
-                            hmask, feat, &done_mask, T, Tb, O, acc, last, false);
+                            hmask, feat, &done_mask, T, Tb, O, acc, last, false, nb_unused);
     if (wave == 0) {
       int wmax = last;
 #pragma unroll

@@ -52,9 +52,11 @@ static_assert(VB_HASH == 1 << 9, "the slot hash keeps 9 bits");
 // With DET the per-vertex terms of every kept tet's four corners are written
 // out (with the corner's global vertex id as a sort key) instead of being
 // combined, and k_vertex_gather adds them in a fixed order.
-// A 5-waves-per-SIMD target fits the kernel in 96 VGPRs without spills.
+// A 4-waves-per-SIMD target (at most 128 VGPRs): at 5 the kernel fits 96
+// VGPRs only by spilling a dozen values to scratch inside its loops, and
+// took 61 us against 52 us at the training shape.
 template <int P, bool DET>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_vertex_bwd(void* ws, Layout L) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vertex_bwd(void* ws, Layout L) {
   __shared__ uint32_t hkey[DET ? 1 : VB_HASH];   // vertex id + 1; 0: empty
   __shared__ float hval[7][DET ? 1 : VB_HASH];   // dverts xyz, dsdf, dcolors xyz
   __shared__ int bscene;
@@ -202,7 +204,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         dc[m] = group_sum<P>(dc[m]);
       }
     }
-    if (tet_ok && (any || DET) && q0 == 0) {
+    // every lane of the group holds the same sums (a butterfly of commutative
+    // adds) and chains the tet's view-independent parts alike; lane q then
+    // adds the tet's corners a = q (mod min(P, 4)) to the vertex sums
+    constexpr int PV = P < 4 ? P : 4;
+    if (tet_ok && (any || DET)) {
     const DevScene& S = sc[ks];
     // normal: n = g/|g|, g = E^-1 df
     if (dn[0] != 0.0f || dn[1] != 0.0f || dn[2] != 0.0f) {
@@ -249,14 +255,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       // sort's identity value)
       uint32_t* key = at<uint32_t>(ws, L.o_vkey_a);
       float4* term = at<float4>(ws, L.o_vterm);
+#pragma unroll
       for (int a = 0; a < 4; ++a) {
+        if (a % PV != q0) continue;
         const size_t cid = 4 * (size_t)k + (size_t)a;
         key[cid] = (uint32_t)S.vbase + (uint32_t)idx[a];
         term[2 * cid] = make_float4(dv[a][0], dv[a][1], dv[a][2], dfv[a]);
         term[2 * cid + 1] = make_float4(0.25f * dc[0], 0.25f * dc[1], 0.25f * dc[2], 0.0f);
       }
     } else
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
+      if (a % PV != q0) continue;
       const uint32_t vv = (uint32_t)idx[a];
       const float val[7] = {dv[a][0], dv[a][1], dv[a][2], dfv[a], 0.25f * dc[0], 0.25f * dc[1], 0.25f * dc[2]};
       bool put = false;
