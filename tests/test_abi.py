@@ -236,15 +236,16 @@ def test_regularizer_entry_points_validate_on_the_host(L):
 
 def test_resort_window_arguments(L):
     """The resort window is 0..RENDER_WINDOW_MAX on 8x8 tiles; with it on, the
-    workspace holds 44 bytes per entry more (its backward's blend records,
-    blend masks and pair places)."""
+    workspace holds 44 bytes per entry for its backward's blend records,
+    blend masks and pair places, and not the per-tile order's 8-byte blend
+    mask per entry: 36 bytes per entry more."""
     w = synth.tiny()
     scenes, views, p = _args(L, w, (8, 8))
     rc, base = _size(L, scenes, views, p, ent=10000)
     assert rc == 0
     p.window = 5
     rc, with_win = _size(L, scenes, views, p, ent=10000)
-    assert rc == 0 and 44 * 10000 <= with_win - base <= 44 * 10000 + 3 * 256
+    assert rc == 0 and 36 * 10000 <= with_win - base <= 36 * 10000 + 3 * 256
     for bad in (-1, L.RENDER_WINDOW_MAX + 1):
         p.window = bad
         assert _size(L, scenes, views, p)[0] == L.RENDER_EINVAL
