@@ -431,7 +431,8 @@ __global__ __launch_bounds__(256) void k_project(void* ws, Layout L, int tw_log2
           }
           for (int F = 0; F < 4; ++F) {
             const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
-            R.D[F] = (px[B] - px[A]) * (py[C] - py[A]) - (py[B] - py[A]) * (px[C] - px[A]);
+            const float D = (px[B] - px[A]) * (py[C] - py[A]) - (py[B] - py[A]) * (px[C] - px[A]);
+            R.rD[F] = D != 0.0f ? rcp(D) : 0.0f;   // once per record, not per pixel
           }
           R.c[0] = T.c[0]; R.c[1] = T.c[1]; R.c[2] = T.c[2];
           R.zt = zt;

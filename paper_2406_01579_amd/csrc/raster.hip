@@ -173,7 +173,7 @@ __device__ __forceinline__ void face_grad(const ViewRec& R, const PixEval& h, fl
   constexpr int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
   constexpr int I[3] = {A, B, C};
   const float invS = rcp(h.S[F]);
-  const float fF = h.f[F];
+  const float fF = F == h.fe ? h.fin : h.fout;   // F is the entry or the exit face
   float a[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {

@@ -29,7 +29,7 @@ template <int NWV, int CHN>
 __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, const uint32_t* __restrict__ srec,
                                               uint32_t start, uint32_t end, const Tile8& c, float s, float alpha_min,
                                               float alpha_clamp, float t_min, ViewRec* recs, float (*alds)[64],
-                                              uint64_t* pmask, uint32_t* poff, uint64_t* hm, float (*feat)[CHN],
+                                              PairMap<CHN>& pm, uint64_t* hm, float (*feat)[CHN],
                                               unsigned long long* done_mask,
                                               float& T, float& Tb, float& O, float (&acc)[7], int& last,
                                               bool want_acc, uint32_t& nblend,
@@ -64,9 +64,9 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
       const int e = q / 7, k = q - e * 7;
       feat[k][e] = k < 3 ? recs[e].c[k] : k == 3 ? recs[e].zt : recs[e].n[k - 4];
     }
-    if (wave == 0) chunk_pairs<CHN>(recs, n, c, ~*done_mask, pmask, poff);
+    if (wave == 0) chunk_pairs<CHN>(recs, n, c, ~*done_mask, pm);
     __syncthreads();
-    for_each_pair<CHN>(n, pmask, poff, NT, [&](int e, int pix) {
+    for_each_pair<CHN>(pm, NT, [&](int e, int pix) {
       const float qx = (float)(c.tx * 8 + (pix & 7)) + 0.5f, qy = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
       PixEval h;
       if (pixel_eval(recs[e], qx, qy, s, h) && h.alpha >= alpha_min) {
@@ -161,7 +161,7 @@ __device__ __forceinline__ void background_tiles(void* ws, const Layout& L, cons
 }  // namespace
 
 template <int NWV, int CHN>
-__global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, float alpha_min, float alpha_clamp,
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_composite_mw(void* ws, Layout L, float alpha_min, float alpha_clamp,
                                                            float t_min) {
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
@@ -170,8 +170,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   float* tlast_out = at<float>(ws, L.o_tlast);
   __shared__ ViewRec recs[CHN];
   __shared__ float alds[CHN][64];
-  __shared__ uint64_t pmask[CHN];
-  __shared__ uint32_t poff[CHN + 1];
+  __shared__ PairMap<CHN> pm;
   __shared__ uint64_t hm[64];
   __shared__ float feat[7][CHN];
   __shared__ unsigned long long done_mask;
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_mw(void* ws, Layout L, f
   int last = -1;
   uint32_t nblend = 0;
   const bool count = L.o_pairs != 0;
-  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pmask, poff, hm,
+  forward_sweep<NWV, CHN>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, alds, pm, hm,
                           feat, &done_mask, T, Tb, O, acc, last, true, nblend,
                           L.o_bmask ? at<unsigned long long>(ws, L.o_bmask) : nullptr);
   if ((threadIdx.x >> 6) == 0) {
@@ -267,8 +266,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   __shared__ float abuf[CHB][64];    // raw alpha
   __shared__ float e2buf[CHB][64];   // exp(s f_next)
   __shared__ uint8_t sel[CHB][64];   // entry face | exit face << 2
-  __shared__ uint64_t pmask[CHB];
-  __shared__ uint32_t poff[CHB + 1];
+  __shared__ PairMap<CHB> pm;        // phase A's pairs
+  __shared__ uint64_t pmask[CHB];    // phase B: per entry, the pixels that blended it
+  __shared__ uint32_t poff[CHB + 1]; // and the places of its pairs
   __shared__ uint64_t hmask[64];     // per pixel: chunk entries it may have blended (bit e)
   __shared__ float feat[7][CHB];     // per entry: c[3], zt, n[3] (conflict-free gathers)
   __shared__ unsigned long long done_mask;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     float T = 1.0f, O = 0.0f;
     float acc[7];
     uint32_t nb_unused = 0;
-    forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, pmask, poff,
+    forward_sweep<NWV, CHB>(vrec, srec, start, end, c, s, alpha_min, alpha_clamp, t_min, recs, abuf, pm,
                             hmask, feat, &done_mask, T, Tb, O, acc, last, false, nb_unused);
     if (wave == 0) {
       int wmax = last;
@@ -359,10 +359,10 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
       // lane e: the pixels that blended entry e (the forward's masks, loaded
       // a chunk ahead)
       const uint64_t live_e = bm_cur;
-      chunk_pairs<CHB>(recs, n, c, live_e, pmask, poff);
+      chunk_pairs<CHB>(recs, n, c, live_e, pm);
     }
     __syncthreads();
-    for_each_pair<CHB>(n, pmask, poff, NT, [&](int e, int pix) {
+    for_each_pair<CHB>(pm, NT, [&](int e, int pix) {
       const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
       PixEval h;
       if (pixel_eval(recs[e], px_, py_, s, h)) {

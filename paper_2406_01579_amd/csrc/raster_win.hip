@@ -134,8 +134,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   __shared__ float alds[CHW][64];
   __shared__ float zlds[CHW][64];
   __shared__ float feat[7][CHW];        // per entry: c[3], zt, n[3]
-  __shared__ uint64_t pmask[CHW];
-  __shared__ uint32_t poff[CHW + 1];
+  __shared__ PairMap<CHW> pm;
   __shared__ uint32_t hm[64];           // per pixel: the chunk's candidates (bit e)
   __shared__ float pay[WS][8][64];      // per slot: alpha, c[3], zt, n[3]
   __shared__ unsigned long long done_mask;
@@ -202,9 +201,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
     if (end - base > 2u * CHW) rp.fetch_idx(srec, base + 2 * CHW, (int)min((uint32_t)CHW, end - base - 2 * CHW));
     __syncthreads();
     load_chunk_tables(recs, n, feat, hm, NT);
-    if (wave == 0) chunk_pairs<CHW>(recs, n, c, ~done_mask, pmask, poff);
+    if (wave == 0) chunk_pairs<CHW>(recs, n, c, ~done_mask, pm);
     __syncthreads();
-    for_each_pair<CHW>(n, pmask, poff, NT, [&](int e, int pix) {
+    for_each_pair<CHW>(pm, NT, [&](int e, int pix) {
       const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
       PixEval h;
       if (pixel_eval(recs[e], px_, py_, s, h) && h.alpha >= alpha_min) {
@@ -321,8 +320,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   __shared__ uint8_t sel[CHB][64];      // entry face | exit face << 2
   __shared__ float feat[7][CHB];        // per entry: c[3], zt, n[3]
   __shared__ uint32_t erec[CHB], eslot[CHB];   // per entry: record, gradient slot
-  __shared__ uint64_t pmask[CHB];
-  __shared__ uint32_t poff[CHB + 1];
+  __shared__ PairMap<CHB> pm;
   __shared__ uint32_t hm[64];           // per pixel: the chunk's candidates (bit e)
   __shared__ uint32_t pay[WS][6][64];   // per slot: raw alpha, g . features, e2, faces, record, slot
   __shared__ uint32_t wsum[NWV];
@@ -411,9 +409,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
       eslot[threadIdx.x] = d;
       if ((uint64_t)d < cap) emask[d] = 0ull;
     }
-    if (wave == 0) chunk_pairs<CHB>(recs, n, c, ~done_mask, pmask, poff);
+    if (wave == 0) chunk_pairs<CHB>(recs, n, c, ~done_mask, pm);
     __syncthreads();
-    for_each_pair<CHB>(n, pmask, poff, NT, [&](int e, int pix) {
+    for_each_pair<CHB>(pm, NT, [&](int e, int pix) {
       const float px_ = (float)(c.tx * 8 + (pix & 7)) + 0.5f, py_ = (float)(c.ty * 8 + (pix >> 3)) + 0.5f;
       PixEval h;
       if (pixel_eval(recs[e], px_, py_, s, h) && h.alpha >= alpha_min) {

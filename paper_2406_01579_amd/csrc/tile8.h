@@ -146,35 +146,80 @@ __device__ __forceinline__ void pair_offsets(int n, uint64_t m_e, uint64_t* pmas
   if (lane == 0) poff[0] = 0u;
 }
 
+// A chunk's pair list, laid out so that a lane finds the entry of its pair
+// with a popcount and one LDS read (a binary search over the entries'
+// offsets was six dependent LDS reads per pair).  The entries with at least
+// one pair are listed in order; per block of 64 consecutive pairs, bstart
+// marks the pairs that begin a listed entry and bfirst counts the listed
+// entries that begin before the block.  Pair p (block b = p / 64) then
+// belongs to listed entry bfirst[b] + (starts in block b at or before p) - 1.
+template <int CH>
+struct PairMap {
+  uint64_t bstart[CH];   // per block of 64 pairs: bit q set where a listed entry's pairs begin
+  uint64_t lmask[CH];    // listed entry k: its pixel mask
+  uint32_t bfirst[CH];   // per block: listed entries beginning before it
+  uint32_t lent[CH];     // listed entry k: its chunk index | its first pair << 8
+  uint32_t total;        // pairs in the chunk
+};
+
+// Wave 0, lane e < n: m_e is entry e's pixel mask.  Every lane of the wave
+// must call it; the map is complete after the next barrier.
+template <int CH>
+__device__ __forceinline__ void pair_map(int n, uint64_t m_e, PairMap<CH>& M) {
+  static_assert(CH <= 64, "one lane per entry");
+  const int lane = threadIdx.x & 63;
+  const uint64_t m = lane < n ? m_e : 0ull;
+  const uint32_t cnt = (uint32_t)__popcll(m);
+  uint32_t x = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    x += lane >= d ? y : 0u;
+  }
+  const uint32_t first = x - cnt;
+  const uint32_t k = (uint32_t)__popcll(__ballot(m != 0ull) & ((1ull << lane) - 1ull));
+  // the pairs fill at most CH blocks; this wave's own LDS operations take
+  // effect in program order, so the clear lands before the marks
+  if (lane < CH) M.bstart[lane] = 0ull;
+  __builtin_amdgcn_wave_barrier();
+  if (m != 0ull) {
+    M.lmask[k] = m;
+    M.lent[k] = (uint32_t)lane | (first << 8);
+    atomicOr(&M.bstart[first >> 6], 1ull << (first & 63u));
+  }
+  __builtin_amdgcn_wave_barrier();
+  const uint64_t bs = lane < CH ? M.bstart[lane] : 0ull;
+  const uint32_t bc = (uint32_t)__popcll(bs);
+  uint32_t y = bc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t z = __shfl_up(y, d, 64);
+    y += lane >= d ? z : 0u;
+  }
+  if (lane < CH) M.bfirst[lane] = y - bc;
+  if (lane == 63) M.total = x;
+}
+
 // Wave 0, lane e < n: entry e's pairs are the pixels of its rectangle in
 // live_e (the pixels that still take part for that entry).
 template <int CH>
 __device__ __forceinline__ void chunk_pairs(const ViewRec* recs, int n, const Tile8& c, uint64_t live_e,
-                                            uint64_t* pmask, uint32_t* poff) {
+                                            PairMap<CH>& M) {
   const int lane = threadIdx.x & 63;
-  pair_offsets<CH>(n, lane < n ? rect_mask(recs[lane], c) & live_e : 0ull, pmask, poff);
+  pair_map<CH>(n, lane < n ? rect_mask(recs[lane], c) & live_e : 0ull, M);
 }
 
-// Last entry whose first pair (or group) is at or before p.
-template <int CH>
-__device__ __forceinline__ int entry_of(int n, const uint32_t* poff, uint32_t p) {
-  int e = 0;
-#pragma unroll
-  for (int step = CH / 2; step > 0; step >>= 1) {
-    const int t = e + step;
-    e = (t < n && poff[t] <= p) ? t : e;
-  }
-  return e;
-}
-
-// All threads: f(e, pix) for every listed pair (entry e, local pixel pix).
+// All threads: f(e, pix) for every listed pair (entry e, local pixel pix),
+// entry-major, pixels in ascending order inside an entry.
 template <int CH, class F>
-__device__ __forceinline__ void for_each_pair(int n, const uint64_t* pmask, const uint32_t* poff, int nthreads,
-                                              F&& f) {
-  const uint32_t total = poff[n];
+__device__ __forceinline__ void for_each_pair(const PairMap<CH>& M, int nthreads, F&& f) {
+  const uint32_t total = M.total;
   for (uint32_t p = threadIdx.x; p < total; p += (uint32_t)nthreads) {
-    const int e = entry_of<CH>(n, poff, p);
-    f(e, select_bit(pmask[e], p - poff[e]));
+    const uint32_t b = p >> 6;
+    // pair 0 begins the first listed entry, so at least one start lies at or before p
+    const uint32_t k = M.bfirst[b] + (uint32_t)__popcll(M.bstart[b] & (~0ull >> (63u - (p & 63u)))) - 1u;
+    const uint32_t le = M.lent[k];
+    f((int)(le & 0xffu), select_bit(M.lmask[k], p - (le >> 8)));
   }
 }
 

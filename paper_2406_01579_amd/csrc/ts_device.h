@@ -40,9 +40,10 @@ __host__ __device__ constexpr int face_vertex(int F, int k) {
                 : (k == 0 ? 1 : k == 1 ? 2 : 3);
 }
 
-__device__ __forceinline__ bool face_inside(float N0, float N1, float N2, float D) {
-  if (D > 0.0f) return N0 >= 0.0f && N1 >= 0.0f && N2 >= 0.0f;
-  if (D < 0.0f) return N0 <= 0.0f && N1 <= 0.0f && N2 <= 0.0f;
+// rD: 1 / D, or 0 where D == 0 (it has D's sign)
+__device__ __forceinline__ bool face_inside(float N0, float N1, float N2, float rD) {
+  if (rD > 0.0f) return N0 >= 0.0f && N1 >= 0.0f && N2 >= 0.0f;
+  if (rD < 0.0f) return N0 <= 0.0f && N1 <= 0.0f && N2 <= 0.0f;
   return false;
 }
 
@@ -53,11 +54,13 @@ __device__ __forceinline__ bool face_inside(float N0, float N1, float N2, float 
 // The six edge cross products e_ij = cross(P_i - p, P_j - p) give every N
 // exactly (a swapped pair is an exact negation).  Along the ray, with
 // w_k = 1/Z_k (App. A.2):  f = sum N_k w_k f_k / sum N_k w_k,
-// 1/z = sum N_k w_k / D.  Entry = nearest hit face, exit = farthest.
+// 1/z = sum N_k w_k / D.  Entry = nearest hit face, exit = farthest; the
+// interpolated f is divided out for those two faces only.
 struct PixEval {
   float ax[4], ay[4];
   float N[4][3];
-  float S[4], f[4];
+  float S[4];
+  float fin, fout; // f at the entry / exit face
   int fe, fx;      // entry / exit face
   float zin_inv;   // 1 / depth where the ray enters (entry face); larger is nearer
   float alpha;     // Eq. 1 (unclamped)
@@ -99,29 +102,33 @@ __device__ __forceinline__ bool pixel_eval(const ViewRec& r, float qx, float qy,
   h.N[3][0] = e23; h.N[3][1] = -e13; h.N[3][2] = e12;
   // every face is evaluated (no branches); only inside faces are selected
   int nh = 0;
-  float best_in = -INFINITY, best_out = INFINITY, fin = 0.0f, fout = 0.0f;
+  float best_in = -INFINITY, best_out = INFINITY;
+  float num_in = 0.0f, S_in = 1.0f, num_out = 0.0f, S_out = 1.0f;
   h.fe = 0;
   h.fx = 0;
 #pragma unroll
   for (int F = 0; F < 4; ++F) {
-    const bool in = face_inside(h.N[F][0], h.N[F][1], h.N[F][2], r.D[F]);
+    const bool in = face_inside(h.N[F][0], h.N[F][1], h.N[F][2], r.rD[F]);
     const int A = face_vertex(F, 0), B = face_vertex(F, 1), C = face_vertex(F, 2);
     const float qa = h.N[F][0] * r.iz[A], qb = h.N[F][1] * r.iz[B], qc = h.N[F][2] * r.iz[C];
     const float S = (qa + qb) + qc;
     const float num = fmaf(qa, r.f[A], fmaf(qb, r.f[B], qc * r.f[C]));
-    const float f = num * rcp(S);
-    const float invz = S * rcp(r.D[F]);  // 1 / depth at the hit: larger is nearer
+    const float invz = S * r.rD[F];  // 1 / depth at the hit: larger is nearer
     h.S[F] = S;
-    h.f[F] = f;
     nh += in ? 1 : 0;
     const bool bi = in && invz > best_in, bo = in && invz < best_out;
     best_in = bi ? invz : best_in;
-    fin = bi ? f : fin;
+    num_in = bi ? num : num_in;
+    S_in = bi ? S : S_in;
     h.fe = bi ? F : h.fe;
     best_out = bo ? invz : best_out;
-    fout = bo ? f : fout;
+    num_out = bo ? num : num_out;
+    S_out = bo ? S : S_out;
     h.fx = bo ? F : h.fx;
   }
+  const float fin = num_in * rcp(S_in), fout = num_out * rcp(S_out);
+  h.fin = fin;
+  h.fout = fout;
   h.zin_inv = best_in;
   // Eq. 1, stable form, with the hardware exponential
   const float d = fin - fout;

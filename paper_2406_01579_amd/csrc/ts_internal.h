@@ -88,7 +88,8 @@ struct ViewRec {
   float px[4], py[4];
   float iz[4];      // 1 / Z_k
   float f[4];
-  float D[4];       // 2D determinant of each projected face (exact sign)
+  float rD[4];      // 1 / the 2D determinant of each projected face (its sign: the
+                    // face's orientation); 0 for a degenerate face
   float c[3];
   float zt;         // mean camera depth (blend depth, sort key)
   float n[3];
