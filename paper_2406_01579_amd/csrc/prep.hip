@@ -529,10 +529,15 @@ __device__ __forceinline__ void block_entry(const uint32_t* loff, uint32_t m, ui
   tile = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
 }
 
+// records per thread of a 256-thread scan block (one, or none past the block's
+// records, when a block holds fewer than 256)
+constexpr int SCAN_PER = SCAN_TILE >= 256 ? SCAN_TILE / 256 : 1;
+static_assert(SCAN_TILE % 256 == 0 || 256 % SCAN_TILE == 0, "scan blocks of whole thread rounds");
+
 // The block's records: counts, their exclusive scan (loff) and the total.
 __device__ __forceinline__ uint32_t block_record_offsets(const uint32_t* __restrict__ count1, uint32_t q0, uint32_t m,
-                                                         uint32_t* loff, uint32_t* lds, uint32_t (&c)[SCAN_TILE / 256]) {
-  constexpr int PER = SCAN_TILE / 256;
+                                                         uint32_t* loff, uint32_t* lds, uint32_t (&c)[SCAN_PER]) {
+  constexpr int PER = SCAN_PER;
   const int t = threadIdx.x;
   uint32_t sum = 0;
 #pragma unroll
@@ -545,7 +550,7 @@ __device__ __forceinline__ uint32_t block_record_offsets(const uint32_t* __restr
   uint32_t run = block_exclusive_scan_256(sum, lds, &tot);
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    loff[t * PER + i] = run;
+    if (t * PER + i < SCAN_TILE) loff[t * PER + i] = run;
     run += c[i];
   }
   __syncthreads();
@@ -567,7 +572,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(void* ws, Layout L, int tw_
   const uint32_t q0 = blockIdx.x * SCAN_TILE;
   if (q0 >= n) return;
   const uint32_t m = min((uint32_t)SCAN_TILE, n - q0);
-  uint32_t c[SCAN_TILE / 256];
+  uint32_t c[SCAN_PER];
   const uint32_t tot = block_record_offsets(count1, q0, m, loff, lds, c);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
   for (uint32_t e0 = 0; e0 < tot; e0 += 256u) {
@@ -712,7 +717,7 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   uint4* rbox = at<uint4>(ws, L.o_rbox);
   uint32_t* cursor = at<uint32_t>(ws, L.o_tile_cnt);
   uint32_t* val2 = at<uint32_t>(ws, sorted_entry_records(L));
-  constexpr int PER = SCAN_TILE / 256;
+  constexpr int PER = SCAN_PER;
   __shared__ uint32_t loff[SCAN_TILE];
   __shared__ uint32_t lds[8];
   const uint32_t* part = at<const uint32_t>(ws, L.o_scan_part);
@@ -748,7 +753,9 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
 
 hipError_t launch_emit(void* ws, const Layout& L, const render_params& p, hipStream_t st) {
   int twl = __builtin_ctz((unsigned)p.tile_w), thl = __builtin_ctz((unsigned)p.tile_h);
-  k_emit<<<1024, 256, 0, st>>>(ws, L, twl, thl);
+  // one block per SCAN_TILE records, up to 4096 (then several each)
+  const int64_t nb = L.scan_blocks_rec;
+  k_emit<<<(unsigned)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096), 256, 0, st>>>(ws, L, twl, thl);
   return hipGetLastError();
 }
 

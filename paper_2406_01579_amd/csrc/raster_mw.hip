@@ -263,6 +263,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   uint4* pairs = at<uint4>(ws, L.o_pairs);
   __shared__ ViewRec recs[CHB];
   __shared__ uint4 eseg[CHB];        // per entry with a blended pixel: record, view, tile, gradient slot
+  __shared__ uint32_t ridx[CHB];     // per entry: its record
   __shared__ float abuf[CHB][64];    // raw alpha
   __shared__ float e2buf[CHB][64];   // exp(s f_next)
   __shared__ uint8_t sel[CHB][64];   // entry face | exit face << 2
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     const uint32_t base = (uint32_t)cb;
     const int n = (int)min((uint32_t)CHB, pend - base);
     __syncthreads();
-    rp.store(recs, n);
+    rp.store(recs, n, ridx);
     if (cb - CHB >= (int64_t)start) rp.fetch_rec(vrec, rbox);
     if (cb - 2 * CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb - 2 * CHB), CHB);
     bm_cur = bm_next;
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
         unpack_rect(R, i0, i1, j0, j1);
         const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
         const uint32_t d = R.entry0 + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
-        eseg[lane] = make_uint4(srec[base + lane], (uint32_t)c.view, tile_xy, d);
+        eseg[lane] = make_uint4(ridx[lane], (uint32_t)c.view, tile_xy, d);
       }
       // each pixel visits only the entries it blended, nearest-last first
       uint32_t m = m0;

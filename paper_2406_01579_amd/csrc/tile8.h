@@ -233,6 +233,7 @@ template <int CH, int NT, bool E0 = false>
 struct RecPipe {
   static constexpr int PQ = (CH * 8 + NT - 1) / NT;
   uint32_t idx[PQ];
+  uint32_t cur[PQ];                      // the record indices of the parts in flight
   float vx[PQ], vy[PQ], vz[PQ], vw[PQ];  // scalars, so the parts stay in registers
   __device__ __forceinline__ void fetch_idx(const uint32_t* __restrict__ srec, uint32_t base, int n) {
 #pragma unroll
@@ -247,6 +248,7 @@ struct RecPipe {
 #pragma unroll
     for (int j = 0; j < PQ; ++j) {
       const int q = (int)threadIdx.x + j * NT;
+      cur[j] = idx[j];
       const float4 t = reinterpret_cast<const float4*>(vrec)[(size_t)idx[j] * 8 + (size_t)(q & 7)];
       vx[j] = t.x;
       vy[j] = t.y;
@@ -255,11 +257,16 @@ struct RecPipe {
       if (E0 && (q & 7) == 7) vw[j] = __uint_as_float(rbox[idx[j]].w);   // entry0: the record's last word
     }
   }
-  __device__ __forceinline__ void store(ViewRec* recs, int n) const {
+  // With ridx, also each record's index (what a chunk needs of srec later
+  // comes from LDS then, not from a global load on its critical path).
+  __device__ __forceinline__ void store(ViewRec* recs, int n, uint32_t* ridx = nullptr) const {
 #pragma unroll
     for (int j = 0; j < PQ; ++j) {
       const int q = (int)threadIdx.x + j * NT;
-      if (q < n * 8) reinterpret_cast<float4*>(&recs[q >> 3])[q & 7] = make_float4(vx[j], vy[j], vz[j], vw[j]);
+      if (q < n * 8) {
+        reinterpret_cast<float4*>(&recs[q >> 3])[q & 7] = make_float4(vx[j], vy[j], vz[j], vw[j]);
+        if (ridx && (q & 7) == 0) ridx[q >> 3] = cur[j];
+      }
     }
   }
 };

@@ -117,7 +117,7 @@ enum { G_PX = 0, G_PY = 4, G_IZ = 8, G_F = 12, G_C = 16, G_ZT = 19, G_N = 20 };
 // workspace layout
 // ---------------------------------------------------------------------------
 constexpr int PF_TILE = 1024;      // tets per pre-filter block
-constexpr int SCAN_TILE = 512;     // records per scan block (the emit kernel's unit too)
+constexpr int SCAN_TILE = 256;     // records per scan block (the emit kernel's unit too)
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 4;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
