@@ -99,7 +99,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
 
   const TileCtx c = tile_ctx<TW, TH>(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = V.s;
+  const float s = uniform_f(V.s);
   const uint32_t start = c.start, end = c.end;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
 
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
 
   const TileCtx c = tile_ctx<TW, TH>(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = V.s;
+  const float s = uniform_f(V.s);
   const uint32_t start = c.start, end = c.end;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
   const size_t plane = (size_t)V.W * V.H;

@@ -45,17 +45,17 @@ __device__ __forceinline__ void forward_sweep(const ViewRec* __restrict__ vrec, 
   }
   RecPipe<CHN, NT> rp;
   if (start < end) {
-    rp.fetch_idx(srec, start, (int)min((uint32_t)CHN, end - start));
+    rp.fetch_idx(srec, start, end - 1);
     rp.fetch_rec(vrec);
-    if (end - start > (uint32_t)CHN) rp.fetch_idx(srec, start + CHN, (int)min((uint32_t)CHN, end - start - CHN));
+    rp.fetch_idx(srec, start + CHN, end - 1);
   }
   for (uint32_t base = start; base < end; base += CHN) {
     __syncthreads();
     if (*done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHN, end - base);
     rp.store(recs, n);
-    if (end - base > (uint32_t)CHN) rp.fetch_rec(vrec);
-    if (end - base > 2u * CHN) rp.fetch_idx(srec, base + 2 * CHN, (int)min((uint32_t)CHN, end - base - 2 * CHN));
+    rp.fetch_rec(vrec);
+    rp.fetch_idx(srec, base + 2 * CHN, end - 1);
     __syncthreads();
     // phase A: coverage and Eq. 1 of the live (entry, pixel) pairs, packed;
     // hm[pixel] collects the chunk entries the pixel may blend
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))
   }
   const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = V.s;
+  const float s = uniform_f(V.s);
   const uint32_t start = c.start, end = c.end;
   float T = 1.0f, Tb = 1.0f, O = 0.0f;
   float acc[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   if (!recompute && at<const uint32_t>(ws, L.o_bwd_pend)[blockIdx.x] == bslots[blockIdx.x].start) return;
   const Tile8 c = tile8(vw, bslots);
   const DevView& V = vw[c.view];
-  const float s = V.s;
+  const float s = uniform_f(V.s);
   const uint32_t start = c.start, end = c.end;
   const size_t plane = (size_t)V.W * V.H;
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
@@ -333,21 +333,26 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   // wave 0, lane e: the blend mask of the current chunk's entry e, and of the
   // next chunk's (its load in flight across the current chunk)
   uint64_t bm_cur = 0ull, bm_next = 0ull;
+  // the chunk starting at b, or below the list the entry pend - 1 again
+  const auto below = [&](int64_t b) { return b >= (int64_t)start ? (uint32_t)b : pend - 1u; };
   if (pend > start) {
-    rp.fetch_idx(srec, (uint32_t)cb0, (int)(pend - (uint32_t)cb0));
+    rp.fetch_idx(srec, (uint32_t)cb0, pend - 1u);
     rp.fetch_rec(vrec, rbox);
-    if (cb0 - CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb0 - CHB), CHB);
+    rp.fetch_idx(srec, below(cb0 - CHB), pend - 1u);
     if (wave == 0 && lane < pend - (uint32_t)cb0 && lane < (unsigned)CHB) bm_next = bmask[(uint32_t)cb0 + lane];
   }
   for (int64_t cb = cb0; cb >= (int64_t)start && pend > start; cb -= CHB) {
     const uint32_t base = (uint32_t)cb;
     const int n = (int)min((uint32_t)CHB, pend - base);
     __syncthreads();
-    rp.store(recs, n, ridx);
-    if (cb - CHB >= (int64_t)start) rp.fetch_rec(vrec, rbox);
-    if (cb - 2 * CHB >= (int64_t)start) rp.fetch_idx(srec, (uint32_t)(cb - 2 * CHB), CHB);
+    // the next masks' load is issued before the next records', so taking
+    // over the current masks (a wait for their load, a chunk old) does not
+    // also wait for the record loads just issued
     bm_cur = bm_next;
     if (wave == 0 && cb - CHB >= (int64_t)start && lane < (unsigned)CHB) bm_next = bmask[base - CHB + lane];
+    rp.store(recs, n, ridx);
+    rp.fetch_rec(vrec, rbox);
+    rp.fetch_idx(srec, below(cb - 2 * CHB), pend - 1u);
     __syncthreads();
     // phase A: coverage, faces and Eq. 1 of every (entry, pixel) pair the
     // forward blended, packed

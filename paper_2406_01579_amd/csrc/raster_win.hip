@@ -141,7 +141,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
 
   const Tile8 c = tile8(vw, at<const TileSlot>(ws, L.o_tile_order));
   const DevView& V = vw[c.view];
-  const float s = V.s;
+  const float s = uniform_f(V.s);
   const uint32_t start = c.start, end = c.end;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float qx = (float)c.i + 0.5f, qy = (float)c.j + 0.5f;
@@ -187,9 +187,9 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
   }
   RecPipe<CHW, NT> rp;
   if (start < end) {
-    rp.fetch_idx(srec, start, (int)min((uint32_t)CHW, end - start));
+    rp.fetch_idx(srec, start, end - 1);
     rp.fetch_rec(vrec);
-    if (end - start > (uint32_t)CHW) rp.fetch_idx(srec, start + CHW, (int)min((uint32_t)CHW, end - start - CHW));
+    rp.fetch_idx(srec, start + CHW, end - 1);
   }
   for (uint32_t base = start; base < end; base += CHW) {
     __syncthreads();
@@ -197,8 +197,8 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
     const int n = (int)min((uint32_t)CHW, end - base);
     walked = base + (uint32_t)n;
     rp.store(recs, n);
-    if (end - base > (uint32_t)CHW) rp.fetch_rec(vrec);
-    if (end - base > 2u * CHW) rp.fetch_idx(srec, base + 2 * CHW, (int)min((uint32_t)CHW, end - base - 2 * CHW));
+    rp.fetch_rec(vrec);
+    rp.fetch_idx(srec, base + 2 * CHW, end - 1);
     __syncthreads();
     load_chunk_tables(recs, n, feat, hm, NT);
     if (wave == 0) chunk_pairs<CHW>(recs, n, c, ~done_mask, pm);
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   if (pend == bslots[blockIdx.x].start) return;
   const Tile8 c = tile8(vw, bslots);
   const DevView& V = vw[c.view];
-  const float s = V.s;
+  const float s = uniform_f(V.s);
   const uint32_t start = c.start, end = pend;   // the forward walked [start, pend)
   const unsigned lane = threadIdx.x & 63u;
   const int wave = threadIdx.x >> 6;
@@ -386,16 +386,18 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
     if (lane == 0) done_mask = m;
   }
   RecPipe<CHB, NT, true> rp;
-  rp.fetch_idx(srec, start, (int)min((uint32_t)CHB, end - start));
-  rp.fetch_rec(vrec, rbox);
-  if (end - start > (uint32_t)CHB) rp.fetch_idx(srec, start + CHB, (int)min((uint32_t)CHB, end - start - CHB));
+  if (start < end) {
+    rp.fetch_idx(srec, start, end - 1);
+    rp.fetch_rec(vrec, rbox);
+    rp.fetch_idx(srec, start + CHB, end - 1);
+  }
   for (uint32_t base = start; base < end; base += CHB) {
     __syncthreads();
     if (done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHB, end - base);
     rp.store(recs, n);
-    if (end - base > (uint32_t)CHB) rp.fetch_rec(vrec, rbox);
-    if (end - base > 2u * CHB) rp.fetch_idx(srec, base + 2 * CHB, (int)min((uint32_t)CHB, end - base - 2 * CHB));
+    rp.fetch_rec(vrec, rbox);
+    rp.fetch_idx(srec, base + 2 * CHB, end - 1);
     __syncthreads();
     load_chunk_tables(recs, n, feat, hm, NT);
     if (threadIdx.x < (unsigned)n) {

@@ -235,14 +235,19 @@ struct RecPipe {
   uint32_t idx[PQ];
   uint32_t cur[PQ];                      // the record indices of the parts in flight
   float vx[PQ], vy[PQ], vz[PQ], vw[PQ];  // scalars, so the parts stay in registers
-  __device__ __forceinline__ void fetch_idx(const uint32_t* __restrict__ srec, uint32_t base, int n) {
+  // The chunk of entries from b, cut at hi (a valid entry): a part past hi
+  // loads entry hi's index again.  Callers issue every load of the pipeline
+  // unconditionally (past the list: its last entry, cached and never
+  // stored), so no register is given a default while an older load into it
+  // may be in flight, a wait that would also cover the loads just issued.
+  __device__ __forceinline__ void fetch_idx(const uint32_t* __restrict__ srec, uint32_t b, uint32_t hi) {
 #pragma unroll
     for (int j = 0; j < PQ; ++j) {
       const int q = (int)threadIdx.x + j * NT;
-      idx[j] = q < n * 8 ? srec[base + (uint32_t)(q >> 3)] : 0u;
+      idx[j] = srec[min(b + (uint32_t)(q >> 3), hi)];
     }
   }
-  // unconditional: a part past the chunk reads record 0 (allocated) and is never stored
+  // every part (one past the chunk reads a record of the list, never stored)
   __device__ __forceinline__ void fetch_rec(const ViewRec* __restrict__ vrec,
                                             const uint4* __restrict__ rbox = nullptr) {
 #pragma unroll

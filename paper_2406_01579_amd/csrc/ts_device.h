@@ -40,11 +40,13 @@ __host__ __device__ constexpr int face_vertex(int F, int k) {
                 : (k == 0 ? 1 : k == 1 ? 2 : 3);
 }
 
-// rD: 1 / D, or 0 where D == 0 (it has D's sign)
+// rD: 1 / D, or 0 where D == 0 (it has D's sign).  Written without branches
+// (bitwise on the comparisons), so the four faces' tests are plain compares
+// rather than divergent blocks that each wait for their own LDS operands.
 __device__ __forceinline__ bool face_inside(float N0, float N1, float N2, float rD) {
-  if (rD > 0.0f) return N0 >= 0.0f && N1 >= 0.0f && N2 >= 0.0f;
-  if (rD < 0.0f) return N0 <= 0.0f && N1 <= 0.0f && N2 <= 0.0f;
-  return false;
+  const bool up = (N0 >= 0.0f) & (N1 >= 0.0f) & (N2 >= 0.0f);
+  const bool down = (N0 <= 0.0f) & (N1 <= 0.0f) & (N2 <= 0.0f);
+  return ((rD > 0.0f) & up) | ((rD < 0.0f) & down);
 }
 
 // One pixel centre against one record.  For a projected face (A,B,C) the
@@ -66,6 +68,13 @@ struct PixEval {
   float alpha;     // Eq. 1 (unclamped)
   float e1, e2;    // expm1(-s d), exp(s f_next) (for the derivative)
 };
+
+// A wave-uniform float moved into a scalar register: its load is waited for
+// here, once, and not at its first use inside a loop, where the wait would
+// also cover every load the loop's prefetch has in flight.
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 
 // exp(x) from the hardware base-2 exponential
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
