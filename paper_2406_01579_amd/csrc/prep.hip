@@ -83,14 +83,15 @@ __device__ __forceinline__ int find_scene_by_block(const DevScene* sc, int ns, i
 // Out-of-range vertex indices never reach a memory access: such a tet is
 // dropped (and counted in the header when `invalid` is given).
 __device__ __forceinline__ bool keep_tet(const DevScene& S, int k, float tf, uint32_t* invalid, int4* vi_out) {
-  int4 vi = reinterpret_cast<const int4*>(S.tets)[k];
+  int4 vi = load_tet(S.tets, k);
   if (vi_out) *vi_out = vi;
   if ((unsigned)vi.x >= (unsigned)S.V || (unsigned)vi.y >= (unsigned)S.V || (unsigned)vi.z >= (unsigned)S.V ||
       (unsigned)vi.w >= (unsigned)S.V) {
     if (invalid) *invalid = 1u;
     return false;
   }
-  float f0 = S.sdf[vi.x], f1 = S.sdf[vi.y], f2 = S.sdf[vi.z], f3 = S.sdf[vi.w];
+  const auto* sdf = gmem(S.sdf);
+  float f0 = sdf[vi.x], f1 = sdf[vi.y], f2 = sdf[vi.z], f3 = sdf[vi.w];
   float fmax = fmaxf(fmaxf(f0, f1), fmaxf(f2, f3));
   float fmin = fminf(fminf(f0, f1), fminf(f2, f3));
   return alpha_eq1(fmax, fmin, S.s) >= tf;
@@ -252,7 +253,8 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
 #pragma unroll
   for (int q = 0; q < PF_PER_THREAD; ++q) {
     kp[q] = (nib >> q) & 1u;
-    vi[q] = kp[q] ? reinterpret_cast<const int4*>(S.tets)[k0 + q] : make_int4(0, 0, 0, 0);
+    vi[q] = make_int4(0, 0, 0, 0);
+    if (kp[q]) vi[q] = load_tet(S.tets, k0 + q);
     c += kp[q] ? 1u : 0u;
   }
   uint32_t tot;
@@ -265,10 +267,10 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
     const int idx[4] = {vi[q].x, vi[q].y, vi[q].z, vi[q].w};
     TetRec r;
     for (int a = 0; a < 4; ++a) {
-      r.x[a][0] = S.verts[3 * (size_t)idx[a] + 0];
-      r.x[a][1] = S.verts[3 * (size_t)idx[a] + 1];
-      r.x[a][2] = S.verts[3 * (size_t)idx[a] + 2];
-      r.f[a] = S.sdf[idx[a]];
+      r.x[a][0] = gmem(S.verts)[3 * (size_t)idx[a] + 0];
+      r.x[a][1] = gmem(S.verts)[3 * (size_t)idx[a] + 1];
+      r.x[a][2] = gmem(S.verts)[3 * (size_t)idx[a] + 2];
+      r.f[a] = gmem(S.sdf)[idx[a]];
     }
     // g = E^-1 (f_k - f_0), E rows e_k = x_k - x_0 (k = 1..3)
     float e[3][3], df[3];
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(PF_THREADS) void k_pf_scatter(void* ws, Layout L, f
     float gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     for (int j = 0; j < 3; ++j) r.n[j] = (gn > 0.0f) ? g[j] / gn : 0.0f;
     for (int j = 0; j < 3; ++j) {
-      const float* C = S.colors;
+      const auto* C = gmem(S.colors);
       r.c[j] = ((C[3 * (size_t)idx[0] + j] + C[3 * (size_t)idx[1] + j]) +
                 (C[3 * (size_t)idx[2] + j] + C[3 * (size_t)idx[3] + j])) * 0.25f;
     }

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite(void* ws, Layout L, float 
   if (c.inside) {
     const size_t plane = (size_t)V.W * V.H;
     const size_t px = (size_t)c.j * V.W + c.i;
-    float* out = V.out;
+    auto* out = gmem(V.out);
     out[0 * plane + px] = fmaf(T, V.bg[0], acc[0]);
     out[1 * plane + px] = fmaf(T, V.bg[1], acc[1]);
     out[2 * plane + px] = fmaf(T, V.bg[2], acc[2]);
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
   // upstream gradient
   float gr[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
+  for (int q = 0; q < 8; ++q) gr[q] = c.inside ? gmem(V.dout)[q * plane + px] : 0.0f;
   float Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
 
   // the tile is processed from its largest last-blended position down

@@ -144,7 +144,7 @@ __device__ __forceinline__ void background_tiles(void* ws, const Layout& L, cons
     if (i >= V.W || j >= V.H) continue;
     const size_t plane = (size_t)V.W * V.H;
     const size_t px = (size_t)j * V.W + i;
-    float* out = V.out;
+    auto* out = gmem(V.out);
     out[0 * plane + px] = V.bg[0];
     out[1 * plane + px] = V.bg[1];
     out[2 * plane + px] = V.bg[2];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(5, 8))
   if ((threadIdx.x >> 6) == 0 && c.inside) {
     const size_t plane = (size_t)V.W * V.H;
     const size_t px = (size_t)c.j * V.W + c.i;
-    float* out = V.out;
+    auto* out = gmem(V.out);
     out[0 * plane + px] = fmaf(T, V.bg[0], acc[0]);
     out[1 * plane + px] = fmaf(T, V.bg[1], acc[1]);
     out[2 * plane + px] = fmaf(T, V.bg[2], acc[2]);
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   float Rbehind = 0.0f;
   if (wave == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
+    for (int q = 0; q < 8; ++q) gr[q] = c.inside ? gmem(V.dout)[q * plane + px] : 0.0f;
     Rbehind = gr[0] * V.bg[0] + gr[1] * V.bg[1] + gr[2] * V.bg[2];
   }
   // where this tile's pairs go
@@ -481,7 +481,7 @@ __device__ __forceinline__ void pair_row(const PairIn& q, const DevView* __restr
   reinterpret_cast<float4*>(&R)[2] = src[2];
   reinterpret_cast<float4*>(&R)[3] = src[3];
   const DevView& V = vw[q.b.y];
-  const float* dout = V.dout;
+  const auto* dout = gmem(V.dout);
   const int W = V.W, H = V.H;
   const int pix = (int)(q.a.w & 63u);
   const int i = (int)(q.b.z & 0xffffu) * 8 + (pix & 7), j = (int)(q.b.z >> 16) * 8 + (pix >> 3);

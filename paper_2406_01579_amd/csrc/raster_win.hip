@@ -265,7 +265,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_win(void* ws, Layout L, 
     if (c.inside) {
       const size_t plane = (size_t)V.W * V.H;
       const size_t px = (size_t)c.j * V.W + c.i;
-      float* out = V.out;
+      auto* out = gmem(V.out);
       out[0 * plane + px] = fmaf(T, V.bg[0], acc[0]);
       out[1 * plane + px] = fmaf(T, V.bg[1], acc[1]);
       out[2 * plane + px] = fmaf(T, V.bg[2], acc[2]);
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   const size_t px = c.inside ? (size_t)c.j * V.W + c.i : 0;
   float gr[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) gr[q] = c.inside ? V.dout[q * plane + px] : 0.0f;
+  for (int q = 0; q < 8; ++q) gr[q] = c.inside ? gmem(V.dout)[q * plane + px] : 0.0f;
 
   // ---- sweep 1 (window and blend records in wave 0)
   float T = 1.0f;

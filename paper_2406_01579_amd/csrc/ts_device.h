@@ -69,6 +69,27 @@ struct PixEval {
   float e1, e2;    // expm1(-s d), exp(s f_next) (for the derivative)
 };
 
+// Image planes and scene arrays are reached through pointers read from a
+// descriptor, which the compiler treats as generic (flat) addresses.  A flat load also
+// counts against the LDS wait counter, so every LDS wait after it waits for
+// the load too; through a global-space pointer it does not.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// A tet's four vertex ids through a global-space pointer.
+__device__ __forceinline__ int4 load_tet(const int32_t* tets, size_t k) {
+  const auto* t = gmem(tets) + 4 * k;
+  return make_int4(t[0], t[1], t[2], t[3]);
+}
+
+// Float atomic add to device memory through a global-space pointer (for a
+// pointer read from a descriptor; see gmem).
+__device__ __forceinline__ void gatomic_add(float* p, float v) {
+  __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // A wave-uniform float moved into a scalar register: its load is waited for
 // here, once, and not at its first use inside a loop, where the wait would
 // also cover every load the loop's prefetch has in flight.

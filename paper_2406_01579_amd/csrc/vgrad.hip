@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
       }
     }
-    const int4 vi = reinterpret_cast<const int4*>(S.tets)[T.tet];
+    const int4 vi = load_tet(S.tets, T.tet);
     const int idx[4] = {vi.x, vi.y, vi.z, vi.w};
     if constexpr (DET) {
       // the four corners' terms and sort keys (corner id 4 k + a is the
@@ -286,10 +286,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       }
       if (!put) {
         for (int m = 0; m < 3; ++m) {
-          if (val[m] != 0.0f) unsafeAtomicAdd(&S.dverts[3 * (size_t)vv + m], val[m]);
-          if (val[4 + m] != 0.0f) unsafeAtomicAdd(&S.dcolors[3 * (size_t)vv + m], val[4 + m]);
+          if (val[m] != 0.0f) gatomic_add(&S.dverts[3 * (size_t)vv + m], val[m]);
+          if (val[4 + m] != 0.0f) gatomic_add(&S.dcolors[3 * (size_t)vv + m], val[4 + m]);
         }
-        if (val[3] != 0.0f) unsafeAtomicAdd(&S.dsdf[vv], val[3]);
+        if (val[3] != 0.0f) gatomic_add(&S.dsdf[vv], val[3]);
       }
     }
     }
@@ -302,10 +302,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         if (key == 0u) continue;
         const size_t vv = (size_t)(key - 1u);
         for (int m = 0; m < 3; ++m) {
-          if (hval[m][h] != 0.0f) unsafeAtomicAdd(&S.dverts[3 * vv + m], hval[m][h]);
-          if (hval[4 + m][h] != 0.0f) unsafeAtomicAdd(&S.dcolors[3 * vv + m], hval[4 + m][h]);
+          if (hval[m][h] != 0.0f) gatomic_add(&S.dverts[3 * vv + m], hval[m][h]);
+          if (hval[4 + m][h] != 0.0f) gatomic_add(&S.dcolors[3 * vv + m], hval[4 + m][h]);
         }
-        if (hval[3][h] != 0.0f) unsafeAtomicAdd(&S.dsdf[vv], hval[3][h]);
+        if (hval[3][h] != 0.0f) gatomic_add(&S.dsdf[vv], hval[3][h]);
       }
     }
     __syncthreads();
