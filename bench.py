@@ -52,17 +52,17 @@ TET_GRAD_RW_B = 2 * 92
 # waves per CU).  Valid only for the kernel sources with these digests;
 # reported as null once they change.
 MEASURED = {"sha256": {"paper_2406_01579_amd/csrc/raster_mw.hip":
-                       "ee403a76507ed4c155f2fce7c09853c8b56a3e44748afd12c291301fe78c7db0",
+                       "4489e318cb83a81c7cbb312a5f6ad87db0fbb2694c5c192eb31f15a5579f8021",
                        "paper_2406_01579_amd/csrc/ts_device.h":
-                       "09c6d7e0d2fc2409b55062cfe388862a397babd32b4eb7b877609b5b170e8442",
+                       "1d460977169d1c084a1b36e572048bb91e1e0af4ea703fbdbf89cf80f8df331e",
                        "paper_2406_01579_amd/csrc/tile8.h":
-                       "03f51eef33d998dfbad73d765e26865a7f91fd9c3b1bec7d68dccaf513e91670",
+                       "83bb8bebe55172092063087a21a2361760b74440877a48bfc046755a7f0cd36b",
                        "paper_2406_01579_amd/csrc/ts_internal.h":
-                       "f504bf2368d21b9e7e75844193b93a63cc4fba9c2d61d2ec03b1ee951d45d781"},
-            "composite_bwd": {"traffic": 261.3e6, "valu_issue_frac": 0.41, "lds_util": 0.1644,
-                              "lds_active_bytes": 1.2541e9, "lds_bank_conflict_frac": 0.318, "occupancy_pct": 37.1},
-            "composite": {"traffic": 124.9e6, "valu_issue_frac": 0.577, "lds_util": 0.2294,
-                          "lds_active_bytes": 1.1086e9, "lds_bank_conflict_frac": 0.443, "occupancy_pct": 38.9}}
+                       "aebba5bd1e11dd09db825e3d8078375d3197ad6cf68afbdc4296cc448b32e16b"},
+            "composite_bwd": {"traffic": 261.4e6, "valu_issue_frac": 0.44, "lds_util": 0.1589,
+                              "lds_active_bytes": 1.1937e9, "lds_bank_conflict_frac": 0.275, "occupancy_pct": 37.4},
+            "composite": {"traffic": 125.4e6, "valu_issue_frac": 0.656, "lds_util": 0.1853,
+                          "lds_active_bytes": 0.8162e9, "lds_bank_conflict_frac": 0.367, "occupancy_pct": 39.9}}
 
 
 def measured_counters(kernel, args):
