@@ -395,19 +395,19 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
     __syncthreads();
     if (done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHB, end - base);
-    rp.store(recs, n);
+    rp.store(recs, n, erec);
     rp.fetch_rec(vrec, rbox);
     rp.fetch_idx(srec, base + 2 * CHB, end - 1);
     __syncthreads();
     load_chunk_tables(recs, n, feat, hm, NT);
     if (threadIdx.x < (unsigned)n) {
-      // the entry's record and gradient slot; its blend mask starts empty
+      // the entry's gradient slot (its record came with the chunk's records);
+      // its blend mask starts empty
       const ViewRec& R = recs[threadIdx.x];
       int i0, i1, j0, j1;
       unpack_rect(R, i0, i1, j0, j1);
       const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
       const uint32_t d = R.entry0 + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
-      erec[threadIdx.x] = srec[base + threadIdx.x];
       eslot[threadIdx.x] = d;
       if ((uint64_t)d < cap) emask[d] = 0ull;
     }
