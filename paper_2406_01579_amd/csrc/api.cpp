@@ -223,6 +223,7 @@ bool plan_layout(const render_scene* scenes, int ns, const render_view* views, i
   L.o_trec = take(sizeof(TetRec) * (size_t)kept_cap);
   L.o_vrec = take(sizeof(ViewRec) * (size_t)rec_cap);
   L.o_rbox = take(16 * (size_t)rec_cap);
+  L.o_rfirst = take(4 * (size_t)rec_cap);
   L.o_count1 = take(4 * (size_t)rec_cap);
   L.o_key1a = take(4 * (size_t)rec_cap);
   L.o_scan_part = take(4 * (size_t)(L.scan_blocks_rec + 1));

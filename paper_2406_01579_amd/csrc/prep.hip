@@ -716,7 +716,8 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
   const DevHeader* hdr = at<const DevHeader>(ws, L.o_hdr);
   const DevView* vw = at<const DevView>(ws, L.o_view);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
-  uint4* rbox = at<uint4>(ws, L.o_rbox);
+  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
+  uint32_t* rfirst = at<uint32_t>(ws, L.o_rfirst);
   uint32_t* cursor = at<uint32_t>(ws, L.o_tile_cnt);
   uint32_t* val2 = at<uint32_t>(ws, sorted_entry_records(L));
   constexpr int PER = SCAN_PER;
@@ -735,7 +736,7 @@ __global__ __launch_bounds__(256) void k_emit(void* ws, Layout L, int tw_log2, i
     const uint32_t base = part[blk];
 #pragma unroll
     for (int i = 0; i < PER; ++i)
-      if (c[i] != 0u) rbox[q0 + (uint32_t)(t * PER + i)].w = base + loff[t * PER + i];
+      if (c[i] != 0u) rfirst[q0 + (uint32_t)(t * PER + i)] = base + loff[t * PER + i];
     for (uint32_t e0 = 0; e0 < tot; e0 += 256u) {
       const uint32_t e = e0 + (uint32_t)t;
       const bool active = e < tot;

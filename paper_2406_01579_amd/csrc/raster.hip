@@ -55,16 +55,16 @@ __device__ __forceinline__ TileCtx tile_ctx(const DevView* vw, const TileSlot* s
 }
 
 // The records of sorted entries [base, base + n) into LDS, eight threads per
-// 128-byte record.  With rbox, the copy's first-entry field comes from the
-// record's compact box, where the emit kernel writes it.
+// 128-byte record.  With rfirst, the copy's first-entry field comes from the
+// records' first entries, where the placement kernel writes them.
 __device__ __forceinline__ void load_chunk(ViewRec* recs, const ViewRec* __restrict__ vrec,
                                            const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads,
-                                           const uint4* __restrict__ rbox = nullptr) {
+                                           const uint32_t* __restrict__ rfirst = nullptr) {
   for (int q = threadIdx.x; q < n * 8; q += nthreads) {
     const int e = q >> 3, part = q & 7;
     const uint32_t r = srec[base + e];
     float4 t = reinterpret_cast<const float4*>(&vrec[r])[part];
-    if (rbox && part == 7) t.w = __uint_as_float(rbox[r].w);   // entry0 is the last word of the record
+    if (rfirst && part == 7) t.w = __uint_as_float(rfirst[r]);   // entry0 is the last word of the record
     reinterpret_cast<float4*>(&recs[e])[part] = t;
   }
 }
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(void* ws, Layout L, fl
        cb >= (int64_t)start && pend > start; cb -= CH) {
     const uint32_t base = (uint32_t)cb;
     const int n = (int)min((uint32_t)CH, pend - base);
-    load_chunk(recs, vrec, srec, base, n, NT, at<const uint4>(ws, L.o_rbox));
+    load_chunk(recs, vrec, srec, base, n, NT, at<const uint32_t>(ws, L.o_rfirst));
     if (WSLOT)
       for (int q = threadIdx.x; q < NW * CH * TGRAD_STRIDE; q += NT) (&gaccw[0][0][0])[q] = 0.0f;
     else if (NW > 1)

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   float Tnext = 1.0f;
   // chunks from the one holding pend - 1 down to start; only the first is partial
   const int64_t cb0 = (int64_t)start + (((int64_t)pend - 1 - (int64_t)start) / CHB) * CHB;
-  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
+  const uint32_t* rfirst = at<const uint32_t>(ws, L.o_rfirst);
   RecPipe<CHB, NT, true> rp;
   // wave 0, lane e: the blend mask of the current chunk's entry e, and of the
   // next chunk's (its load in flight across the current chunk)
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
   const auto below = [&](int64_t b) { return b >= (int64_t)start ? (uint32_t)b : pend - 1u; };
   if (pend > start) {
     rp.fetch_idx(srec, (uint32_t)cb0, pend - 1u);
-    rp.fetch_rec(vrec, rbox);
+    rp.fetch_rec(vrec, rfirst);
     rp.fetch_idx(srec, below(cb0 - CHB), pend - 1u);
     if (wave == 0 && lane < pend - (uint32_t)cb0 && lane < (unsigned)CHB) bm_next = bmask[(uint32_t)cb0 + lane];
   }
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_mw(void* ws, Layout 
     bm_cur = bm_next;
     if (wave == 0 && cb - CHB >= (int64_t)start && lane < (unsigned)CHB) bm_next = bmask[base - CHB + lane];
     rp.store(recs, n, ridx);
-    rp.fetch_rec(vrec, rbox);
+    rp.fetch_rec(vrec, rfirst);
     rp.fetch_idx(srec, below(cb - 2 * CHB), pend - 1u);
     __syncthreads();
     // phase A: coverage, faces and Eq. 1 of every (entry, pixel) pair the

@@ -308,6 +308,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   const uint32_t* srec = at<const uint32_t>(ws, sorted_entry_records(L));
   const ViewRec* vrec = at<const ViewRec>(ws, L.o_vrec);
   const uint4* rbox = at<const uint4>(ws, L.o_rbox);
+  const uint32_t* rfirst = at<const uint32_t>(ws, L.o_rfirst);
   uint4* blends = at<uint4>(ws, L.o_wblend);
   unsigned long long* emask = at<unsigned long long>(ws, L.o_wmask);
   uint32_t* ebase = at<uint32_t>(ws, L.o_wbase);
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
   RecPipe<CHB, NT, true> rp;
   if (start < end) {
     rp.fetch_idx(srec, start, end - 1);
-    rp.fetch_rec(vrec, rbox);
+    rp.fetch_rec(vrec, rfirst);
     rp.fetch_idx(srec, start + CHB, end - 1);
   }
   for (uint32_t base = start; base < end; base += CHB) {
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
     if (done_mask == ~0ull) break;
     const int n = (int)min((uint32_t)CHB, end - base);
     rp.store(recs, n, erec);
-    rp.fetch_rec(vrec, rbox);
+    rp.fetch_rec(vrec, rfirst);
     rp.fetch_idx(srec, base + 2 * CHB, end - 1);
     __syncthreads();
     load_chunk_tables(recs, n, feat, hm, NT);
@@ -478,11 +479,12 @@ __global__ __launch_bounds__(64 * NWV) void k_composite_bwd_win(void* ws, Layout
     const uint32_t idx = b0 + threadIdx.x;
     uint32_t d = 0u, cnt = 0u;
     if (idx < end) {
-      const uint4 bx = rbox[srec[idx]];   // pixel rectangle, view, first entry
+      const uint32_t r = srec[idx];
+      const uint4 bx = rbox[r];   // pixel rectangle, view
       const int i0 = (int)(bx.x & 0xffffu), i1 = (int)(bx.x >> 16), j0 = (int)(bx.y & 0xffffu),
                 j1 = (int)(bx.y >> 16);
       const int tx0 = i0 >> 3, ty0 = j0 >> 3, nx = (i1 >> 3) - tx0 + 1;
-      d = bx.w + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
+      d = rfirst[r] + (uint32_t)((c.ty - ty0) * nx + (c.tx - tx0));
       (void)j1;
       cnt = (uint64_t)d < cap ? (uint32_t)__popcll(mask_load(emask + d)) : 0u;
     }

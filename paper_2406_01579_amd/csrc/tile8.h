@@ -10,16 +10,16 @@ namespace ts {
 namespace {
 
 // The records of sorted entries [base, base + n) into LDS, eight threads per
-// 128-byte record.  With rbox, the copy's first-entry field comes from the
-// record's compact box, where the emit kernel writes it.
+// 128-byte record.  With rfirst, the copy's first-entry field comes from the
+// records' first entries, where the placement kernel writes them.
 __device__ __forceinline__ void load_recs(ViewRec* recs, const ViewRec* __restrict__ vrec,
                                           const uint32_t* __restrict__ srec, uint32_t base, int n, int nthreads,
-                                          const uint4* __restrict__ rbox = nullptr) {
+                                          const uint32_t* __restrict__ rfirst = nullptr) {
   for (int q = threadIdx.x; q < n * 8; q += nthreads) {
     const int e = q >> 3, part = q & 7;
     const uint32_t r = srec[base + e];
     float4 t = reinterpret_cast<const float4*>(&vrec[r])[part];
-    if (rbox && part == 7) t.w = __uint_as_float(rbox[r].w);   // entry0 is the last word of the record
+    if (rfirst && part == 7) t.w = __uint_as_float(rfirst[r]);   // entry0 is the last word of the record
     reinterpret_cast<float4*>(&recs[e])[part] = t;
   }
 }
@@ -228,7 +228,7 @@ __device__ __forceinline__ void for_each_pair(const PairMap<CH>& M, int nthreads
 // one after it are in flight too, so a chunk's two dependent global loads
 // overlap the previous chunk's work.  Each thread owns PQ of the chunk's
 // 16-byte record parts.  With E0, the copy's first-entry field comes from
-// the record's compact box (loaded beside the last part).
+// the records' first entries (loaded beside the last part).
 template <int CH, int NT, bool E0 = false>
 struct RecPipe {
   static constexpr int PQ = (CH * 8 + NT - 1) / NT;
@@ -249,7 +249,7 @@ struct RecPipe {
   }
   // every part (one past the chunk reads a record of the list, never stored)
   __device__ __forceinline__ void fetch_rec(const ViewRec* __restrict__ vrec,
-                                            const uint4* __restrict__ rbox = nullptr) {
+                                            const uint32_t* __restrict__ rfirst = nullptr) {
 #pragma unroll
     for (int j = 0; j < PQ; ++j) {
       const int q = (int)threadIdx.x + j * NT;
@@ -259,7 +259,7 @@ struct RecPipe {
       vy[j] = t.y;
       vz[j] = t.z;
       vw[j] = t.w;
-      if (E0 && (q & 7) == 7) vw[j] = __uint_as_float(rbox[idx[j]].w);   // entry0: the record's last word
+      if (E0 && (q & 7) == 7) vw[j] = __uint_as_float(rfirst[idx[j]]);   // entry0: the record's last word
     }
   }
   // With ridx, also each record's index (what a chunk needs of srec later

@@ -82,8 +82,8 @@ struct TetRec {
 static_assert(sizeof(TetRec) == 96, "tet record is 96 bytes");
 
 // Per (view, kept tet) record read by the compositing kernels (128 B, one
-// cache line): projected vertices, inverse camera depths, SDF, 2D face
-// determinants, shading features, pixel rectangle.
+// cache line): projected vertices, inverse camera depths, SDF, reciprocal 2D
+// face determinants, shading features, pixel rectangle.
 struct ViewRec {
   float px[4], py[4];
   float iz[4];      // 1 / Z_k
@@ -97,7 +97,7 @@ struct ViewRec {
   uint32_t ry;      // j0 | j1 << 16
   int32_t kept;     // global kept slot
   int32_t view;
-  uint32_t entry0;  // first tile-duplicated entry: filled into LDS copies from the compact box
+  uint32_t entry0;  // first tile-duplicated entry: filled into LDS copies from the records' first entries
 };
 static_assert(sizeof(ViewRec) == 128, "view record is 128 bytes");
 
@@ -134,7 +134,8 @@ struct Layout {
   size_t o_pf_cnt, o_kept_tet, o_trec;
   size_t o_pf_keep;   // pre-filter decisions, one bit per tet (PF_TILE / 32 words per block)
   size_t o_vrec, o_count1, o_key1a, o_scan_part;   // key1a: depth float bits per record
-  size_t o_rbox;   // per record: pixel rectangle (rx, ry), view, first entry (16 B)
+  size_t o_rbox;   // per record: pixel rectangle (rx, ry), view (16 B; the last word unused)
+  size_t o_rfirst; // per record: its first entry (4 B, dense: the placement kernel's writes coalesce)
   size_t o_hist;
   size_t o_key2a, o_key2b, o_val2a, o_val2b, o_eflag;
   size_t o_ranges, o_tile_hist, o_tile_order, o_tgrad, o_last, o_tlast;

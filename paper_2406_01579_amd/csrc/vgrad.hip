@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int32_t* scene_views = at<const int32_t>(ws, L.o_scene_views);
   const int32_t* kbase = at<const int32_t>(ws, L.o_scene_kept_base);
   const int32_t* rbase = at<const int32_t>(ws, L.o_view_rec_base);
-  const uint4* rbox = at<const uint4>(ws, L.o_rbox);
+  const uint32_t* rfirst = at<const uint32_t>(ws, L.o_rfirst);
   const TetRec* trec = at<const TetRec>(ws, L.o_trec);
   const uint32_t* count1 = at<const uint32_t>(ws, L.o_count1);
   const uint8_t* eflag = at<const uint8_t>(ws, L.o_eflag);
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
           for (int z = 0; z < 23; ++z) hit = hit || g[z] != 0.0f;
         } else {
-        const uint32_t o = rbox[r].w;   // the record's first entry
+        const uint32_t o = rfirst[r];   // the record's first entry
         const uint32_t n = (uint32_t)min((uint64_t)cnt, cap > o ? cap - o : 0ull);
         if (n == 0u) continue;  // entries past the capacity (an overflowed forward)
         // reached flags, bit j for entry o + j: the first eight from two
